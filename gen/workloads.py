@@ -1,0 +1,137 @@
+"""Seeded synthetic tactile-indentation workloads.
+
+Each builder returns a :class:`Workload`: a slave (tactile pad) surface, a
+master (indenter) surface, the contact parameters, and a per-vertex search
+direction for the step bound.  Positions are generated in float64; with
+``fp32=True`` they are rounded to float32 (and kept as float64 arrays), so
+the FP64 oracle and the float32 GPU path see the very same coordinates.
+
+Only geometry and random numbers live here; no part of the contact method.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import meshes
+
+
+@dataclass
+class Workload:
+    name: str
+    xs: np.ndarray           # slave positions [Vs, 3]
+    ts: np.ndarray           # slave triangles [Ts, 3] int32
+    xm: np.ndarray           # master positions [Vm, 3]
+    tm: np.ndarray           # master triangles [Tm, 3] int32
+    rule_n: int              # n x n samples per slave triangle
+    kappa: float
+    dhat: float
+    delta_T: float
+    dxs: np.ndarray          # search direction, slave [Vs, 3]
+    dxm: np.ndarray          # search direction, master [Vm, 3]
+    xs_rest: np.ndarray = field(default=None)
+    info: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.xs_rest is None:
+            self.xs_rest = self.xs
+
+    @property
+    def n_samples(self):
+        return self.ts.shape[0] * self.rule_n * self.rule_n
+
+
+def _r32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _finish(w: Workload, fp32: bool) -> Workload:
+    if fp32:
+        for k in ("xs", "xm", "dxs", "dxm", "xs_rest"):
+            setattr(w, k, _r32(getattr(w, k)))
+    return w
+
+
+def small_indent(seed: int = 1, fp32: bool = True, delta_T: float = 0.0) -> Workload:
+    """Plain GMCP case: 16x16 flat pad (512 tris, 10x10 mm), 2x2 samples per
+    triangle (2048), icosphere subdivision 3 (642 V / 1280 T, R = 5 mm) with a
+    random rotation and a +-0.5 mm lateral offset, lowest vertex 10 um above
+    the pad, so sample gaps spread over [10 um, dhat].  dhat = 1 mm,
+    kappa = 1e5.  Search direction: every vertex of both meshes moves by a
+    vector uniform in a 0.5 mm ball (seed 11)."""
+    rng = np.random.default_rng(seed)
+    xs, ts = meshes.pad(16, 1e-2)
+    xm, tm = meshes.icosphere(3, 5e-3)
+    xm = xm @ meshes.random_rotation(rng).T
+    off = rng.uniform(-0.5e-3, 0.5e-3, size=2)
+    xm[:, 0] += off[0]
+    xm[:, 1] += off[1]
+    xm = meshes.place_above(xm, xs, 10e-6)
+    r2 = np.random.default_rng(11)
+    dxs = meshes.ball_uniform(r2, xs.shape[0], 0.5e-3)
+    dxm = meshes.ball_uniform(r2, xm.shape[0], 0.5e-3)
+    w = Workload("small_indent_16x16_ico3", xs, ts, xm, tm, 2, 1e5, 1e-3, delta_T, dxs, dxm)
+    return _finish(w, fp32)
+
+
+def large_indent(seed: int = 2, fp32: bool = True, indenter: str = "sphere",
+                 g_min: float = 10e-6, pad_n: int = 128, rule_n: int = 4) -> Workload:
+    """Single large indentation: 128x128 gel pad (32768 tris, 10x10 mm) with
+    +-50 um vertex z-noise, 4x4 = 16 samples per triangle (524288 samples),
+    pressed by a ~40k-triangle indenter placed g_min above the pad:
+      sphere: geodesic sphere, frequency 45 (40500 T), R = 5 mm, three radial
+              bumps of up to 2 % R and +-10 um vertex noise;
+      letter: extruded 5x7-cell block letter, 4 mm deep, tilted <= 2 deg.
+    Search direction: indenter rigid motion of 0.2 mm down plus a 0.2 deg
+    rotation about a random horizontal axis; pad vertices uniform in a
+    20 um ball."""
+    rng = np.random.default_rng(seed)
+    xs, ts = meshes.pad(pad_n, 1e-2, noise=50e-6, rng=rng)
+    if indenter == "sphere":
+        xm, tm = meshes.geodesic_sphere(45, 5e-3)
+        xm = meshes.perturb_radial(xm, np.zeros(3), rng, n_bumps=3, amp=0.02)
+        xm = xm + rng.uniform(-10e-6, 10e-6, size=xm.shape)
+        center = np.zeros(3)
+    elif indenter == "letter":
+        xm, tm = meshes.letter(cell=1e-3, depth=4e-3, refine=10)
+        tilt_axis = np.array([rng.normal(), rng.normal(), 0.0])
+        xm = xm @ meshes.axis_angle(tilt_axis, np.deg2rad(rng.uniform(0, 2))).T
+        center = xm.mean(axis=0)
+    else:
+        raise ValueError(indenter)
+    xm = meshes.place_above(xm, xs, g_min)
+    center = center + (xm.mean(axis=0) - center) if indenter == "letter" else np.array(
+        [0.0, 0.0, xm[:, 2].min() + 5e-3])
+    ang = np.deg2rad(0.2)
+    h = rng.normal(size=2)
+    R = meshes.axis_angle([h[0], h[1], 0.0], ang)
+    dxm = (xm - center) @ R.T + center - xm
+    dxm[:, 2] -= 0.2e-3
+    dxs = meshes.ball_uniform(rng, xs.shape[0], 20e-6)
+    w = Workload(f"large_indent_{pad_n}x{pad_n}_{indenter}", xs, ts, xm, tm, rule_n, 1e5, 1e-3, 0.0,
+                 dxs, dxm, info={"g_min": g_min})
+    return _finish(w, fp32)
+
+
+def flat_punch(n_pad: int = 8, n_punch: int = 5, gap: float = 3e-4, length: float = 1e-2,
+               punch_length: float = 1.4e-2, rule_n: int = 2, fp32: bool = False) -> Workload:
+    """A flat rectangular master, meshed independently of the pad (its grid
+    does not match the pad's), parallel to a flat pad at a uniform gap.  The
+    punch is larger than the pad so it covers every sample.  Normals: pad +z,
+    punch -z (flipped triangle order)."""
+    xs, ts = meshes.pad(n_pad, length)
+    xm, tm = meshes.pad(n_punch, punch_length)
+    tm = tm[:, [0, 2, 1]].copy()
+    xm[:, 0] += 0.13 * punch_length / n_punch      # shift so the grids do not line up
+    xm[:, 1] += 0.07 * punch_length / n_punch
+    xm[:, 2] = gap
+    z = np.zeros_like(xs)
+    w = Workload("flat_punch", xs, ts, xm, tm, rule_n, 1e5, 1e-3, 0.0, z, np.zeros_like(xm))
+    return _finish(w, fp32)
+
+
+def to_problem(w: Workload):
+    """Oracle problem built from a workload (for tests and the CPU baseline)."""
+    from oracle import Problem
+    return Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, None, w.xs_rest)
