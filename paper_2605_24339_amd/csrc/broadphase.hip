@@ -1,0 +1,461 @@
+// Broad phase: per-environment uniform grid over the master triangles,
+// queried with the support prism of every slave triangle.
+//
+// Grid domain of an environment: the slave surface's box grown by eps_max
+// (a master triangle outside it cannot be reached by any sample's support
+// segment).  Cells are numbered x-fastest inside the environment's slice of
+// the cell array.  Every master triangle is counted into each cell its box
+// touches (atomic counts), the counts are scanned into cell starts, and a
+// second pass places the triangle ids (the counters return to zero, ready
+// for the next call).  A (prism, triangle) pair is reported only from the
+// cell that holds the low corner of the two boxes' intersection, so each
+// candidate appears once; each slave triangle's list is then sorted, which
+// makes the candidate lists deterministic.
+#include "common.h"
+
+namespace gmcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename R>
+__device__ inline void load3(const R *x, int64_t v, float o[3]) {
+  o[0] = (float)x[3 * v];
+  o[1] = (float)x[3 * v + 1];
+  o[2] = (float)x[3 * v + 2];
+}
+
+// outward rounding margin for float boxes of (possibly double) coordinates
+__device__ inline float grow(float v) { return fabsf(v) * 4e-7f + 1e-30f; }
+
+__global__ void k_box_init(uint32_t *box, int n_env) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_env) return;
+  for (int d = 0; d < 3; ++d) {
+    box[6 * e + d] = 0xffffffffu;    // min: largest ordered value
+    box[6 * e + 3 + d] = 0u;         // max: smallest ordered value
+  }
+}
+
+// slave surface box per environment (swept: union of x and x + dx)
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
+                                                         const int32_t *__restrict__ ts,
+                                                         const int32_t *__restrict__ s_env, int64_t Ts,
+                                                         uint32_t *box) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lane = threadIdx.x & (kWave - 1);
+  bool ok = t < Ts;
+  int env = ok ? s_env[t] : -1;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (ok) {
+    for (int j = 0; j < 3; ++j) {
+      int v = ts[3 * t + j];
+      float p[3];
+      load3(xs, v, p);
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fminf(lo[d], p[d] - grow(p[d]));
+        hi[d] = fmaxf(hi[d], p[d] + grow(p[d]));
+      }
+      if (dxs) {
+        for (int d = 0; d < 3; ++d) {
+          float q = (float)(xs[3 * (int64_t)v + d] + dxs[3 * (int64_t)v + d]);
+          lo[d] = fminf(lo[d], q - grow(q));
+          hi[d] = fmaxf(hi[d], q + grow(q));
+        }
+      }
+    }
+  }
+  // environments are contiguous in triangle order: most waves hold one
+  uint64_t vm = __ballot(ok);
+  if (!vm) return;
+  int e0 = __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave);
+  bool uniform = __all(!ok || env == e0);
+  if (uniform) {
+    for (int d = 0; d < 3; ++d) {
+      float a = lo[d], b = hi[d];
+      for (int o = 32; o > 0; o >>= 1) {
+        a = fminf(a, __shfl_xor(a, o, kWave));
+        b = fmaxf(b, __shfl_xor(b, o, kWave));
+      }
+      lo[d] = a;
+      hi[d] = b;
+    }
+    if (lane == 0) {
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&box[6 * e0 + d], float_to_ordered(lo[d]));
+        atomicMax(&box[6 * e0 + 3 + d], float_to_ordered(hi[d]));
+      }
+    }
+  } else if (ok) {
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&box[6 * env + d], float_to_ordered(lo[d]));
+      atomicMax(&box[6 * env + 3 + d], float_to_ordered(hi[d]));
+    }
+  }
+}
+
+// grid geometry per environment: domain = box grown by `pad`, cell size
+// from the caller (cell > 0) or max(eps_max / 4, cbrt(volume / budget)),
+// enlarged until the cell count fits the environment's budget
+__global__ void k_grid_setup(const EnvInfo *__restrict__ env, const uint32_t *__restrict__ box, GridEnv *grid,
+                             int n_env, int swept) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_env) return;
+  const EnvInfo &v = env[e];
+  GridEnv g;
+  float lo[3], hi[3];
+  bool empty = false;
+  float pad = swept ? 0.0f : (float)v.dhat * 1.0001f;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = ordered_to_float(box[6 * e + d]);
+    hi[d] = ordered_to_float(box[6 * e + 3 + d]);
+    if (!(lo[d] <= hi[d])) empty = true;
+    lo[d] -= pad;
+    hi[d] += pad;
+  }
+  if (empty || v.cell_budget <= 0 || v.st1 == v.st0) {
+    g.valid = 0;
+    g.nx = g.ny = g.nz = 1;
+    g.h = 1.0f;
+    g.inv_h = 1.0f;
+    for (int d = 0; d < 3; ++d) g.lo[d] = 0.0f;
+    grid[e] = g;
+    return;
+  }
+  double ext[3] = {hi[0] - (double)lo[0], hi[1] - (double)lo[1], hi[2] - (double)lo[2]};
+  double span = fmax(ext[0], fmax(ext[1], ext[2]));
+  double vol = fmax(ext[0], span * 1e-3) * fmax(ext[1], span * 1e-3) * fmax(ext[2], span * 1e-3);
+  double h = v.cell > 0.0 ? v.cell : fmax(v.dhat * 0.25, cbrt(vol / (double)v.cell_budget));
+  if (!(h > span * 1e-6)) h = span * 1e-6 + 1e-30;
+  int64_t n[3], tot = 1;
+  for (int it = 0; it < 200; ++it) {
+    tot = 1;
+    for (int d = 0; d < 3; ++d) {
+      n[d] = (int64_t)(ext[d] / h) + 1;
+      tot *= n[d];
+    }
+    if (tot <= v.cell_budget) break;
+    h *= 1.05 * cbrt((double)tot / (double)v.cell_budget);
+  }
+  g.valid = tot <= v.cell_budget && n[0] < (1 << 30) && n[1] < (1 << 30) && n[2] < (1 << 30);
+  g.h = (float)h;
+  g.inv_h = (float)(1.0 / h);
+  g.nx = (int)n[0];
+  g.ny = (int)n[1];
+  g.nz = (int)n[2];
+  for (int d = 0; d < 3; ++d) g.lo[d] = lo[d];
+  grid[e] = g;
+}
+
+__device__ inline int cell_coord(const GridEnv &g, float x, int d) {
+  float f = (x - g.lo[d]) * g.inv_h;
+  int n = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+  int c = (int)floorf(f);
+  return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+__device__ inline bool box_hits_grid(const GridEnv &g, const float lo[3], const float hi[3]) {
+  float ext[3] = {g.nx * g.h, g.ny * g.h, g.nz * g.h};
+  for (int d = 0; d < 3; ++d)
+    if (hi[d] < g.lo[d] || lo[d] > g.lo[d] + ext[d]) return false;
+  return true;
+}
+
+// master triangle boxes (and unit normals): static or swept over dx
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_master_boxes(const R *__restrict__ xm, const R *__restrict__ dxm,
+                                                            const int32_t *__restrict__ tm, int64_t Tm,
+                                                            float4 *__restrict__ mbox) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Tm) return;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  R p[3][3];
+  for (int j = 0; j < 3; ++j) {
+    int64_t v = tm[3 * t + j];
+    for (int d = 0; d < 3; ++d) {
+      p[j][d] = xm[3 * v + d];
+      float f = (float)p[j][d];
+      lo[d] = fminf(lo[d], f - grow(f));
+      hi[d] = fmaxf(hi[d], f + grow(f));
+      if (dxm) {
+        float q = (float)(p[j][d] + dxm[3 * v + d]);
+        lo[d] = fminf(lo[d], q - grow(q));
+        hi[d] = fmaxf(hi[d], q + grow(q));
+      }
+    }
+  }
+  R f1[3], f2[3];
+  for (int d = 0; d < 3; ++d) {
+    f1[d] = p[1][d] - p[0][d];
+    f2[d] = p[2][d] - p[0][d];
+  }
+  R N[3] = {f1[1] * f2[2] - f1[2] * f2[1], f1[2] * f2[0] - f1[0] * f2[2], f1[0] * f2[1] - f1[1] * f2[0]};
+  R len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+  R inv = len > R(0) ? R(1) / len : R(0);
+  mbox[3 * t + 0] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+  mbox[3 * t + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+  mbox[3 * t + 2] = make_float4((float)(N[0] * inv), (float)(N[1] * inv), (float)(N[2] * inv), 0.0f);
+}
+
+// pass 0: count incidences; pass 1: place ids (counters return to zero)
+__global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restrict__ mbox,
+                                                           const int32_t *__restrict__ m_env,
+                                                           const EnvInfo *__restrict__ env,
+                                                           const GridEnv *__restrict__ grid, int64_t Tm,
+                                                           int32_t *__restrict__ cell_cnt,
+                                                           const int32_t *__restrict__ cell_start,
+                                                           int32_t *__restrict__ items, int64_t cap_items,
+                                                           int64_t total_cells, DevStatus *st, int pass) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Tm) return;
+  int e = m_env[t];
+  GridEnv g = grid[e];
+  if (!g.valid) return;
+  float4 a = mbox[3 * t], b = mbox[3 * t + 1];
+  float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+  if (!box_hits_grid(g, lo, hi)) return;
+  int c0[3], c1[3];
+  for (int d = 0; d < 3; ++d) {
+    c0[d] = cell_coord(g, lo[d], d);
+    c1[d] = cell_coord(g, hi[d], d);
+  }
+  int64_t base = env[e].cell0;
+  bool fits = true;
+  if (pass == 1) {
+    int64_t total = cell_start[total_cells];
+    fits = total <= cap_items;
+    if (!fits && t == 0) {
+      atomicMax(&st->need_items, (unsigned long long)total);
+      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+    }
+  }
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+        if (pass == 0) {
+          atomicAdd(&cell_cnt[cell], 1);
+        } else {
+          int slot = cell_start[cell] + atomicSub(&cell_cnt[cell], 1) - 1;
+          if (fits) items[slot] = (int32_t)t;
+        }
+      }
+}
+
+// prism box of slave triangle t: its vertices moved by +-eps_max along n_T
+template <typename R>
+__device__ inline bool prism_box(const R *xs, const int32_t *ts, int64_t t, float eps, float lo[3], float hi[3],
+                                 float n_out[3]) {
+  R p[3][3];
+  for (int j = 0; j < 3; ++j) {
+    int64_t v = ts[3 * t + j];
+    for (int d = 0; d < 3; ++d) p[j][d] = xs[3 * v + d];
+  }
+  R e1[3], e2[3];
+  for (int d = 0; d < 3; ++d) {
+    e1[d] = p[1][d] - p[0][d];
+    e2[d] = p[2][d] - p[0][d];
+  }
+  R N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  R len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+  if (!(len > R(0))) return false;
+  float n[3] = {(float)(N[0] / len), (float)(N[1] / len), (float)(N[2] / len)};
+  for (int d = 0; d < 3; ++d) {
+    float off = fabsf(n[d]) * eps;
+    float a = fminf(fminf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
+    float b = fmaxf(fmaxf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
+    lo[d] = a - off - grow(a) - eps * 1e-6f;
+    hi[d] = b + off + grow(b) + eps * 1e-6f;
+    n_out[d] = n[d];
+  }
+  return true;
+}
+
+constexpr int kQueryWaves = kThreads / kWave;
+constexpr int kQuerySort = 256;  // lists up to this length are sorted in LDS
+
+// One wave per slave triangle; the lanes split the cells of the prism box.
+// pass 0: count the candidates; pass 1: write them (wave prefix offsets)
+// and sort the triangle's list ascending.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, const int32_t *__restrict__ ts,
+                                                     const int32_t *__restrict__ s_order,
+                                                     const int32_t *__restrict__ s_env,
+                                                     const EnvInfo *__restrict__ env,
+                                                     const GridEnv *__restrict__ grid, int64_t Ts,
+                                                     const int32_t *__restrict__ cell_start,
+                                                     const int32_t *__restrict__ items,
+                                                     const float4 *__restrict__ mbox, int32_t *__restrict__ cand_cnt,
+                                                     const int32_t *__restrict__ cand_off, int32_t *__restrict__ cand,
+                                                     int64_t cap_cand, int64_t cap_items, int64_t total_cells,
+                                                     DevStatus *st, int pass) {
+  __shared__ int32_t lst[kQueryWaves][kQuerySort];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kQueryWaves + w;
+  if (i >= Ts) return;
+  const int64_t t = s_order[i];
+  if (cell_start[total_cells] > cap_items) {  // grid incomplete
+    if (pass == 0 && lane == 0) cand_cnt[t] = 0;
+    return;
+  }
+  int64_t out = 0;
+  if (pass == 1) {
+    out = cand_off[t];
+    if (cand_off[Ts] > cap_cand) {
+      if (i == 0 && lane == 0) {
+        atomicMax(&st->need_cand, (unsigned long long)cand_off[Ts]);
+        atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+      }
+      return;
+    }
+  }
+  const int e = s_env[t];
+  const GridEnv g = grid[e];
+  const float eps = (float)env[e].dhat;
+  float lo[3], hi[3], n[3];
+  int c0[3] = {0, 0, 0}, c1[3] = {-1, 0, 0};
+  if (g.valid && prism_box(xs, ts, t, eps, lo, hi, n) && box_hits_grid(g, lo, hi)) {
+    for (int d = 0; d < 3; ++d) {
+      c0[d] = cell_coord(g, lo[d], d);
+      c1[d] = cell_coord(g, hi[d], d);
+    }
+  }
+  const int nxr = c1[0] - c0[0] + 1, nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
+  const int ncell = nxr > 0 ? nxr * nyr * nzr : 0;
+  const int64_t base = env[e].cell0;
+  // walk this lane's cells; emit(M) for each candidate reported here
+  auto walk = [&](auto &&emit) {
+    for (int ci = lane; ci < ncell; ci += kWave) {
+      int x = c0[0] + ci % nxr, y = c0[1] + (ci / nxr) % nyr, z = c0[2] + ci / (nxr * nyr);
+      int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+      int s0 = cell_start[cell], s1 = cell_start[cell + 1];
+      for (int j = s0; j < s1; ++j) {
+        int M = items[j];
+        float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1], nm = mbox[3 * (int64_t)M + 2];
+        if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
+        // report from the cell holding the low corner of the overlap only
+        if (cell_coord(g, fmaxf(a.x, lo[0]), 0) != x || cell_coord(g, fmaxf(a.y, lo[1]), 1) != y ||
+            cell_coord(g, fmaxf(a.z, lo[2]), 2) != z)
+          continue;
+        // facing test with slack: the narrow phase takes the exact decision
+        if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
+        emit(M);
+      }
+    }
+  };
+  int cnt = 0;
+  walk([&](int) { ++cnt; });
+  int incl = cnt;
+  for (int d = 1; d < kWave; d <<= 1) {
+    int v = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += v;
+  }
+  const int total = __shfl(incl, kWave - 1, kWave);
+  if (pass == 0) {
+    if (lane == 0) cand_cnt[t] = total;
+    return;
+  }
+  int pos = incl - cnt;
+  int32_t *l = cand + out;
+  if (total <= kQuerySort) {
+    // gather in LDS, then rank sort (ids are unique) straight into place
+    walk([&](int M) { lst[w][pos++] = M; });
+    wave_sync();
+    for (int k = lane; k < total; k += kWave) {
+      int v = lst[w][k], r = 0;
+      for (int m = 0; m < total; ++m) r += lst[w][m] < v;
+      l[r] = v;
+    }
+    return;
+  }
+  walk([&](int M) { l[pos++] = M; });
+  __threadfence_block();
+  wave_sync();
+  if (lane == 0) {
+    for (int a = 1; a < total; ++a) {
+      int v = l[a], b = a - 1;
+      while (b >= 0 && l[b] > v) {
+        l[b + 1] = l[b];
+        --b;
+      }
+      l[b + 1] = v;
+    }
+  }
+}
+
+__global__ void k_cand_total(const int32_t *cand_off, int64_t Ts, DevStatus *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <typename R>
+hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, bool swept) {
+  Buffers &b = c->b;
+  uint32_t *box = swept ? b.sbox : b.box;
+  GridEnv *grid = swept ? b.sgrid : b.grid;
+  int32_t *cnt = swept ? b.scell_cnt : b.cell_cnt;
+  int32_t *start = swept ? b.scell_start : b.cell_start;
+  int32_t *items = swept ? b.sitems : b.items;
+  float4 *mbox = swept ? b.smbox : b.mbox;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_box_init, dim3((c->n_env + 63) / 64), dim3(64), 0, s, box, c->n_env);
+  if (c->Ts)
+    hipLaunchKernelGGL(k_slave_box<R>, dim3(nblk(c->Ts)), dim3(kThreads), 0, s, xs, swept ? dxs : nullptr, c->ts,
+                       b.s_env, c->Ts, box);
+  hipLaunchKernelGGL(k_grid_setup, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.env, box, grid, c->n_env,
+                     swept ? 1 : 0);
+  if (c->Tm) {
+    hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr,
+                       c->tm, c->Tm, mbox);
+    hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,
+                       cnt, start, items, c->caps.grid_items, c->total_cells, b.status, 0);
+  }
+  hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1);
+  if (e != hipSuccess) return e;
+  if (c->Tm)
+    hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,
+                       cnt, start, items, c->caps.grid_items, c->total_cells, b.status, 1);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
+  Buffers &b = c->b;
+  hipStream_t s = c->stream;
+  hipError_t e = reset_status(c, 1);
+  if (e != hipSuccess) return e;
+  prof_mark(c, ST_GRID, 0);
+  e = build_grid<R>(c, xs, xm, nullptr, nullptr, false);
+  prof_mark(c, ST_GRID, 1);
+  if (e != hipSuccess) return e;
+  prof_mark(c, ST_QUERY, 0);
+  if (c->Ts) {
+    hipLaunchKernelGGL(k_query<R>, dim3((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
+                       b.grid, c->Ts, b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand,
+                       c->caps.candidates, c->caps.grid_items, c->total_cells, b.status, 0);
+  }
+  e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(c, b.cand_cnt, b.cand_off, c->Ts + 1);
+  if (e != hipSuccess) return e;
+  if (c->Ts)
+    hipLaunchKernelGGL(k_query<R>, dim3((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
+                       b.grid, c->Ts, b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand,
+                       c->caps.candidates, c->caps.grid_items, c->total_cells, b.status, 1);
+  prof_mark(c, ST_QUERY, 1);
+  hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
+  return hipGetLastError();
+}
+
+template hipError_t build_grid<float>(gmcp_ctx *, const float *, const float *, const float *, const float *, bool);
+template hipError_t build_grid<double>(gmcp_ctx *, const double *, const double *, const double *, const double *,
+                                       bool);
+template hipError_t launch_broadphase<float>(gmcp_ctx *, const float *, const float *);
+template hipError_t launch_broadphase<double>(gmcp_ctx *, const double *, const double *);
+
+}  // namespace gmcp

@@ -1,0 +1,319 @@
+// Step bound for a search direction dx:
+//   linearised gap, Eqs. (ccd) and (global_ccd), over the selected samples
+//   of the last assembly, and additive CCD (Li, Kaufman, Jiang 2021) over
+//   swept (sample point, master triangle) pairs found with a grid over the
+//   master triangles' swept boxes.
+// Both reduce with a float atomic-min on the bit pattern of positive floats
+// (order-independent, hence deterministic).  Positions in the CCD are taken
+// relative to the sample point's start, so float32 keeps small distances.
+#include "common.h"
+
+namespace gmcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kAccdMaxIter = 1 << 14;
+
+__global__ void k_alpha_init(uint32_t *bits, int n_env) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_env) bits[e] = 0x7f800000u;  // +inf
+}
+
+template <typename R> __device__ inline float to_float_down(R v);
+template <> __device__ inline float to_float_down<float>(float v) { return v; }
+template <> __device__ inline float to_float_down<double>(double v) { return __double2float_rd(v); }
+
+__device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
+  // a >= 0 here; uint order of non-negative floats is float order
+  uint64_t vm = __ballot(env >= 0);
+  if (!vm) return;
+  int e0 = __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave);
+  bool uniform = __all(env < 0 || env == e0);
+  if (uniform) {
+    float m = env >= 0 ? a : INFINITY;
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, kWave));
+    if (lane == 0 && m < INFINITY) atomicMin(&bits[e0], __float_as_uint(m));
+  } else if (env >= 0 && a < INFINITY) {
+    atomicMin(&bits[env], __float_as_uint(a));
+  }
+}
+
+// Eq. (ccd): alpha_k = 0.9 g_k / (-grad g_k . dx) for grad g_k . dx < 0
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restrict__ rec, const DevStatus *st,
+                                                          int64_t cap_active, const R *__restrict__ tri_nrm,
+                                                          const int32_t *__restrict__ ts,
+                                                          const int32_t *__restrict__ tm,
+                                                          const int32_t *__restrict__ s_env,
+                                                          const EnvInfo *__restrict__ env,
+                                                          const double *__restrict__ rule, const R *__restrict__ dxs,
+                                                          const R *__restrict__ dxm, uint32_t *bits) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t na = (int64_t)st->n_active;
+  bool ok = na <= cap_active && i < na;
+  float a = INFINITY;
+  int e = -1;
+  if (ok) {
+    Rec<R> r = rec[i];
+    e = s_env[r.T];
+    const R *n = tri_nrm + 3 * (int64_t)r.T;
+    const double *rq = rule + ((env[e].rule_n - 1) * 16 + r.q) * 3;
+    R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
+    R bm[3] = {r.b0, r.b1, r.b2};
+    R gd = 0;
+    for (int s = 0; s < 3; ++s) {
+      const R *d = dxs + 3 * (int64_t)ts[3 * (int64_t)r.T + s];
+      gd -= bs[s] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+    }
+    if (dxm)
+      for (int m = 0; m < 3; ++m) {
+        const R *d = dxm + 3 * (int64_t)tm[3 * (int64_t)r.M + m];
+        gd += bm[m] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+      }
+    if (gd < R(0)) a = to_float_down<R>(R(0.9) * r.g / (-gd));
+  }
+  env_min(bits, e, a, lane);
+}
+
+// squared distance from the origin-relative point p to triangle (a, b, c):
+// closest point by Voronoi regions of the vertices, edges and face
+template <typename R>
+__device__ inline R pt_tri_dist2(const R p[3], const R a[3], const R b[3], const R c[3]) {
+  R ab[3], ac[3], ap[3];
+  for (int d = 0; d < 3; ++d) {
+    ab[d] = b[d] - a[d];
+    ac[d] = c[d] - a[d];
+    ap[d] = p[d] - a[d];
+  }
+  auto dot = [](const R *x, const R *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+  R q[3];
+  R d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= R(0) && d2 <= R(0)) {
+    for (int d = 0; d < 3; ++d) q[d] = a[d];
+  } else {
+    R bp[3];
+    for (int d = 0; d < 3; ++d) bp[d] = p[d] - b[d];
+    R d3 = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3 >= R(0) && d4 <= d3) {
+      for (int d = 0; d < 3; ++d) q[d] = b[d];
+    } else {
+      R vc = d1 * d4 - d3 * d2;
+      if (vc <= R(0) && d1 >= R(0) && d3 <= R(0)) {
+        R v = d1 / (d1 - d3);
+        for (int d = 0; d < 3; ++d) q[d] = a[d] + v * ab[d];
+      } else {
+        R cp[3];
+        for (int d = 0; d < 3; ++d) cp[d] = p[d] - c[d];
+        R d5 = dot(ab, cp), d6 = dot(ac, cp);
+        if (d6 >= R(0) && d5 <= d6) {
+          for (int d = 0; d < 3; ++d) q[d] = c[d];
+        } else {
+          R vb = d5 * d2 - d1 * d6;
+          if (vb <= R(0) && d2 >= R(0) && d6 <= R(0)) {
+            R w = d2 / (d2 - d6);
+            for (int d = 0; d < 3; ++d) q[d] = a[d] + w * ac[d];
+          } else {
+            R va = d3 * d6 - d5 * d4;
+            if (va <= R(0) && (d4 - d3) >= R(0) && (d5 - d6) >= R(0)) {
+              R w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+              for (int d = 0; d < 3; ++d) q[d] = b[d] + w * (c[d] - b[d]);
+            } else {
+              R den = R(1) / (va + vb + vc);
+              R v = vb * den, w = vc * den;
+              for (int d = 0; d < 3; ++d) q[d] = a[d] + ab[d] * v + ac[d] * w;
+            }
+          }
+        }
+      }
+    }
+  }
+  R r[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+  return dot(r, r);
+}
+
+// additive CCD, thickness 0, separation ratio s, horizon 1: the point starts
+// at the origin (coordinates are relative to it)
+template <typename R>
+__device__ inline R accd(const R dp[3], const R a0[3], const R da[3], const R b0[3], const R db[3], const R c0[3],
+                         const R dc[3], R s) {
+  R mean[3], up[3], ua[3], ub[3], uc[3];
+  for (int d = 0; d < 3; ++d) {
+    mean[d] = R(0.25) * (dp[d] + da[d] + db[d] + dc[d]);
+    up[d] = dp[d] - mean[d];
+    ua[d] = da[d] - mean[d];
+    ub[d] = db[d] - mean[d];
+    uc[d] = dc[d] - mean[d];
+  }
+  auto nrm = [](const R *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+  R l = nrm(up) + fmax(nrm(ua), fmax(nrm(ub), nrm(uc)));
+  if (!(l > R(0))) return R(1);
+  R p[3] = {0, 0, 0}, a[3], b[3], c[3];
+  for (int d = 0; d < 3; ++d) {
+    a[d] = a0[d];
+    b[d] = b0[d];
+    c[d] = c0[d];
+  }
+  R dist = sqrt(pt_tri_dist2(p, a, b, c));
+  if (!(dist > R(0))) return R(0);
+  R gmin = s * dist, t = 0, step = (R(1) - s) * dist / l;
+  for (int it = 0; it < kAccdMaxIter; ++it) {
+    for (int d = 0; d < 3; ++d) {
+      p[d] += step * up[d];
+      a[d] += step * ua[d];
+      b[d] += step * ub[d];
+      c[d] += step * uc[d];
+    }
+    dist = sqrt(pt_tri_dist2(p, a, b, c));
+    if (t > R(0) && dist < gmin) break;
+    t += step;
+    if (t > R(1)) return R(1);
+    step = R(0.9) * dist / l;
+  }
+  return t;
+}
+
+__device__ inline int cell_coord(const GridEnv &g, float x, int d) {
+  float f = (x - g.lo[d]) * g.inv_h;
+  int n = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+  int c = (int)floorf(f);
+  return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+// one thread per (slave triangle, rule point)
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_ccd_accd(
+    const R *__restrict__ xs, const R *__restrict__ xm, const R *__restrict__ dxs, const R *__restrict__ dxm,
+    const int32_t *__restrict__ ts, const int32_t *__restrict__ tm, const int32_t *__restrict__ s_order,
+    const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const double *__restrict__ rule,
+    const GridEnv *__restrict__ grid, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items,
+    const float4 *__restrict__ smbox, int64_t Ts, int64_t cap_items, int64_t total_cells, uint32_t *bits,
+    DevStatus *st) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t ti = i / 16;
+  int q = (int)(i % 16);
+  float amin = INFINITY;
+  int e = -1;
+  unsigned long long npairs = 0;
+  if (ti < Ts && cell_start[total_cells] <= cap_items) {
+    int64_t T = s_order[ti];
+    e = s_env[T];
+    const EnvInfo &ev = env[e];
+    GridEnv g = grid[e];
+    if (q < ev.nq && g.valid) {
+      const double *rq = rule + ((ev.rule_n - 1) * 16 + q) * 3;
+      R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
+      int64_t v[3] = {ts[3 * T], ts[3 * T + 1], ts[3 * T + 2]};
+      R s0[3], dp[3], off[3];
+      for (int d = 0; d < 3; ++d) {
+        s0[d] = xs[3 * v[0] + d];
+        off[d] = bs[1] * (xs[3 * v[1] + d] - s0[d]) + bs[2] * (xs[3 * v[2] + d] - s0[d]);
+        dp[d] = bs[0] * dxs[3 * v[0] + d] + bs[1] * dxs[3 * v[1] + d] + bs[2] * dxs[3 * v[2] + d];
+      }
+      float lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        R p0 = s0[d] + off[d];
+        float a = (float)p0, b = (float)(p0 + dp[d]);
+        float mn = fminf(a, b), mx = fmaxf(a, b);
+        lo[d] = mn - fabsf(mn) * 4e-7f - 1e-30f;
+        hi[d] = mx + fabsf(mx) * 4e-7f + 1e-30f;
+      }
+      int c0[3], c1[3];
+      for (int d = 0; d < 3; ++d) {
+        c0[d] = cell_coord(g, lo[d], d);
+        c1[d] = cell_coord(g, hi[d], d);
+      }
+      float ext[3] = {g.nx * g.h, g.ny * g.h, g.nz * g.h};
+      bool inside = true;
+      for (int d = 0; d < 3; ++d)
+        if (hi[d] < g.lo[d] || lo[d] > g.lo[d] + ext[d]) inside = false;
+      if (inside) {
+        int64_t base = ev.cell0;
+        for (int z = c0[2]; z <= c1[2]; ++z)
+          for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) {
+              int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+              for (int jj = cell_start[cell]; jj < cell_start[cell + 1]; ++jj) {
+                int M = items[jj];
+                float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
+                if (ma.x > hi[0] || mb.x < lo[0] || ma.y > hi[1] || mb.y < lo[1] || ma.z > hi[2] || mb.z < lo[2])
+                  continue;
+                if (cell_coord(g, fmaxf(ma.x, lo[0]), 0) != x || cell_coord(g, fmaxf(ma.y, lo[1]), 1) != y ||
+                    cell_coord(g, fmaxf(ma.z, lo[2]), 2) != z)
+                  continue;
+                ++npairs;
+                R A[3], B[3], C[3], dA[3], dB[3], dC[3];
+                int64_t w0 = tm[3 * (int64_t)M], w1 = tm[3 * (int64_t)M + 1], w2 = tm[3 * (int64_t)M + 2];
+                for (int d = 0; d < 3; ++d) {
+                  R pd = s0[d] + off[d];
+                  A[d] = (xm[3 * w0 + d] - s0[d]) - off[d];
+                  B[d] = (xm[3 * w1 + d] - s0[d]) - off[d];
+                  C[d] = (xm[3 * w2 + d] - s0[d]) - off[d];
+                  (void)pd;
+                  dA[d] = dxm ? dxm[3 * w0 + d] : R(0);
+                  dB[d] = dxm ? dxm[3 * w1 + d] : R(0);
+                  dC[d] = dxm ? dxm[3 * w2 + d] : R(0);
+                }
+                R t = accd<R>(dp, A, dA, B, dB, C, dC, R(0.1));
+                amin = fminf(amin, to_float_down<R>(t));
+              }
+            }
+      }
+    }
+  }
+  // pair count: wave sum, one atomic
+  unsigned long long tot = npairs;
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
+  if (lane == 0 && tot) atomicAdd(&st->n_swept, tot);
+  env_min(bits, e, amin, lane);
+}
+
+template <typename R>
+__global__ void k_alpha_final(const uint32_t *bits, int n_env, R *alpha) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_env) return;
+  float a = __uint_as_float(bits[e]);
+  // shrink the float bound so it never exceeds the exact one
+  float r = a < 1.0f ? a * (1.0f - 1.0f / 8192.0f) : 1.0f;
+  alpha[e] = (R)r;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha) {
+  Buffers &b = c->b;
+  hipStream_t s = c->stream;
+  hipError_t e = reset_status(c, 4);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_alpha_init, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env);
+  const R *dm = dxm;
+  prof_mark(c, ST_CCD_LINEAR, 0);
+  hipLaunchKernelGGL(k_ccd_linear<R>, dim3(nblk(c->caps.active)), dim3(kThreads), 0, s, (const Rec<R> *)b.rec,
+                     b.status, c->caps.active, (const R *)b.tri_nrm, c->ts, c->tm, b.s_env, b.env, b.rule, dxs, dm,
+                     b.alpha_bits);
+  prof_mark(c, ST_CCD_LINEAR, 1);
+  prof_mark(c, ST_CCD_GRID, 0);
+  e = build_grid<R>(c, xs, xm, dxs, dm, true);
+  prof_mark(c, ST_CCD_GRID, 1);
+  if (e != hipSuccess) return e;
+  prof_mark(c, ST_CCD_ACCD, 0);
+  if (c->Ts)
+    hipLaunchKernelGGL(k_ccd_accd<R>, dim3(nblk(c->Ts * 16)), dim3(kThreads), 0, s, xs, xm, dxs, dm, c->ts, c->tm,
+                       b.s_order, b.s_env, b.env, b.rule, b.sgrid, b.scell_start, b.sitems, b.smbox, c->Ts,
+                       c->caps.grid_items, c->total_cells, b.alpha_bits, b.status);
+  prof_mark(c, ST_CCD_ACCD, 1);
+  hipLaunchKernelGGL(k_alpha_final<R>, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env, alpha);
+  return hipGetLastError();
+}
+
+template hipError_t launch_ccd<float>(gmcp_ctx *, const float *, const float *, const float *, const float *,
+                                      float *);
+template hipError_t launch_ccd<double>(gmcp_ctx *, const double *, const double *, const double *, const double *,
+                                       double *);
+
+}  // namespace gmcp

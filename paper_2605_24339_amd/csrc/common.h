@@ -1,0 +1,204 @@
+// Internal declarations of the GMCP HIP library (gfx950 only).
+//
+// Device-side data layout (all carved from the caller's workspace):
+//   static   - rules, per-environment parameters, Morton-ordered work tiles,
+//              vertex->triangle adjacency of both meshes, rest areas;
+//   per call - broad-phase grid and candidate lists, active-sample records,
+//              per-slave-triangle sums, contact pairs, pairs bucketed by
+//              master triangle, BSR row counts, step-bound scratch, status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/gmcp.h"
+
+namespace gmcp {
+
+constexpr int kWave = 64;
+constexpr int kMaxRule = 4;            // n <= 4  => <= 16 samples per triangle
+constexpr int kTilePerBlock = 4;       // narrow phase: 4 waves, one tile each
+
+// ---------------------------------------------------------------- status
+struct DevStatus {
+  int32_t code;
+  int32_t pad;
+  unsigned long long index;  // min offending id (atomicMin), ~0ull if none
+  unsigned long long n_active, n_pairs, nnzb, n_cand, n_swept;
+  unsigned long long need_items, need_cand, need_active, need_pairs, need_row;
+};
+
+// --------------------------------------------------------- per environment
+struct EnvInfo {
+  double kappa, dhat, delta_T, cell;
+  int32_t rule_n, nq;
+  int32_t sv0, sv1, st0, st1;   // slave vertex / triangle ranges
+  int32_t mv0, mv1, mt0, mt1;   // master ranges
+  int64_t cell0, cell_budget;   // grid cell slice [cell0, cell0 + budget)
+  int64_t samp0;                // first sample id
+  int32_t tile0, tile1;         // work tiles of this environment
+};
+
+struct GridEnv {           // one environment's uniform grid for this call
+  float lo[3];
+  float h, inv_h;
+  int32_t nx, ny, nz;
+  int32_t valid;
+};
+
+struct Tile {              // narrow-phase work item: tris [first, first+count) of s_order
+  int32_t first, count, env, nq;
+};
+
+template <typename R>
+struct Rec {               // selected sample record
+  int32_t k, M, T, q;
+  R g, b0, b1, b2, c1, c2, p, pad;
+};
+
+template <typename R>
+struct Pair {              // one (slave triangle, master triangle) contact
+  int32_t T, M;
+  R mm[6];   // sum c2 bm_i bm_j           (sym, order 00 01 02 11 12 22)
+  R sm[9];   // sum -c2 bs_a bm_j          (a-major)
+  R gm[3];   // sum c1 bm_j
+};
+
+// ----------------------------------------------------------------- context
+struct Buffers {
+  // static
+  EnvInfo *env;
+  Tile *tiles;
+  int32_t *s_order, *samp_off, *s_env, *m_env;
+  int32_t *s_vt_off, *s_vt, *m_vt_off, *m_vt;   // vt entries: tri*4 + corner
+  double *rule;                                 // [4][16][3] xi, eta, w
+  void *area;                                   // [Ts] R
+  // broad phase
+  GridEnv *grid;
+  uint32_t *box;                                // [n_env][6] ordered-float bits
+  int32_t *cell_cnt, *cell_start, *items;
+  float4 *mbox;                                 // [Tm][3]: lo, hi, unit normal
+  int32_t *cand_cnt, *cand_off, *cand;
+  // narrow / assembly
+  void *rec;                                    // Rec<R>[cap.active]
+  void *tri_nrm;                                // [Ts][3] R
+  void *tri_sum;                                // [Ts][9] R: ss[6], gs[3]
+  int32_t *tri_npair, *tri_poff, *tri_roff, *tri_rcnt;
+  void *pair;                                   // Pair<R>[cap.pairs]
+  double *tile_E;
+  int32_t *mp_cnt, *mp_off, *mp_list;
+  int32_t *row_cnt;                             // [V+1]
+  // step bound
+  GridEnv *sgrid;
+  uint32_t *sbox;
+  int32_t *scell_cnt, *scell_start, *sitems;
+  float4 *smbox;                                // [Tm][3]: swept lo, hi, (unused)
+  uint32_t *alpha_bits;                         // [n_env]
+  // hvp
+  void *hv_tri;                                 // [Ts][3] R
+  void *hv_pair;                                // [pairs][3] R
+  // scan scratch
+  int32_t *scan_tmp;
+  DevStatus *status;
+};
+
+// kernel stages timed by the optional event profiler (gmcp_profile)
+enum Stage {
+  ST_GRID = 0,     // grid build (boxes, counts, scan, placement)
+  ST_QUERY,        // candidate query (count + fill)
+  ST_NARROW,       // narrow phase + barrier + per-triangle / pair sums
+  ST_BUCKET,       // pairs bucketed by master triangle
+  ST_GRAD,         // gradient rows
+  ST_ROWS,         // BSR rows (count + fill)
+  ST_CCD_LINEAR,   // linearised step bound
+  ST_CCD_GRID,     // swept grid build
+  ST_CCD_ACCD,     // additive CCD over swept pairs
+  ST_COUNT
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<int> stage;          // per recorded pair
+  std::vector<size_t> first;       // index of the start event in pool
+};
+
+}  // namespace gmcp
+
+struct gmcp_ctx {
+  gmcp::Prof prof;
+  hipStream_t stream;
+  bool f64, kinematic;
+  int n_env;
+  int64_t Vs, Vm, Ts, Tm, Ns, V, n_tiles, total_cells;
+  gmcp_caps caps;
+  const int32_t *ts, *tm;
+  std::vector<gmcp::EnvInfo> henv;
+  bool samples_built, broadphase_done, assembled;
+  gmcp::Buffers b;
+  size_t scan_tmp_elems;
+};
+
+namespace gmcp {
+
+// ------------------------------------------------------------ launchers
+// each returns hipSuccess or the launch error
+hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n);
+hipError_t fill_i32(gmcp_ctx *c, int32_t *p, int32_t v, int64_t n);
+hipError_t reset_status(gmcp_ctx *c, int which);
+// event profiler: prof_mark(c, s, 0) before a stage's launches, (c, s, 1) after
+void prof_mark(gmcp_ctx *c, int stage, int end);
+
+template <typename R> hipError_t launch_rest_area(gmcp_ctx *c, const R *x_rest, R *weights);
+template <typename R> hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm);
+// grid over master triangles per environment; swept != 0 uses the boxes of
+// the motion x -> x + dx (domain: slave swept box) instead of the prism region
+template <typename R>
+hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, bool swept);
+template <typename R>
+hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref, const R *dgap,
+                           R *energy, R *grad, const gmcp_bsr *H);
+template <typename R>
+hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha);
+template <typename R>
+hipError_t launch_hvp(gmcp_ctx *c, const R *vx, const R *vd, R *ox, R *od);
+template <typename R>
+hipError_t launch_sample_results(gmcp_ctx *c, int32_t *M, R *g, R *bm, R *c1, R *c2, R *p);
+
+// ---------------------------------------------------------- device utils
+__device__ inline uint32_t float_to_ordered(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ordered_to_float(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ inline void set_error(DevStatus *st, int code, unsigned long long index) {
+  atomicCAS(&st->code, 0, code);
+  atomicMin(&st->index, index);
+}
+
+// xcd-aware block index: hardware dispatches consecutive blocks round-robin
+// over the 8 XCDs; this makes consecutive logical blocks land on one XCD so
+// neighbouring (Morton-adjacent) work shares that XCD's L2.
+__device__ inline int xcd_block(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  int per = (nblocks + kXcd - 1) / kXcd;
+  int x = bid % kXcd, i = bid / kXcd;
+  int full = nblocks % kXcd;  // XCDs 0..full-1 get `per` blocks, others per-1
+  if (full == 0) return x * per + i;
+  if (x < full) return x * per + i;
+  return full * per + (x - full) * (per - 1) + i;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace gmcp
