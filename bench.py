@@ -3,13 +3,16 @@
 
 One step = one pass of the whole path over the resident input: broad phase,
 assembly (selection, barrier, energy, gradient, BSR Hessian) and the step
-bound (linearised gap + additive CCD).  Workload: the single large
+bound (linearised gap + additive CCD).  Headline workload: the single large
 indentation - 128x128 noisy gel pad (32768 triangles, 4x4 samples each =
 524288 samples) under a 40500-triangle perturbed geodesic sphere, float32.
+The step is captured once into a HIP graph and replayed; the broad-phase
+cell size is chosen by the autotuner first.
 
 Prints one JSON line: samples/s over the timed steps (inputs already in
-HBM), per-stage HIP-event times, the roofline of the dominant stage and the
-FP64 oracle's throughput on the host cores (a reported baseline).
+HBM), per-kernel HIP-event times, the roofline of the dominant kernel, the
+same figures for the 256-environment batch, and the FP64 oracle's
+throughput on the host cores (a reported baseline, not the target).
 """
 from __future__ import annotations
 
@@ -25,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMCP samples/s (E+grad+Hess) & CCD pairs/s, % HBM peak; Newton iters learned vs plain"
 HBM_PEAK_GBS = 8000.0
+# kernels that one profiled stage brackets exactly (candidates for the roofline)
+KERNEL_STAGES = {"query_count": "k_query", "query_fill": "k_query", "narrow": "k_narrow",
+                 "grad_rows": "k_grad", "rows_count": "k_rows", "rows_fill": "k_rows",
+                 "ccd_linear": "k_ccd_linear", "ccd_accd": "k_ccd_accd"}
 
 
 def src_hash() -> str:
@@ -36,34 +43,104 @@ def src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stage_bytes(stage: str, w, st, ctx) -> float | None:
-    """Algorithmic bytes of one launch of a stage: every input the stage's
-    function needs read once, every output it produces written once."""
-    Vs, Vm, Ts, Tm = w.xs.shape[0], w.xm.shape[0], w.ts.shape[0], w.tm.shape[0]
-    na, npair, nc = int(st.n_active), int(st.n_pairs), int(st.n_candidates)
+def kernel_bytes(stage: str, sz: dict) -> int:
+    """Algorithmic bytes of one launch: each input the kernel's function
+    needs, read once, and each output it produces, written once (float32)."""
+    Vs, Vm, Ts, Tm = sz["Vs"], sz["Vm"], sz["Ts"], sz["Tm"]
+    na, npair, nc, nnzb, ntile = sz["n_active"], sz["n_pairs"], sz["n_cand"], sz["nnzb"], sz["n_tiles"]
+    V = Vs + Vm
     if stage == "narrow":
-        # slave positions/triangles/areas, candidate lists, master triangles and
-        # positions; selected-sample records (48 B), per-triangle normal+sums
-        # (48 B) and counters (16 B), pair sums (80 B), tile energies
-        return (12 * Vs + 12 * Ts + 4 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm
-                + 48 * na + 48 * Ts + 16 * Ts + 80 * npair + 8 * ctx.n_tiles_est)
-    if stage == "bsr_rows":
-        nnzb = int(st.nnzb)
-        return (4 * 3 * Ts + 48 * Ts + 80 * npair + 4 * 3 * Tm + 4 * (Vs + Vm + 2)
-                + 40 * nnzb + 4 * (Vs + Vm + 1))
-    if stage == "cand_query":
-        return 12 * Vs + 12 * Ts + 48 * Tm + 4 * (Ts + 1) + 4 * nc
+        # slave x / triangles / areas, candidate CSR, master triangles + x;
+        # records 48 B per selected sample, per-triangle normal+sums+counters
+        # 64 B, pairs 80 B, tile energies 8 B
+        return 12 * Vs + 16 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm + 48 * na + 64 * Ts + 80 * npair + 8 * ntile
+    if stage in ("query_count", "query_fill"):
+        out = 4 * Ts if stage == "query_count" else 4 * nc
+        return 12 * Vs + 12 * Ts + 48 * Tm + 4 * (Ts + 1) + out
+    if stage in ("rows_count", "rows_fill"):
+        out = 4 * V if stage == "rows_count" else 40 * nnzb + 4 * (V + 1)
+        return 48 * Ts + 84 * npair + 4 * (V + 1) + 12 * (Ts + Tm) + 4 * (Tm + 1) + out
+    if stage == "grad_rows":
+        return 48 * Ts + 84 * npair + 4 * (V + 1) + 12 * (Ts + Tm) + 4 * (Tm + 1) + 12 * V
+    if stage == "ccd_linear":
+        return 48 * na + 12 * Ts + 24 * Vs + 12 * Tm + 12 * Vm
     if stage == "ccd_accd":
         return 24 * Vs + 12 * Ts + 24 * Vm + 12 * Tm + 48 * Tm
-    if stage == "grid_build":
-        return 12 * Vs + 12 * Ts + 12 * Vm + 12 * Tm + 48 * Tm
-    if stage == "grad_rows":
-        return 48 * Ts + 80 * npair + 12 * (Vs + Vm)
-    return None
+    return 0
+
+
+def time_replays(g, steps: int, stream) -> float:
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure(name, envs, batch, steps, warmup, dev):
+    """Autotune, capture, time; per-kernel stage times; roofline of the
+    dominant kernel."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24339_amd import Context, autotune
+
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    xs, xm, dxs, dxm = t(batch.xs), t(batch.xm), t(batch.dxs), t(batch.dxm)
+
+    def make(cells):
+        return Context(batch.ts, batch.tm, batch.slave_v_off, batch.slave_t_off, batch.master_v_off,
+                       batch.master_t_off, [w.rule_n for w in envs], [w.kappa for w in envs],
+                       [w.dhat for w in envs], [w.delta_T for w in envs], cells, dtype=torch.float32,
+                       device=dev)
+
+    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=None)
+    ctx = make(cells)
+    ctx.build_samples(xs)
+    g = ctx.capture(xs, xm, dxs, dxm)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        g.replay()
+    ms = time_replays(g, steps, stream)
+    st = ctx.status()
+    if st.code != 0:
+        raise SystemExit(f"{name}: status {st.code} after the timed steps")
+    ctx.profile(True)
+    for _ in range(max(3, min(steps, 20))):
+        ctx.step(xs, xm, dxs, dxm)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    st = ctx.status()
+    stages = {k: v[0] / v[1] for k, v in prof.items() if v[1] > 0}
+    Ns = sum(w.n_samples for w in envs)
+    sz = dict(Vs=batch.xs.shape[0], Vm=batch.xm.shape[0], Ts=batch.ts.shape[0], Tm=batch.tm.shape[0],
+              n_active=int(st.n_active), n_pairs=int(st.n_pairs), n_cand=int(st.n_candidates),
+              nnzb=int(st.nnzb), n_tiles=sum((w.ts.shape[0] * w.rule_n ** 2 + 63) // 64 for w in envs))
+    kern = {k: v for k, v in stages.items() if k in KERNEL_STAGES}
+    dom = max(kern, key=kern.get)
+    byts = kernel_bytes(dom, sz)
+    achieved = byts / (kern[dom] * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            rec = json.load(fh).get(f"{name}/{dom}")
+        if rec and rec.get("src_hash") == src_hash():
+            traffic = rec.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": KERNEL_STAGES[dom],
+            "stage": dom, "algorithmic_bytes": int(byts), "avg_ms": round(kern[dom], 5)}
+    ccd_ms = stages.get("ccd_linear", 0) + stages.get("ccd_grid", 0) + stages.get("ccd_accd", 0)
+    return dict(ms=ms, value=Ns / (ms * 1e-3), samples=Ns, stages={k: round(v, 5) for k, v in stages.items()},
+                roofline=roof, sizes=sz, n_swept=int(st.n_swept), ccd_ms=ccd_ms, autotune=table,
+                cells=cells[:4])
 
 
 def cpu_baseline(w, budget_s: float) -> dict:
-    import numpy as np
     import oracle
     from gen import workloads
     P = workloads.to_problem(w)
@@ -77,31 +154,30 @@ def cpu_baseline(w, budget_s: float) -> dict:
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    ns = P.Ns * reps
-    return {"value": ns / dt, "unit": "samples/s", "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
-            "kind": "oracle",
-            "sample": f"{reps} full passes (narrow + assembly with BSR + step bound) of the whole "
-                      f"{P.Ns}-sample workload, FP64, {dt:.1f} s"}
+    return {"value": P.Ns * reps / dt, "unit": "samples/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", threads)), "kind": "oracle",
+            "sample": f"{reps} full passes (narrow phase + assembly with BSR + step bound) over all "
+                      f"{P.Ns} samples of the same workload, FP64, OpenMP, {dt:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--indenter", default="sphere", choices=["sphere", "letter"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph of the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -115,91 +191,41 @@ def main():
         return
 
     from gen import workloads
-    from paper_2605_24339_amd import Context
 
-    w = workloads.large_indent(indenter=args.indenter)
     dev = torch.device("cuda", 0)
-    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
-    xs, xm, dxs, dxm = t(w.xs), t(w.xm), t(w.dxs), t(w.dxm)
-    ctx = Context.single(w.ts, w.tm, w.xs.shape[0], w.xm.shape[0], rule_n=w.rule_n, kappa=w.kappa,
-                         dhat=w.dhat, delta_T=w.delta_T, dtype=torch.float32, device=dev)
-    ctx.build_samples(xs)
-    # first pass settles the capacities (checked), then unchecked steps
-    ctx.step(xs, xm, dxs, dxm, check=True)
-    for _ in range(max(0, args.warmup - 1)):
-        ctx.step(xs, xm, dxs, dxm)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.step(xs, xm, dxs, dxm)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = e0.elapsed_time(e1) / args.steps
-    st = ctx.status()
-    if st.code != 0:
-        raise SystemExit(f"status {st.code} after the timed steps")
-    n_swept = int(st.n_swept)
-    n_active = int(st.n_active)
-
-    # per-stage times over a second timed pass (events on the library's stream)
-    ctx.profile(True)
-    for _ in range(args.steps):
-        ctx.step(xs, xm, dxs, dxm)
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    st2 = ctx.status()
-    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
-    ctx.n_tiles_est = (w.ts.shape[0] + 3) // 4
-    dom = max(stages, key=stages.get)
-    dom_ms = stages[dom]
-    byts = stage_bytes(dom, w, st2, ctx)
-    roof = None
-    if byts is not None:
-        achieved = byts / (dom_ms * 1e-3) / 1e9
-        traffic = None
-        tf = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tf):
-            with open(tf) as fh:
-                rec = json.load(fh)
-            ent = rec.get(dom)
-            if ent and ent.get("src_hash") == src_hash() and ent.get("workload") == w.name:
-                traffic = ent.get("bytes_per_launch")
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes": int(byts), "avg_ms": round(dom_ms, 5)}
-
-    Ns = w.n_samples
+    w = workloads.large_indent(indenter=args.indenter)
+    single = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev)
     out = {
         "metric": METRIC,
-        "value": Ns / (ms * 1e-3),
+        "value": single["value"],
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": single["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "slave_tris": int(w.ts.shape[0]), "samples": int(Ns),
+        "config": {"workload": w.name, "slave_tris": int(w.ts.shape[0]), "samples": int(w.n_samples),
                    "master_tris": int(w.tm.shape[0]), "rule": f"{w.rule_n}x{w.rule_n}", "dhat": w.dhat,
                    "kappa": w.kappa},
-        "ccd_pairs_per_s": (n_active + n_swept) / ((stages.get("ccd_linear", 0) + stages.get("ccd_grid", 0)
-                                                    + stages.get("ccd_accd", 0)) * 1e-3 + 1e-30),
-        "active_samples": n_active,
-        "swept_pairs": n_swept,
-        "nnzb": int(st2.nnzb),
-        "stage_ms": {k: round(v, 5) for k, v in stages.items()},
-        "wall_s_timed": round(wall, 4),
-        "roofline": roof,
+        "ccd_pairs_per_s": (single["sizes"]["n_active"] + single["n_swept"]) / (single["ccd_ms"] * 1e-3),
+        "active_samples": single["sizes"]["n_active"],
+        "swept_pairs": single["n_swept"],
+        "nnzb": single["sizes"]["nnzb"],
+        "stage_ms": single["stages"],
+        "autotune_ms": single["autotune"],
+        "roofline": single["roofline"],
     }
+    if not args.no_batched:
+        B = workloads.batched()
+        bt = measure("batched_256", B.envs, B, max(5, args.steps // 10), 2, dev)
+        out["batched"] = {"workload": "batched_256_envs", "samples": bt["samples"], "value": bt["value"],
+                          "unit": "samples/s", "ms_per_step": bt["ms"], "stage_ms": bt["stages"],
+                          "ccd_pairs_per_s": (bt["sizes"]["n_active"] + bt["n_swept"]) / (bt["ccd_ms"] * 1e-3),
+                          "roofline": bt["roofline"], "autotune_ms": bt["autotune"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

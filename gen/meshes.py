@@ -185,6 +185,37 @@ def letter(cell: float = 1e-3, depth: float = 4e-3, refine: int = 10, glyph=None
     return pts, tri
 
 
+def tet_block(nx: int, ny: int, nz: int, h: float):
+    """Box of nx x ny x nz cubes of edge h over [0, nx h] x [0, ny h] x [0, nz h],
+    each cube split into 6 tetrahedra along its main diagonal (Kuhn split),
+    consistently positively oriented.  Returns (x [V, 3], tets [6 n, 4],
+    top [2 nx ny, 3] boundary triangles of the face z = nz h, CCW from +z,
+    bottom vertex ids on z = 0)."""
+    gx, gy, gz = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    x = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(np.float64) * h
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    c = [vid(i + (b & 1), j + ((b >> 1) & 1), k + ((b >> 2) & 1)) for b in range(8)]  # corner b = (dx, dy, dz)
+    # the six monotone paths from corner 0 to corner 7
+    paths = [(1, 3), (1, 5), (2, 3), (2, 6), (4, 5), (4, 6)]
+    tets = []
+    for a, b in paths:
+        tets.append(np.stack([c[0], c[a], c[b], c[7]], 1))
+    tets = np.concatenate(tets).astype(np.int64)
+    p = x[tets]
+    vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+    flip = vol < 0
+    tets[flip] = tets[flip][:, [0, 2, 1, 3]]
+    ti, tj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ti, tj = ti.ravel(), tj.ravel()
+    v00, v10 = vid(ti, tj, nz), vid(ti + 1, tj, nz)
+    v11, v01 = vid(ti + 1, tj + 1, nz), vid(ti, tj + 1, nz)
+    top = np.concatenate([np.stack([v00, v10, v11], 1), np.stack([v00, v11, v01], 1)])
+    bottom = np.nonzero(x[:, 2] == 0.0)[0]
+    return x, tets.astype(np.int32), top.astype(np.int32), bottom.astype(np.int32)
+
+
 def random_rotation(rng) -> np.ndarray:
     """Uniformly distributed rotation matrix (from a normalised quaternion)."""
     q = rng.normal(size=4)

@@ -114,6 +114,86 @@ def large_indent(seed: int = 2, fp32: bool = True, indenter: str = "sphere",
     return _finish(w, fp32)
 
 
+@dataclass
+class Batch:
+    """Environments concatenated: global vertex ids, offset tables per env."""
+    envs: list
+    xs: np.ndarray
+    ts: np.ndarray
+    xm: np.ndarray
+    tm: np.ndarray
+    dxs: np.ndarray
+    dxm: np.ndarray
+    slave_v_off: np.ndarray
+    slave_t_off: np.ndarray
+    master_v_off: np.ndarray
+    master_t_off: np.ndarray
+
+    @property
+    def rule_n(self):
+        return [w.rule_n for w in self.envs]
+
+    @property
+    def n_samples(self):
+        return sum(w.n_samples for w in self.envs)
+
+
+def concat(envs) -> Batch:
+    vo = np.cumsum([0] + [w.xs.shape[0] for w in envs])
+    to = np.cumsum([0] + [w.ts.shape[0] for w in envs])
+    mvo = np.cumsum([0] + [w.xm.shape[0] for w in envs])
+    mto = np.cumsum([0] + [w.tm.shape[0] for w in envs])
+    return Batch(envs, np.concatenate([w.xs for w in envs]),
+                 np.concatenate([w.ts + vo[i] for i, w in enumerate(envs)]).astype(np.int32),
+                 np.concatenate([w.xm for w in envs]),
+                 np.concatenate([w.tm + mvo[i] for i, w in enumerate(envs)]).astype(np.int32),
+                 np.concatenate([w.dxs for w in envs]), np.concatenate([w.dxm for w in envs]),
+                 vo, to, mvo, mto)
+
+
+_GEO_CACHE = {}
+
+
+def _geo(freq):
+    if freq not in _GEO_CACHE:
+        _GEO_CACHE[freq] = meshes.geodesic_sphere(freq, 1.0)
+    x, t = _GEO_CACHE[freq]
+    return x.copy(), t.copy()
+
+
+def batched(n_env: int = 256, seed: int = 3000, fp32: bool = True, dt: float = 1e-3) -> Batch:
+    """Many robot-learning environments of uneven size.  Environment e (seed
+    seed + e): pad n x n with n ~ U{32..128} (10 mm, +-50 um noise); n x n
+    samples per triangle with n ~ U{2,3,4}; geodesic-sphere indenter of
+    frequency ~ U{7..45} (980..40500 triangles), R ~ U[3, 6] mm, uniform
+    random rotation, lowest vertex g_min ~ U[0.01, 0.5] dhat above the pad;
+    search direction = the indenter's rigid motion over dt with linear
+    velocity uniform in a 0.1 m/s ball and angular speed <= 1 rad/s, pad
+    vertices uniform in a 20 um ball."""
+    envs = []
+    for e in range(n_env):
+        rng = np.random.default_rng(seed + e)
+        n = int(rng.integers(32, 129))
+        rule = int(rng.integers(2, 5))
+        freq = int(rng.integers(7, 46))
+        R = rng.uniform(3e-3, 6e-3)
+        dhat = 1e-3
+        xs, ts = meshes.pad(n, 1e-2, noise=50e-6, rng=rng)
+        xm, tm = _geo(freq)
+        xm = (xm @ meshes.random_rotation(rng).T) * R
+        xm[:, :2] += rng.uniform(-1e-3, 1e-3, size=2)
+        xm = meshes.place_above(xm, xs, rng.uniform(0.01, 0.5) * dhat)
+        center = xm.mean(axis=0)
+        v = meshes.ball_uniform(rng, 1, 0.1)[0]
+        axis = rng.normal(size=3)
+        Rot = meshes.axis_angle(axis, rng.uniform(0, 1.0) * dt)
+        dxm = (xm - center) @ Rot.T + center - xm + v * dt
+        dxs = meshes.ball_uniform(rng, xs.shape[0], 20e-6)
+        w = Workload(f"env{e}", xs, ts, xm, tm, rule, 1e5, dhat, 0.0, dxs, dxm)
+        envs.append(_finish(w, fp32))
+    return concat(envs)
+
+
 def flat_punch(n_pad: int = 8, n_punch: int = 5, gap: float = 3e-4, length: float = 1e-2,
                punch_length: float = 1.4e-2, rule_n: int = 2, fp32: bool = False) -> Workload:
     """A flat rectangular master, meshed independently of the pad (its grid

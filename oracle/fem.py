@@ -1,0 +1,157 @@
+"""Oracle: linear-elastic tetrahedra and one implicit Euler step with GMCP
+contact (test infrastructure only; FP64, numpy / scipy).
+
+Incremental potential of one step (target x_tilde = x_t + dt v_t):
+    E(x) = 1/2 sum_i m_i |x_i - x_tilde_i|^2 / dt^2 + Psi_el(x) + Psi_GMCP(x)
+    Psi_el = sum_tets vol (mu eps:eps + lambda/2 tr(eps)^2),  eps = sym(grad u), u = x - X
+with linear shape functions (grad N_1..3 = rows of Dm^-1, grad N_0 = -sum),
+lumped mass rho vol / 4 per tet vertex.  Newton with a direct sparse solve,
+step capped by the GMCP step bound, Armijo backtracking; stop when
+|grad E|_inf <= tol * F_ref.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+
+
+def lame(young, poisson):
+    mu = young / (2.0 * (1.0 + poisson))
+    lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    return mu, lam
+
+
+def shape_gradients(X, tets):
+    """grad N [n_tet, 4, 3] and volumes [n_tet]."""
+    p = X[tets]
+    Dm = np.stack([p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]], axis=2)  # columns
+    inv = np.linalg.inv(Dm)
+    g = np.empty((tets.shape[0], 4, 3))
+    g[:, 1:] = inv            # row a of Dm^-1 = grad N_{a+1}
+    g[:, 0] = -inv.sum(axis=1)
+    vol = np.abs(np.linalg.det(Dm)) / 6.0
+    return g, vol
+
+
+def stiffness(X, tets, young, poisson):
+    """K (3V x 3V, scipy CSR): the Hessian of Psi_el, assembled element by element."""
+    mu, lam = lame(young, poisson)
+    g, vol = shape_gradients(X, tets)
+    n = tets.shape[0]
+    I = np.eye(3)
+    rows, cols, vals = [], [], []
+    for a in range(4):
+        for b in range(4):
+            dab = np.einsum("ni,ni->n", g[:, a], g[:, b])
+            blk = vol[:, None, None] * (mu * dab[:, None, None] * I[None]
+                                        + mu * np.einsum("ni,nk->nik", g[:, b], g[:, a])
+                                        + lam * np.einsum("ni,nk->nik", g[:, a], g[:, b]))
+            for i in range(3):
+                for k in range(3):
+                    rows.append(3 * tets[:, a] + i)
+                    cols.append(3 * tets[:, b] + k)
+                    vals.append(blk[:, i, k])
+    V = X.shape[0]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * V, 3 * V))
+
+
+def elastic_energy(X, tets, young, poisson, x):
+    """Psi_el evaluated element by element from its definition."""
+    mu, lam = lame(young, poisson)
+    g, vol = shape_gradients(X, tets)
+    u = (x - X)[tets]                                  # [n, 4, 3]
+    F = np.einsum("nai,naj->nij", u, g)                # grad u
+    eps = 0.5 * (F + np.transpose(F, (0, 2, 1)))
+    tr = np.trace(eps, axis1=1, axis2=2)
+    psi = mu * np.einsum("nij,nij->n", eps, eps) + 0.5 * lam * tr * tr
+    return float(np.sum(vol * psi))
+
+
+def lumped_mass(X, tets, rho):
+    _, vol = shape_gradients(X, tets)
+    m = np.zeros(X.shape[0])
+    for a in range(4):
+        np.add.at(m, tets[:, a], rho * vol / 4.0)
+    return m
+
+
+class Body:
+    def __init__(self, X, tets, top, fixed, young, poisson, rho, dt):
+        self.X = np.asarray(X, float)
+        self.tets = np.asarray(tets)
+        self.top = np.asarray(top)
+        self.fixed = np.zeros(self.X.shape[0], bool)
+        self.fixed[np.asarray(fixed)] = True
+        self.young, self.poisson, self.dt = young, poisson, dt
+        self.K = stiffness(self.X, self.tets, young, poisson)
+        self.m = lumped_mass(self.X, self.tets, rho)
+        self.free = np.repeat(~self.fixed, 3)
+
+    def fem_energy_grad(self, x, x_tilde):
+        dt2 = self.dt * self.dt
+        u = (x - self.X).ravel()
+        Ku = self.K @ u
+        dv = (x - x_tilde)
+        E = 0.5 * np.sum(self.m[:, None] * dv * dv) / dt2 + 0.5 * u @ Ku
+        g = (self.m[:, None] * dv / dt2).ravel() + Ku
+        return E, g.reshape(-1, 3)
+
+
+def newton_step(body: Body, P_of, x_t, v_t, fixed_pos, kappa, dhat, rule_n, xm, tol=1e-6, f_ref=1.0,
+                max_newton=60, armijo=1e-4, x_start=None):
+    """One implicit step; P_of(x) -> oracle.Problem for the slave surface at x.
+    Returns (x, stats dict)."""
+    dt = body.dt
+    fx = body.fixed
+    x_tilde = x_t + dt * v_t
+    x_tilde[fx] = fixed_pos[fx]
+    y = x_tilde.copy() if x_start is None else x_start.copy()
+    y[fx] = fixed_pos[fx]
+
+    def gmcp(x, need_h):
+        P = P_of(x)
+        nr = oracle.narrow(P)
+        A = oracle.assemble(P, nr.M, kinematic=True, project=False, hessian=need_h)
+        return P, nr.M, A
+
+    P, M, _ = gmcp(x_t, False)
+    a0 = oracle.ccd_step(P, M, y - x_t, None).alpha
+    x = x_t + a0 * (y - x_t)
+    x[fx] = fixed_pos[fx]
+    stats = dict(newton_iters=0, assemblies=0, energy_evals=0, start_alpha=a0, residual=np.inf)
+    V = x.shape[0]
+    for _ in range(max_newton):
+        Ef, gf = body.fem_energy_grad(x, x_tilde)
+        P, M, A = gmcp(x, True)
+        stats["assemblies"] += 1
+        g = gf + A.grad[:V]
+        g[fx] = 0.0
+        E = Ef + A.energy
+        stats["residual"] = np.abs(g).max() / f_ref
+        if stats["residual"] <= tol:
+            break
+        stats["newton_iters"] += 1
+        rows = np.repeat(np.arange(V), np.diff(A.row_ptr[:V + 1]))
+        Hb = sp.bsr_matrix((A.val, A.col, A.row_ptr[:V + 1]), shape=(3 * V, 3 * V)) if A.col.size else \
+            sp.csr_matrix((3 * V, 3 * V))
+        del rows
+        Asys = sp.diags(np.repeat(body.m, 3) / dt ** 2) + body.K + Hb
+        fr = body.free
+        d = np.zeros(3 * V)
+        d[fr] = spla.spsolve(Asys.tocsr()[fr][:, fr].tocsc(), -g.ravel()[fr])
+        d = d.reshape(-1, 3)
+        slope = float(np.sum(g * d))
+        alpha = min(1.0, oracle.ccd_step(P, M, d, None).alpha)
+        while True:
+            xn = x + alpha * d
+            Efn, _ = body.fem_energy_grad(xn, x_tilde)
+            _, _, An = gmcp(xn, False)
+            stats["energy_evals"] += 1
+            if Efn + An.energy <= E + armijo * alpha * slope or alpha < 1e-14:
+                break
+            alpha *= 0.5
+        x = xn
+    return x, stats

@@ -347,10 +347,12 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
 }
 
 // ---------------------------------------------------- pairs by master tri
+// pass 0: count pairs per master triangle; pass 1: place (slave triangle,
+// pair) keys into the buckets in arrival order (counters return to zero)
 template <typename R>
 __global__ void k_pair_bucket(const Pair<R> *__restrict__ pair, const DevStatus *st, int64_t cap_pairs,
                               int32_t *__restrict__ mp_cnt, const int32_t *__restrict__ mp_off,
-                              int32_t *__restrict__ mp_list, int pass) {
+                              long long *__restrict__ mp_key, int pass) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t np = (int64_t)st->n_pairs;
   if (np > cap_pairs || p >= np) return;
@@ -359,24 +361,24 @@ __global__ void k_pair_bucket(const Pair<R> *__restrict__ pair, const DevStatus 
     atomicAdd(&mp_cnt[M], 1);
   } else {
     int slot = mp_off[M] + atomicSub(&mp_cnt[M], 1) - 1;
-    mp_list[slot] = (int32_t)p;
+    mp_key[slot] = ((long long)pair[p].T << 32) | (long long)p;
   }
 }
 
+// deterministic order inside each bucket: every key is ranked among its
+// bucket's keys (slave triangle, unique per bucket) and written in place
 template <typename R>
-__global__ void k_bucket_sort(const Pair<R> *__restrict__ pair, const int32_t *__restrict__ mp_off,
-                              int32_t *__restrict__ mp_list, int64_t Tm, const DevStatus *st, int64_t cap_pairs) {
-  int64_t M = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (M >= Tm || (int64_t)st->n_pairs > cap_pairs) return;
-  int b = mp_off[M], e = mp_off[M + 1];
-  for (int i = b + 1; i < e; ++i) {  // by slave triangle: (T, M) pairs are unique
-    int v = mp_list[i], key = pair[v].T, k = i - 1;
-    while (k >= b && pair[mp_list[k]].T > key) {
-      mp_list[k + 1] = mp_list[k];
-      --k;
-    }
-    mp_list[k + 1] = v;
-  }
+__global__ void k_bucket_rank(const Pair<R> *__restrict__ pair, const int32_t *__restrict__ mp_off,
+                              const long long *__restrict__ mp_key, int32_t *__restrict__ mp_list,
+                              const DevStatus *st, int64_t cap_pairs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t np = (int64_t)st->n_pairs;
+  if (np > cap_pairs || i >= np) return;
+  long long key = mp_key[i];
+  int M = pair[key & 0xffffffffLL].M;
+  int b = mp_off[M], e = mp_off[M + 1], r = 0;
+  for (int j = b; j < e; ++j) r += mp_key[j] < key;
+  mp_list[b + r] = (int32_t)(key & 0xffffffffLL);
 }
 
 template <typename R>
@@ -397,6 +399,7 @@ struct RowArgs {
   int32_t *col;
   R *val;
   int64_t cap_nnzb;
+  R *grad;   // nullable: written by the writing pass (pass 1) or alone (pass 2)
 };
 
 constexpr int kRowWaves = 2;
@@ -441,7 +444,54 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
   const int64_t vid = slave ? row : row - a.Vs;
   const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
   const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
-  for (int i = lane; i < slots; i += kWave) {
+  // number of contributions of the row: rows without contact stop here, and
+  // the table used is sized to the row (twice its contributions, pow2)
+  int n_ent = 0;
+  for (int src = sb + lane; src < se; src += kWave) {
+    int ent = slave ? a.s_vt[src] : a.m_vt[src];
+    int t = ent >> 2;
+    if (slave) {
+      int np = a.tri_npair[t];
+      n_ent += np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
+    } else {
+      n_ent += 6 * (a.mp_off[t + 1] - a.mp_off[t]);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
+  if (pass != 0 && a.grad) {
+    // gradient row: slave a: sum_T -gs[T][a] n_T; master j: sum over the
+    // pairs of its master triangles of gm[j] n_T (lane partials, fixed-order
+    // butterfly)
+    R gr[3] = {0, 0, 0};
+    for (int src = sb + lane; src < se; src += kWave) {
+      int ent = slave ? a.s_vt[src] : a.m_vt[src];
+      int t = ent >> 2, corner = ent & 3;
+      if (slave) {
+        if (a.tri_npair[t] == 0) continue;
+        R cf = -a.tri_sum[9 * (int64_t)t + 6 + corner];
+        const R *nn = a.tri_nrm + 3 * (int64_t)t;
+        for (int d = 0; d < 3; ++d) gr[d] += cf * nn[d];
+      } else {
+        for (int i = a.mp_off[t]; i < a.mp_off[t + 1]; ++i) {
+          const Pair<R> &P = a.pair[a.mp_list[i]];
+          const R *nn = a.tri_nrm + 3 * (int64_t)P.T;
+          for (int d = 0; d < 3; ++d) gr[d] += P.gm[corner] * nn[d];
+        }
+      }
+    }
+    for (int d = 0; d < 3; ++d)
+      for (int o = 32; o > 0; o >>= 1) gr[d] += __shfl_xor(gr[d], o, kWave);
+    if (lane == 0)
+      for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = gr[d];
+  }
+  if (pass == 2) return;
+  if (n_ent == 0) {
+    if (pass == 0 && lane == 0) a.row_cnt[row] = 0;
+    return;
+  }
+  int tsz = 64;
+  while (tsz < 2 * n_ent && tsz < slots) tsz <<= 1;
+  for (int i = lane; i < tsz; i += kWave) {
     key[i] = -1;
     if (pass == 1)
       for (int c = 0; c < 6; ++c) acc[6 * i + c] = 0;
@@ -487,7 +537,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
   }
   bool full = false;
   visit_all([&](int32_t col, R cf, int t) {
-    int h = row_slot(key, slots, col, &full);
+    int h = row_slot(key, tsz, col, &full);
     if (pass == 1 && h >= 0) {
       const R *nn = a.tri_nrm + 3 * (int64_t)t;
       R v[6] = {cf * nn[0] * nn[0], cf * nn[0] * nn[1], cf * nn[0] * nn[2],
@@ -508,9 +558,9 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
   wave_sync();
   // compact the used slots
   int nuniq = 0;
-  for (int i0 = 0; i0 < slots; i0 += kWave) {
+  for (int i0 = 0; i0 < tsz; i0 += kWave) {
     int i = i0 + lane;
-    bool used = i < slots && key[i] >= 0;
+    bool used = i < tsz && key[i] >= 0;
     uint64_t m = __ballot(used);
     if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = i;
     nuniq += __popcll(m);
@@ -733,6 +783,7 @@ RowArgs<R> row_args(gmcp_ctx *c, const gmcp_bsr *H) {
   ra.col = H ? H->col : nullptr;
   ra.val = H ? (R *)H->val : nullptr;
   ra.cap_nnzb = H ? H->cap_nnzb : 0;
+  ra.grad = nullptr;
   return ra;
 }
 
@@ -793,22 +844,23 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   unsigned pb = nblk(c->caps.pairs);
   prof_mark(c, ST_BUCKET, 0);
   hipLaunchKernelGGL(k_pair_bucket<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.status, c->caps.pairs, b.mp_cnt,
-                     b.mp_off, b.mp_list, 0);
+                     b.mp_off, b.mp_key, 0);
   e = scan_exclusive(c, b.mp_cnt, b.mp_off, c->Tm + 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pair_bucket<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.status, c->caps.pairs, b.mp_cnt,
-                     b.mp_off, b.mp_list, 1);
-  if (c->Tm)
-    hipLaunchKernelGGL(k_bucket_sort<R>, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, pr, b.mp_off, b.mp_list, c->Tm,
-                       b.status, c->caps.pairs);
+                     b.mp_off, b.mp_key, 1);
+  hipLaunchKernelGGL(k_bucket_rank<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.mp_off, b.mp_key, b.mp_list, b.status,
+                     c->caps.pairs);
   prof_mark(c, ST_BUCKET, 1);
   RowArgs<R> ra = row_args<R>(c, H);
-  prof_mark(c, ST_GRAD, 0);
-  if (grad)
-    hipLaunchKernelGGL((k_grad<R, 0>), dim3(nblk(c->V)), dim3(kThreads), 0, s, ra, nullptr, nullptr, grad);
-  prof_mark(c, ST_GRAD, 1);
+  ra.grad = grad;
+  if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
+    prof_mark(c, ST_GRAD, 0);
+    hipLaunchKernelGGL(k_rows<R>, dim3((unsigned)((c->V + kRowWaves - 1) / kRowWaves)), dim3(kWave * kRowWaves), 0,
+                       s, ra, 2, 64);
+    prof_mark(c, ST_GRAD, 1);
+  }
   if (H) {
-    prof_mark(c, ST_ROWS, 0);
     // distinct-column table per wave: <= 512 slots with two waves per block,
     // 1024 with one (56 B per slot in the writing pass: <= 56 KiB of LDS)
     int slots = 64;
@@ -818,11 +870,14 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     size_t lds0 = (size_t)nw * slots * 8, lds1 = lds0 + (size_t)nw * slots * 48;
     e = fill_i32(c, b.row_cnt + c->V, 0, 1);
     if (e != hipSuccess) return e;
+    prof_mark(c, ST_ROWS_COUNT, 0);
     hipLaunchKernelGGL(k_rows<R>, dim3(rb), dim3(kWave * nw), lds0, s, ra, 0, slots);
+    prof_mark(c, ST_ROWS_COUNT, 1);
     e = scan_exclusive(c, b.row_cnt, H->row_ptr, c->V + 1);
     if (e != hipSuccess) return e;
+    prof_mark(c, ST_ROWS_FILL, 0);
     hipLaunchKernelGGL(k_rows<R>, dim3(rb), dim3(kWave * nw), lds1, s, ra, 1, slots);
-    prof_mark(c, ST_ROWS, 1);
+    prof_mark(c, ST_ROWS_FILL, 1);
     hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, s, H->row_ptr, c->V, b.status, H->cap_nnzb);
   }
   return hipGetLastError();

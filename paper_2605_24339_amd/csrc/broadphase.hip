@@ -7,10 +7,11 @@
 // the cell array.  Every master triangle is counted into each cell its box
 // touches (atomic counts), the counts are scanned into cell starts, and a
 // second pass places the triangle ids (the counters return to zero, ready
-// for the next call).  A (prism, triangle) pair is reported only from the
-// cell that holds the low corner of the two boxes' intersection, so each
-// candidate appears once; each slave triangle's list is then sorted, which
-// makes the candidate lists deterministic.
+// for the next call).  The support prism of a slave triangle is covered by
+// thin slabs along its normal, whose boxes are far tighter than the box of
+// the whole (slanted) prism; candidates found in several cells or slabs are
+// merged in an LDS hash set and each list is written sorted, so candidate
+// lists are deterministic.
 #include "common.h"
 
 namespace gmcp {
@@ -67,10 +68,13 @@ __global__ __launch_bounds__(kThreads) void k_slave_box(const R *__restrict__ xs
       }
     }
   }
-  // environments are contiguous in triangle order: most waves hold one
+  // environments are contiguous in triangle order: most blocks hold one,
+  // which then takes a single set of atomics
+  __shared__ int benv[kThreads / kWave];
+  __shared__ float bbox[kThreads / kWave][6];
+  const int w = threadIdx.x / kWave;
   uint64_t vm = __ballot(ok);
-  if (!vm) return;
-  int e0 = __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave);
+  int e0 = vm ? __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave) : -1;
   bool uniform = __all(!ok || env == e0);
   if (uniform) {
     for (int d = 0; d < 3; ++d) {
@@ -82,16 +86,40 @@ __global__ __launch_bounds__(kThreads) void k_slave_box(const R *__restrict__ xs
       lo[d] = a;
       hi[d] = b;
     }
-    if (lane == 0) {
-      for (int d = 0; d < 3; ++d) {
-        atomicMin(&box[6 * e0 + d], float_to_ordered(lo[d]));
-        atomicMax(&box[6 * e0 + 3 + d], float_to_ordered(hi[d]));
-      }
-    }
   } else if (ok) {
     for (int d = 0; d < 3; ++d) {
       atomicMin(&box[6 * env + d], float_to_ordered(lo[d]));
       atomicMax(&box[6 * env + 3 + d], float_to_ordered(hi[d]));
+    }
+  }
+  if (lane == 0) {
+    benv[w] = uniform ? e0 : -2;  // -1: no triangle, -2: already flushed
+    for (int d = 0; d < 3; ++d) {
+      bbox[w][d] = lo[d];
+      bbox[w][3 + d] = hi[d];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int nw = blockDim.x / kWave;
+  bool same = true;
+  for (int v = 0; v < nw; ++v)
+    if (benv[v] != -1 && benv[v] != benv[0]) same = false;
+  for (int v = 0; v < nw; ++v) {
+    if (benv[v] < 0) continue;
+    if (same && v > 0) continue;
+    float a[6];
+    for (int d = 0; d < 6; ++d) a[d] = bbox[v][d];
+    if (same)
+      for (int u = 1; u < nw; ++u)
+        if (benv[u] >= 0)
+          for (int d = 0; d < 3; ++d) {
+            a[d] = fminf(a[d], bbox[u][d]);
+            a[3 + d] = fmaxf(a[3 + d], bbox[u][3 + d]);
+          }
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&box[6 * benv[v] + d], float_to_ordered(a[d]));
+      atomicMax(&box[6 * benv[v] + 3 + d], float_to_ordered(a[3 + d]));
     }
   }
 }
@@ -244,10 +272,13 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
       }
 }
 
-// prism box of slave triangle t: its vertices moved by +-eps_max along n_T
+constexpr int kQueryWaves = kThreads / kWave;
+constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS set)
+constexpr int kMaxSlabs = 64;
+
+// vertex box and unit normal of slave triangle t (float, grown outward)
 template <typename R>
-__device__ inline bool prism_box(const R *xs, const int32_t *ts, int64_t t, float eps, float lo[3], float hi[3],
-                                 float n_out[3]) {
+__device__ inline bool tri_frame(const R *xs, const int32_t *ts, int64_t t, float tlo[3], float thi[3], float n[3]) {
   R p[3][3];
   for (int j = 0; j < 3; ++j) {
     int64_t v = ts[3 * t + j];
@@ -261,24 +292,32 @@ __device__ inline bool prism_box(const R *xs, const int32_t *ts, int64_t t, floa
   R N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
   R len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
   if (!(len > R(0))) return false;
-  float n[3] = {(float)(N[0] / len), (float)(N[1] / len), (float)(N[2] / len)};
   for (int d = 0; d < 3; ++d) {
-    float off = fabsf(n[d]) * eps;
+    n[d] = (float)(N[d] / len);
     float a = fminf(fminf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
     float b = fmaxf(fmaxf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
-    lo[d] = a - off - grow(a) - eps * 1e-6f;
-    hi[d] = b + off + grow(b) + eps * 1e-6f;
-    n_out[d] = n[d];
+    tlo[d] = a - grow(a);
+    thi[d] = b + grow(b);
   }
   return true;
 }
 
-constexpr int kQueryWaves = kThreads / kWave;
-constexpr int kQuerySort = 256;  // lists up to this length are sorted in LDS
+// box of the prism slab {p + t n : p in T, t0 <= t <= t1}
+__device__ inline void slab_box(const float tlo[3], const float thi[3], const float n[3], float t0, float t1,
+                                float margin, float lo[3], float hi[3]) {
+  for (int d = 0; d < 3; ++d) {
+    float a = fminf(t0 * n[d], t1 * n[d]), b = fmaxf(t0 * n[d], t1 * n[d]);
+    lo[d] = tlo[d] + a - margin;
+    hi[d] = thi[d] + b + margin;
+  }
+}
 
-// One wave per slave triangle; the lanes split the cells of the prism box.
-// pass 0: count the candidates; pass 1: write them (wave prefix offsets)
-// and sort the triangle's list ascending.
+// One wave per slave triangle.  The support prism (|t| <= eps_max along n_T)
+// is covered by up to 64 slabs about one cell thick; the lanes split the
+// cells of all slab boxes, test each master triangle in them (box overlap
+// with the slab box, facing test with slack) and insert it into an LDS hash
+// set, which removes the duplicates of overlapping cells and slabs.
+// pass 0 counts the set; pass 1 writes it sorted ascending.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, const int32_t *__restrict__ ts,
                                                      const int32_t *__restrict__ s_order,
@@ -291,7 +330,8 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      const int32_t *__restrict__ cand_off, int32_t *__restrict__ cand,
                                                      int64_t cap_cand, int64_t cap_items, int64_t total_cells,
                                                      DevStatus *st, int pass) {
-  __shared__ int32_t lst[kQueryWaves][kQuerySort];
+  __shared__ int32_t set[kQueryWaves][kQuerySet];
+  __shared__ int32_t dense[kQueryWaves][kQuerySet];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kQueryWaves + w;
   if (i >= Ts) return;
@@ -314,76 +354,104 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   const int e = s_env[t];
   const GridEnv g = grid[e];
   const float eps = (float)env[e].dhat;
-  float lo[3], hi[3], n[3];
-  int c0[3] = {0, 0, 0}, c1[3] = {-1, 0, 0};
-  if (g.valid && prism_box(xs, ts, t, eps, lo, hi, n) && box_hits_grid(g, lo, hi)) {
-    for (int d = 0; d < 3; ++d) {
-      c0[d] = cell_coord(g, lo[d], d);
-      c1[d] = cell_coord(g, hi[d], d);
+  float tlo[3], thi[3], n[3];
+  const bool ok = g.valid && tri_frame(xs, ts, t, tlo, thi, n);
+  const int S = ok ? max(1, min(kMaxSlabs, (int)ceilf(2.0f * eps / g.h))) : 0;
+  const float dt = 2.0f * eps / (float)max(S, 1);
+  const float margin = eps * 1e-6f;
+  // lane s < S: cell range of slab s
+  int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1}, ncs = 0;
+  if (lane < S) {
+    float lo[3], hi[3];
+    slab_box(tlo, thi, n, -eps + lane * dt, -eps + (lane + 1) * dt, margin, lo, hi);
+    if (box_hits_grid(g, lo, hi)) {
+      for (int d = 0; d < 3; ++d) {
+        c0[d] = cell_coord(g, lo[d], d);
+        c1[d] = cell_coord(g, hi[d], d);
+      }
+      ncs = (c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
     }
   }
-  const int nxr = c1[0] - c0[0] + 1, nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
-  const int ncell = nxr > 0 ? nxr * nyr * nzr : 0;
-  const int64_t base = env[e].cell0;
-  // walk this lane's cells; emit(M) for each candidate reported here
-  auto walk = [&](auto &&emit) {
-    for (int ci = lane; ci < ncell; ci += kWave) {
-      int x = c0[0] + ci % nxr, y = c0[1] + (ci / nxr) % nyr, z = c0[2] + ci / (nxr * nyr);
-      int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
-      int s0 = cell_start[cell], s1 = cell_start[cell + 1];
-      for (int j = s0; j < s1; ++j) {
-        int M = items[j];
-        float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1], nm = mbox[3 * (int64_t)M + 2];
-        if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
-        // report from the cell holding the low corner of the overlap only
-        if (cell_coord(g, fmaxf(a.x, lo[0]), 0) != x || cell_coord(g, fmaxf(a.y, lo[1]), 1) != y ||
-            cell_coord(g, fmaxf(a.z, lo[2]), 2) != z)
-          continue;
-        // facing test with slack: the narrow phase takes the exact decision
-        if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
-        emit(M);
-      }
-    }
-  };
-  int cnt = 0;
-  walk([&](int) { ++cnt; });
-  int incl = cnt;
+  int incl = ncs;
   for (int d = 1; d < kWave; d <<= 1) {
     int v = __shfl_up(incl, d, kWave);
     if (lane >= d) incl += v;
   }
-  const int total = __shfl(incl, kWave - 1, kWave);
+  const int work = __shfl(incl, kWave - 1, kWave);
+  for (int k = lane; k < kQuerySet; k += kWave) set[w][k] = -1;
+  wave_sync();
+  const int64_t base = env[e].cell0;
+  int fresh = 0;
+  bool full = false;
+  for (int w0 = 0; w0 < work; w0 += kWave) {
+    const int wi = w0 + lane;
+    int s = 0;
+    for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
+    s = min(s, kWave - 1);
+    const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
+    const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
+    const int sstart = __shfl(incl - ncs, s, kWave);
+    if (wi >= work) continue;
+    const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
+    const int li = wi - sstart;
+    const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+    float lo[3], hi[3];
+    slab_box(tlo, thi, n, -eps + s * dt, -eps + (s + 1) * dt, margin, lo, hi);
+    const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
+    const int j1 = cell_start[cell + 1];
+    for (int j = cell_start[cell]; j < j1; ++j) {
+      int M = items[j];
+      float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1];
+      if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
+      float4 nm = mbox[3 * (int64_t)M + 2];
+      // facing test with slack: the narrow phase takes the exact decision
+      if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
+      uint32_t h = ((uint32_t)M * 2654435761u) & (kQuerySet - 1);
+      int probe = 0;
+      for (; probe < kQuerySet; ++probe) {
+        int prev = atomicCAS(&set[w][h], -1, M);
+        if (prev == -1) {
+          ++fresh;
+          break;
+        }
+        if (prev == M) break;
+        h = (h + 1) & (kQuerySet - 1);
+      }
+      if (probe == kQuerySet) full = true;
+    }
+  }
+  if (__any(full)) {
+    if (lane == 0) {
+      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+      atomicMin(&st->index, (unsigned long long)t);
+      if (pass == 0) cand_cnt[t] = 0;
+    }
+    return;
+  }
+  int total = fresh;
+  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, kWave);
   if (pass == 0) {
     if (lane == 0) cand_cnt[t] = total;
     return;
   }
-  int pos = incl - cnt;
-  int32_t *l = cand + out;
-  if (total <= kQuerySort) {
-    // gather in LDS, then rank sort (ids are unique) straight into place
-    walk([&](int M) { lst[w][pos++] = M; });
-    wave_sync();
-    for (int k = lane; k < total; k += kWave) {
-      int v = lst[w][k], r = 0;
-      for (int m = 0; m < total; ++m) r += lst[w][m] < v;
-      l[r] = v;
-    }
-    return;
-  }
-  walk([&](int M) { l[pos++] = M; });
-  __threadfence_block();
   wave_sync();
-  if (lane == 0) {
-    for (int a = 1; a < total; ++a) {
-      int v = l[a], b = a - 1;
-      while (b >= 0 && l[b] > v) {
-        l[b + 1] = l[b];
-        --b;
-      }
-      l[b + 1] = v;
-    }
+  int nu = 0;
+  for (int k0 = 0; k0 < kQuerySet; k0 += kWave) {
+    int k = k0 + lane;
+    bool used = set[w][k] >= 0;
+    uint64_t m = __ballot(used);
+    if (used) dense[w][nu + __popcll(m & ((1ull << lane) - 1))] = set[w][k];
+    nu += __popcll(m);
+  }
+  wave_sync();
+  int32_t *l = cand + out;
+  for (int k = lane; k < nu; k += kWave) {  // rank sort: ids are unique
+    int v = dense[w][k], r = 0;
+    for (int m = 0; m < nu; ++m) r += dense[w][m] < v;
+    l[r] = v;
   }
 }
+
 
 __global__ void k_cand_total(const int32_t *cand_off, int64_t Ts, DevStatus *st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
@@ -433,21 +501,23 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   e = build_grid<R>(c, xs, xm, nullptr, nullptr, false);
   prof_mark(c, ST_GRID, 1);
   if (e != hipSuccess) return e;
-  prof_mark(c, ST_QUERY, 0);
-  if (c->Ts) {
-    hipLaunchKernelGGL(k_query<R>, dim3((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
-                       b.grid, c->Ts, b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand,
-                       c->caps.candidates, c->caps.grid_items, c->total_cells, b.status, 0);
-  }
+  const dim3 qgrid((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves));
+  prof_mark(c, ST_QUERY_COUNT, 0);
+  if (c->Ts)
+    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
+                       c->caps.grid_items, c->total_cells, b.status, 0);
+  prof_mark(c, ST_QUERY_COUNT, 1);
   e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
   if (e != hipSuccess) return e;
   e = scan_exclusive(c, b.cand_cnt, b.cand_off, c->Ts + 1);
   if (e != hipSuccess) return e;
+  prof_mark(c, ST_QUERY_FILL, 0);
   if (c->Ts)
-    hipLaunchKernelGGL(k_query<R>, dim3((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
-                       b.grid, c->Ts, b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand,
-                       c->caps.candidates, c->caps.grid_items, c->total_cells, b.status, 1);
-  prof_mark(c, ST_QUERY, 1);
+    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
+                       c->caps.grid_items, c->total_cells, b.status, 1);
+  prof_mark(c, ST_QUERY_FILL, 1);
   hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
   return hipGetLastError();
 }

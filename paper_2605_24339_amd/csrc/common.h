@@ -89,6 +89,7 @@ struct Buffers {
   void *pair;                                   // Pair<R>[cap.pairs]
   double *tile_E;
   int32_t *mp_cnt, *mp_off, *mp_list;
+  long long *mp_key;                            // [pairs] (slave triangle << 32 | pair)
   int32_t *row_cnt;                             // [V+1]
   // step bound
   GridEnv *sgrid;
@@ -105,16 +106,19 @@ struct Buffers {
 };
 
 // kernel stages timed by the optional event profiler (gmcp_profile)
+// (stages marked "kernel" bracket exactly one kernel launch)
 enum Stage {
   ST_GRID = 0,     // grid build (boxes, counts, scan, placement)
-  ST_QUERY,        // candidate query (count + fill)
-  ST_NARROW,       // narrow phase + barrier + per-triangle / pair sums
-  ST_BUCKET,       // pairs bucketed by master triangle
-  ST_GRAD,         // gradient rows
-  ST_ROWS,         // BSR rows (count + fill)
-  ST_CCD_LINEAR,   // linearised step bound
+  ST_QUERY_COUNT,  // kernel k_query, counting pass
+  ST_QUERY_FILL,   // kernel k_query, writing pass
+  ST_NARROW,       // kernel k_narrow: narrow phase + barrier + sums
+  ST_BUCKET,       // pairs bucketed by master triangle (count, scan, place, sort)
+  ST_GRAD,         // kernel k_grad: gradient rows
+  ST_ROWS_COUNT,   // kernel k_rows, counting pass
+  ST_ROWS_FILL,    // kernel k_rows, writing pass
+  ST_CCD_LINEAR,   // kernel k_ccd_linear
   ST_CCD_GRID,     // swept grid build
-  ST_CCD_ACCD,     // additive CCD over swept pairs
+  ST_CCD_ACCD,     // kernel k_ccd_accd
   ST_COUNT
 };
 

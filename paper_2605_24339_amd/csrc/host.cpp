@@ -198,6 +198,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.mp_cnt = p.take<int32_t>(s.Tm + 1);
   t.mp_off = p.take<int32_t>(s.Tm + 1);
   t.mp_list = p.take<int32_t>(cp.pairs);
+  t.mp_key = p.take<long long>(cp.pairs);
   t.row_cnt = p.take<int32_t>(s.V + 1);
   t.sgrid = p.take<GridEnv>(s.n_env);
   t.sbox = p.take<uint32_t>(6 * s.n_env);
@@ -599,9 +600,9 @@ int gmcp_status(gmcp_ctx *c, gmcp_status_info *info) {
   return GMCP_OK;
 }
 
-static const char *kStageNames[gmcp::ST_COUNT] = {"grid_build", "cand_query", "narrow",  "pair_bucket",
-                                                   "grad_rows",  "bsr_rows",   "ccd_linear", "ccd_grid",
-                                                   "ccd_accd"};
+static const char *kStageNames[gmcp::ST_COUNT] = {
+    "grid_build", "query_count", "query_fill", "narrow",     "pair_bucket", "grad_rows",
+    "rows_count", "rows_fill",   "ccd_linear", "ccd_grid",   "ccd_accd"};
 
 int gmcp_profile(gmcp_ctx *c, int enable) {
   if (!c) return GMCP_E_ARG;

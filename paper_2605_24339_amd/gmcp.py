@@ -266,6 +266,24 @@ class Context:
         alpha = self.ccd_step(xs, xm, dxs, dxm, check=check)
         return A, alpha
 
+    def capture(self, xs, xm, dxs, dxm=None) -> "torch.cuda.CUDAGraph":
+        """Capture one full step into a HIP graph.  ``graph.replay()`` re-runs
+        it on whatever the same input tensors hold; outputs land in this
+        context's energy / grad / BSR / alpha buffers.  Capacities are settled
+        by a checked step first (no host synchronisation inside the graph)."""
+        self.step(xs, xm, dxs, dxm, check=True)
+        torch.cuda.synchronize(self.device)
+        side = torch.cuda.Stream(self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.step(xs, xm, dxs, dxm)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(xs, xm, dxs, dxm)
+        self._bind()
+        return g
+
     def hvp(self, vx, vd=None):
         vx = self._x(vx, self.V, "v_x")
         vd = self._vec(vd, self.Ns, "v_d")

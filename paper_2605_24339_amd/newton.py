@@ -1,0 +1,118 @@
+"""Implicit Euler step of a linear-elastic tet body in contact through GMCP:
+Newton on the incremental potential with a CCD-capped backtracking line
+search (the IPC solver structure the paper's contact model plugs into).
+
+    E(x) = 1/2 |x - x_tilde|^2_M / dt^2 + 1/2 (x - X)^T K (x - X) + Psi_GMCP(x)
+
+The tactile surface (slave) is a boundary of the body; the indenter
+(master) is prescribed for the step.  Dirichlet vertices move to their
+prescribed positions at the start of the step and stay there.
+
+Every step runs on the GPU library: GMCP broad phase / assembly / step
+bound (gmcp.h), FEM energy / gradient and the PCG solve (gmcp_fem.h); this
+module holds only the control flow and the bookkeeping of counts.
+Convergence: r = |grad E|_inf / F_ref <= tol with F_ref = E_young h^2
+(h the element size), which does not depend on the starting point.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+
+@dataclass
+class StepStats:
+    newton_iters: int = 0
+    assemblies: int = 0        # full assemblies (energy, gradient, Hessian)
+    energy_evals: int = 0      # energy-only evaluations in the line search
+    cg_iters: int = 0
+    residual: float = float("inf")
+    start_alpha: float = 1.0
+    converged: bool = False
+    alphas: list = field(default_factory=list)
+
+
+class ImplicitSolver:
+    """Newton solver for one body (slave) against a prescribed indenter."""
+
+    def __init__(self, fem, contact, f_ref: float, tol: float = 1e-6, max_newton: int = 60,
+                 armijo: float = 1e-4, cg_rtol: float = 1e-3, cg_max: int = 20000):
+        self.fem = fem
+        self.contact = contact      # gmcp Context, float64, kinematic master, slave = body vertices
+        self.f_ref = f_ref
+        self.tol = tol
+        self.max_newton = max_newton
+        self.armijo = armijo
+        self.cg_rtol = cg_rtol
+        self.cg_max = cg_max
+
+    # -------------------------------------------------------------- pieces
+    def energy(self, x, x_tilde, xm) -> float:
+        e_fem, _ = self.fem.energy(x, x_tilde, grad=False)
+        self.contact.broadphase(x, xm)
+        A = self.contact.assemble(x, xm, grad=False, hessian=False)
+        return float(e_fem.item() + A.energy.sum().item())
+
+    def gradient_system(self, x, x_tilde, xm):
+        e_fem, g = self.fem.energy(x, x_tilde, grad=True)
+        self.contact.broadphase(x, xm)
+        A = self.contact.assemble(x, xm, grad=True, hessian=True)
+        g = g + A.grad
+        g[self.fem.fixed] = 0.0
+        E = float(e_fem.item() + A.energy.sum().item())
+        return E, g, A.hessian
+
+    def feasible_start(self, x_t, y, xm) -> tuple:
+        """x_t + alpha (y - x_t), alpha from the contact step bound (free
+        vertices; Dirichlet vertices are set afterwards)."""
+        d = (y - x_t).contiguous()
+        self.contact.broadphase(x_t, xm)
+        self.contact.assemble(x_t, xm, grad=False, hessian=False)
+        a = float(self.contact.ccd_step(x_t, xm, d).min().item())
+        return x_t + a * d, a
+
+    # ---------------------------------------------------------------- step
+    def solve_step(self, x_t, v_t, xm, fixed_pos, x_start=None) -> tuple:
+        """One implicit step.  fixed_pos: positions of the Dirichlet vertices
+        at the end of the step ([V, 3] tensor, only fixed rows are read).
+        x_start: optional starting guess (the plain start is x_t + dt v_t);
+        it passes the same feasibility filter as the plain start."""
+        st = StepStats()
+        fx = self.fem.fixed
+        x_tilde = x_t + self.fem.dt * v_t
+        x_tilde[fx] = fixed_pos[fx]
+        y = x_tilde.clone() if x_start is None else x_start.clone()
+        y[fx] = fixed_pos[fx]
+        x, st.start_alpha = self.feasible_start(x_t, y, xm)
+        x[fx] = fixed_pos[fx]
+        x = x.contiguous()
+        for it in range(self.max_newton):
+            E, g, H = self.gradient_system(x, x_tilde, xm)
+            st.assemblies += 1
+            st.residual = float(g.abs().max().item()) / self.f_ref
+            if st.residual <= self.tol:
+                st.converged = True
+                break
+            st.newton_iters += 1
+            gn = float(g.norm().item())
+            rtol = min(self.cg_rtol, max(1e-10, (st.residual / 10.0)))
+            d, cg_it, _ = self.fem.solve(H, (-g).contiguous(), rtol=rtol, max_iter=self.cg_max)
+            st.cg_iters += cg_it
+            slope = float((g * d).sum().item())
+            if not slope < 0.0:      # not a descent direction: fall back to steepest descent
+                d = -g / max(gn, 1e-300)
+                slope = float((g * d).sum().item())
+            self.contact.broadphase(x, xm)
+            a = float(self.contact.ccd_step(x, xm, d.contiguous()).min().item())
+            a = min(1.0, a)
+            while True:
+                xn = (x + a * d).contiguous()
+                En = self.energy(xn, x_tilde, xm)
+                st.energy_evals += 1
+                if En <= E + self.armijo * a * slope or a < 1e-14:
+                    break
+                a *= 0.5
+            st.alphas.append(a)
+            x = xn
+        return x, st

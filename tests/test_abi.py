@@ -10,10 +10,18 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "gmcp.h")).read()
+def _declared(header="gmcp.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(gmcp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_fem_header_symbols_exported():
+    from paper_2605_24339_amd import _native
+    lib = _native.lib()
+    names = _declared("gmcp_fem.h")
+    assert set(names) == set(_native.FEM_EXPORTS)
+    assert not [n for n in names if not hasattr(lib, n)]
 
 
 def test_header_declares_the_path_entry_points():
