@@ -48,6 +48,9 @@ EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_strea
            "gmcp_ccd_step", "gmcp_hvp", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
            "gmcp_strerror", "gmcp_profile", "gmcp_profile_stages", "gmcp_profile_stage_name",
            "gmcp_profile_read", "gmcp_rule"]
+# include/gmcp_mlp.h
+MLP_EXPORTS = ["gmcp_mlp_param_count", "gmcp_mlp_work_bytes", "gmcp_mlp_forward", "gmcp_mlp_backward",
+               "gmcp_mlp_mse", "gmcp_mlp_adam", "gmcp_gemm_bf16"]
 # include/gmcp_fem.h
 FEM_EXPORTS = ["gmcp_fem_workspace_size", "gmcp_fem_create", "gmcp_fem_destroy", "gmcp_fem_set_stream",
                "gmcp_fem_nnzb", "gmcp_fem_stiffness", "gmcp_fem_energy", "gmcp_fem_apply", "gmcp_fem_solve"]

@@ -31,6 +31,7 @@ class StepStats:
     start_alpha: float = 1.0
     converged: bool = False
     alphas: list = field(default_factory=list)
+    x0: object = None          # the (filtered) starting point of the Newton iteration
 
 
 class ImplicitSolver:
@@ -87,6 +88,7 @@ class ImplicitSolver:
         x, st.start_alpha = self.feasible_start(x_t, y, xm)
         x[fx] = fixed_pos[fx]
         x = x.contiguous()
+        st.x0 = x.clone()
         for it in range(self.max_newton):
             E, g, H = self.gradient_system(x, x_tilde, xm)
             st.assemblies += 1

@@ -16,6 +16,17 @@ def _declared(header="gmcp.h"):
     return sorted(set(re.findall(r"\b(gmcp_[a-z_0-9]+)\s*\(", src)))
 
 
+def test_mlp_header_symbols_exported_and_param_count():
+    from oracle import mlp as omlp
+    from paper_2605_24339_amd import _native
+    lib = _native.lib()
+    names = _declared("gmcp_mlp.h")
+    assert set(names) == set(_native.MLP_EXPORTS)
+    assert not [n for n in names if not hasattr(lib, n)]
+    lib.gmcp_mlp_param_count.restype = C.c_int64
+    assert lib.gmcp_mlp_param_count() == omlp.N_PARAMS
+
+
 def test_fem_header_symbols_exported():
     from paper_2605_24339_amd import _native
     lib = _native.lib()
