@@ -29,9 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = "GMCP samples/s (E+grad+Hess) & CCD pairs/s, % HBM peak; Newton iters learned vs plain"
 HBM_PEAK_GBS = 8000.0
 # kernels that one profiled stage brackets exactly (candidates for the roofline)
-KERNEL_STAGES = {"query_count": "k_query", "query_fill": "k_query", "narrow": "k_narrow",
-                 "grad_rows": "k_grad", "rows_count": "k_rows", "rows_fill": "k_rows",
-                 "ccd_linear": "k_ccd_linear", "ccd_accd": "k_ccd_accd"}
+KERNEL_STAGES = {"query_count": "k_query<float, 0>", "query_fill": "k_query<float, 1>", "narrow": "k_narrow<float>",
+                 "rows_count": "k_rows<float, 0>", "rows_fill": "k_rows<float, 1>",
+                 "ccd_linear": "k_ccd_linear<float>", "ccd_accd": "k_ccd_accd<float>"}
 
 
 def src_hash() -> str:
@@ -60,8 +60,6 @@ def kernel_bytes(stage: str, sz: dict) -> int:
     if stage in ("rows_count", "rows_fill"):
         out = 4 * V if stage == "rows_count" else 40 * nnzb + 4 * (V + 1)
         return 48 * Ts + 84 * npair + 4 * (V + 1) + 12 * (Ts + Tm) + 4 * (Tm + 1) + out
-    if stage == "grad_rows":
-        return 48 * Ts + 84 * npair + 4 * (V + 1) + 12 * (Ts + Tm) + 4 * (Tm + 1) + 12 * V
     if stage == "ccd_linear":
         return 48 * na + 12 * Ts + 24 * Vs + 12 * Tm + 12 * Vm
     if stage == "ccd_accd":
@@ -81,7 +79,7 @@ def time_replays(g, steps: int, stream) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def measure(name, envs, batch, steps, warmup, dev):
+def measure(name, envs, batch, steps, warmup, dev, tune_cache=None):
     """Autotune, capture, time; per-kernel stage times; roofline of the
     dominant kernel."""
     import numpy as np
@@ -98,7 +96,7 @@ def measure(name, envs, batch, steps, warmup, dev):
                        [w.dhat for w in envs], [w.delta_T for w in envs], cells, dtype=torch.float32,
                        device=dev)
 
-    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=None)
+    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache)
     ctx = make(cells)
     ctx.build_samples(xs)
     g = ctx.capture(xs, xm, dxs, dxm)
@@ -140,6 +138,104 @@ def measure(name, envs, batch, steps, warmup, dev):
                 cells=cells[:4])
 
 
+def _event_ms(fn, reps: int) -> float:
+    import torch
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_autograd(w, dev, reps: int = 10) -> dict:
+    """Differentiable GMCP on the same workload: a pressure-map loss, its
+    forward (broad phase + assembly), backward (force kernel) and double
+    backward (Hessian-vector product) per iteration."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24339_amd import Context
+    from paper_2605_24339_amd.autograd import pressure_map
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    ctx = Context.single(w.ts, w.tm, w.xs.shape[0], w.xm.shape[0], rule_n=w.rule_n, kappa=w.kappa, dhat=w.dhat,
+                         dtype=torch.float32, device=dev)
+    xs, xm = t(w.xs).requires_grad_(True), t(w.xm).requires_grad_(True)
+    wts = ctx.build_samples(xs.detach(), weights=True)
+    target = torch.zeros(ctx.Ns, dtype=torch.float32, device=dev)
+    delta = torch.zeros(ctx.Ns, dtype=torch.float32, device=dev, requires_grad=True)
+
+    def it():
+        p = pressure_map(ctx, xs, xm, delta, wts)
+        L = 0.5 * ((p - target) ** 2).sum()
+        L.backward()
+
+    ms = _event_ms(it, reps)
+    return {"workload": w.name, "ms_per_iteration": ms, "samples_per_s": ctx.Ns / (ms * 1e-3),
+            "what": "pressure-map loss: forward, force backward, HVP double backward, autograd bookkeeping"}
+
+
+def measure_mlp(dev, batch: int = 65536, reps: int = 20) -> dict:
+    """Warm-start MLP: one training step (forward, MSE, backward, Adam) and
+    the bf16 matrix-core GEMM of a hidden layer."""
+    import torch
+
+    from paper_2605_24339_amd.mlp import MLP, PAD, gemm_bf16
+    from paper_2605_24339_amd.warmstart import init_params
+    g = torch.Generator(device="cpu").manual_seed(0)
+    X = torch.randn(batch, PAD, generator=g).to(dev)
+    T = torch.randn(batch, PAD, generator=g).to(dev)
+    net = MLP(init_params(0, dev))
+    act = torch.empty(batch, 6 * 128, dtype=torch.float32, device=dev)
+
+    def step():
+        y, a = net.forward(X, act)
+        _, dy = net.mse(y, T)
+        net.adam(net.backward(X, a, dy))
+
+    ms = _event_ms(step, reps)
+    flops = 3 * 2 * batch * (PAD * 128 + 2 * 128 * 128 + 128 * PAD)
+    Mg, Ng, Kg = 1 << 18, 128, 128
+    A = torch.randn(Mg, Kg, generator=g).to(dev)
+    B = torch.randn(Kg, Ng, generator=g).to(dev)
+    gms = _event_ms(lambda: gemm_bf16(A, B), reps)
+    tf = 2 * Mg * Ng * Kg / (gms * 1e-3) / 1e12
+    return {"train_rows_per_s": batch / (ms * 1e-3), "train_step_ms": ms, "batch": batch,
+            "train_tflops": flops / (ms * 1e-3) / 1e12,
+            "gemm": {"M": Mg, "N": Ng, "K": Kg, "ms": gms, "tflops": tf, "mfma_peak_tflops": 2500.0,
+                     "gbs": 4 * (Mg * Kg + Kg * Ng + Mg * Ng) / (gms * 1e-3) / 1e9, "hbm_peak_gbs": HBM_PEAK_GBS,
+                     "note": "float32 operands converted to bf16 on load, float32 out: HBM-bound at K = 128"}}
+
+
+def measure_dualmesh(dev, reps: int = 50) -> dict:
+    """Dual-mesh mapper: the one-off embedding and the per-frame update of
+    655362 visual vertices on a 20480-triangle surface (float32 update)."""
+    import numpy as np
+    import torch
+
+    from gen import workloads
+    from paper_2605_24339_amd.dualmesh import DualMesh
+    P, V, F = workloads.dual_mesh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dm = DualMesh(P, V, F, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    embed_s = time.perf_counter() - t0
+    Vd = torch.tensor(workloads.smooth_deformation(V), dtype=torch.float32, device=dev)
+    out = torch.empty(P.shape[0], 3, dtype=torch.float32, device=dev)
+    ms = _event_ms(lambda: dm.update(Vd, out), reps)
+    N, nV, nT = P.shape[0], V.shape[0], F.shape[0]
+    byts = 32 * N + 12 * nV + 12 * nT       # tri, bary, delta, out per vertex; surface read once
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"visual_vertices": N, "sim_triangles": nT, "embed_s": embed_s, "update_ms": ms,
+            "update_vertices_per_s": N / (ms * 1e-3), "update_bytes": byts, "update_gbs": gbs,
+            "update_frac_hbm": gbs / HBM_PEAK_GBS}
+
+
 def cpu_baseline(w, budget_s: float) -> dict:
     import oracle
     from gen import workloads
@@ -160,6 +256,49 @@ def cpu_baseline(w, budget_s: float) -> dict:
                       f"{P.Ns} samples of the same workload, FP64, OpenMP, {dt:.1f} s"}
 
 
+def _counter_means(path: str, counter: str) -> dict:
+    """Mean value of one rocprofv3 --pmc counter per kernel name (CSV)."""
+    import csv
+    import re
+    acc = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+            name = re.sub(r"\(.*", "", re.sub(r"^void ", "", name)).split("::")[-1]
+            a = acc.setdefault(name, [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, stage, kernel):
+    """HBM traffic of one kernel from two counter runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+    reads for a plain device copy of known size; stored in
+    profiles/traffic.json under the current source hash."""
+    copy_bytes = 4 * 64 * 1024 * 1024
+    cf = _counter_means(copy_fetch_csv, "FETCH_SIZE")
+    cw = _counter_means(copy_write_csv, "WRITE_SIZE")
+    ck = max(cf, key=cf.get)                    # the copy kernel is the largest dispatch
+    f_scale = copy_bytes / (cf[ck] * 1024.0)
+    w_scale = copy_bytes / (cw[ck] * 1024.0)
+    f = _counter_means(fetch_csv, "FETCH_SIZE")[kernel] * 1024.0 * f_scale
+    w = _counter_means(write_csv, "WRITE_SIZE")[kernel] * 1024.0 * w_scale
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    known = {}
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            known = json.load(fh)
+    known[f"{workload}/{stage}"] = {"kernel": kernel, "src_hash": src_hash(), "fetch_bytes": f, "write_bytes": w,
+                                    "bytes_per_launch": f + w, "copy_kernel": ck,
+                                    "fetch_scale": f_scale, "write_scale": w_scale}
+    with open(tf, "w") as fh:
+        json.dump(known, fh, indent=1)
+    print(json.dumps(known[f"{workload}/{stage}"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,9 +308,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the autograd and MLP measurements")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="measure only the 256-environment batch (for per-workload kernel profiles)")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON file of autotuned cell sizes to reuse (default: tune every run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=7, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "WORKLOAD", "STAGE",
+                             "KERNEL"),
+                    help="CPU only: record the kernel's HBM traffic from rocprofv3 --pmc CSVs")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1",
@@ -193,8 +345,15 @@ def main():
     from gen import workloads
 
     dev = torch.device("cuda", 0)
+    if args.batched_only:
+        B = workloads.batched()
+        bt = measure("batched_256", B.envs, B, args.steps, args.warmup, dev, args.autotune_cache)
+        print(json.dumps({"workload": "batched_256_envs", "samples": bt["samples"], "value": bt["value"],
+                          "unit": "samples/s", "ms_per_step": bt["ms"], "stage_ms": bt["stages"],
+                          "roofline": bt["roofline"], "autotune_ms": bt["autotune"]}))
+        return
     w = workloads.large_indent(indenter=args.indenter)
-    single = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev)
+    single = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev, args.autotune_cache)
     out = {
         "metric": METRIC,
         "value": single["value"],
@@ -221,11 +380,15 @@ def main():
     }
     if not args.no_batched:
         B = workloads.batched()
-        bt = measure("batched_256", B.envs, B, max(5, args.steps // 10), 2, dev)
+        bt = measure("batched_256", B.envs, B, max(5, args.steps // 10), 2, dev, args.autotune_cache)
         out["batched"] = {"workload": "batched_256_envs", "samples": bt["samples"], "value": bt["value"],
                           "unit": "samples/s", "ms_per_step": bt["ms"], "stage_ms": bt["stages"],
                           "ccd_pairs_per_s": (bt["sizes"]["n_active"] + bt["n_swept"]) / (bt["ccd_ms"] * 1e-3),
                           "roofline": bt["roofline"], "autotune_ms": bt["autotune"]}
+    if not args.no_extras:
+        out["autograd"] = measure_autograd(w, dev)
+        out["mlp"] = measure_mlp(dev)
+        out["dualmesh"] = measure_dualmesh(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

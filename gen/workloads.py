@@ -215,3 +215,27 @@ def to_problem(w: Workload):
     """Oracle problem built from a workload (for tests and the CPU baseline)."""
     from oracle import Problem
     return Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, None, w.xs_rest)
+
+
+def dual_mesh(seed: int = 7, sim_freq: int = 32, vis_freq: int = 256, radius: float = 5e-3):
+    """A visual mesh riding on a coarser simulation surface: the simulation
+    surface is a geodesic sphere of frequency ``sim_freq`` (20 f^2
+    triangles; 20480 at f = 32), the visual vertices those of a geodesic
+    sphere of frequency ``vis_freq`` (10 f^2 + 2; 655362 at f = 256) with a
+    uniform radial perturbation of +-0.5 % (surface detail), randomly
+    rotated so the two meshes do not share vertices.  Returns
+    (P [N][3], V [nV][3], F [nT][3] int32), float64."""
+    rng = np.random.default_rng(seed)
+    V, F = _geo(sim_freq)
+    V = V * radius
+    P, _ = _geo(vis_freq)
+    P = (P @ meshes.random_rotation(rng).T) * radius * (1 + rng.uniform(-5e-3, 5e-3, size=(P.shape[0], 1)))
+    return P, V, F
+
+
+def smooth_deformation(x: np.ndarray, amp: float = 0.1, scale: float = 5e-3) -> np.ndarray:
+    """A smooth non-affine deformation of points x (used to move the
+    simulation surface in dual-mesh tests)."""
+    y = x / scale
+    d = np.stack([np.sin(2 * y[:, 1]), np.cos(1.5 * y[:, 2]) * y[:, 0], 0.5 * y[:, 0] * y[:, 1]], axis=1)
+    return x + amp * scale * d

@@ -55,6 +55,9 @@ MLP_EXPORTS = ["gmcp_mlp_param_count", "gmcp_mlp_work_bytes", "gmcp_mlp_forward"
 FEM_EXPORTS = ["gmcp_fem_workspace_size", "gmcp_fem_create", "gmcp_fem_destroy", "gmcp_fem_set_stream",
                "gmcp_fem_nnzb", "gmcp_fem_stiffness", "gmcp_fem_energy", "gmcp_fem_apply", "gmcp_fem_solve"]
 
+# include/gmcp_dualmesh.h
+DUALMESH_EXPORTS = ["gmcp_dualmesh_embed", "gmcp_dualmesh_update"]
+
 _lib = None
 
 

@@ -79,7 +79,7 @@ def tune(make_ctx, envs, inputs, scales=SCALES, reps: int = 20, cache: str | Non
         torch.cuda.empty_cache()
     best = float(min(table, key=table.get))
     if cache:
-        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         known = {}
         if os.path.exists(cache):
             with open(cache) as fh:

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgmcp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["host.cpp", "util.hip", "broadphase.hip", "assemble.hip", "ccd.hip", "fem.hip", "mlp.hip"]
+SOURCES = ["host.cpp", "util.hip", "broadphase.hip", "assemble.hip", "ccd.hip", "fem.hip", "mlp.hip", "dualmesh.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -13,8 +13,8 @@
 // absolute sample positions, so float32 keeps the small gaps accurate.
 //
 // Reductions are deterministic: per triangle and per pair in lane order,
-// per BSR row by exact 64-bit fixed-point sums in an LDS table of the row's
-// columns, per master triangle over pairs sorted by slave triangle.
+// per BSR row by per-column sums in a canonical contribution order, per
+// master triangle over pairs sorted by slave triangle.
 #include "common.h"
 
 namespace gmcp {
@@ -417,23 +417,28 @@ __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full)
 }
 
 // One wave per BSR row.  pass 0 counts the distinct columns, pass 1 writes
-// them.  Every contribution (column, coef, slave triangle whose normal n_T
-// it carries; block = coef n_T n_T^T) is streamed into an LDS hash table of
-// the row's distinct columns.  Pass 1 accumulates the six distinct entries
-// of each (symmetric) block as 64-bit fixed point scaled by a power of two
-// chosen from the row's sum of |coef|: integer addition is exact, so the sum
-// does not depend on the order of the atomics and the result is
-// deterministic.  Columns are then ranked in LDS and written ascending.
-template <typename R>
-__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pass, int slots) {
+// them, pass 2 only computes the gradient row.  The row's contributions
+// (column, coef, slave triangle whose normal n_T it carries; block =
+// coef n_T n_T^T) are enumerated in a canonical order - source by source,
+// sources in adjacency order - and their columns inserted into an LDS hash
+// set.  In pass 1 the contributions are also kept in LDS (rows longer than
+// kRowEnt re-walk their sources instead); each lane then owns one distinct
+// column and sums its contributions in the canonical order, so the float
+// sums are the same on every run.  Columns are ranked and written ascending.
+constexpr int kRowEnt = 512;
+
+template <typename R, int PASS>
+__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots) {
+  constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nw = blockDim.x / kWave;
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  long long *acc = reinterpret_cast<long long *>(smem) + (size_t)w * slots * 6;  // pass 1 only
-  int32_t *key = reinterpret_cast<int32_t *>(smem + (pass ? (size_t)nw * slots * 48 : 0)) +
-                 (size_t)w * 2 * slots;
+  const size_t per_wave = (size_t)slots * 8 + (pass == 1 ? (size_t)kRowEnt * (8 + sizeof(R)) : 0);
+  int32_t *key = reinterpret_cast<int32_t *>(smem + (size_t)w * per_wave);
   int32_t *dense = key + slots;
-  const int64_t row = (int64_t)blockIdx.x * nw + w;
+  int32_t *ecol = dense + slots;
+  int32_t *etri = ecol + kRowEnt;
+  R *ecoef = reinterpret_cast<R *>(etri + kRowEnt);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   if (row >= a.V) return;
   if ((int64_t)a.st_r->n_pairs > a.cap_pairs) {
     if (pass == 0 && lane == 0) a.row_cnt[row] = 0;
@@ -444,19 +449,42 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
   const int64_t vid = slave ? row : row - a.Vs;
   const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
   const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
-  // number of contributions of the row: rows without contact stop here, and
-  // the table used is sized to the row (twice its contributions, pow2)
-  int n_ent = 0;
-  for (int src = sb + lane; src < se; src += kWave) {
-    int ent = slave ? a.s_vt[src] : a.m_vt[src];
-    int t = ent >> 2;
+
+  // contributions of one source (incident triangle), in canonical order
+  auto src_count = [&](int src) -> int {
+    int t = (slave ? a.s_vt[src] : a.m_vt[src]) >> 2;
     if (slave) {
       int np = a.tri_npair[t];
-      n_ent += np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
-    } else {
-      n_ent += 6 * (a.mp_off[t + 1] - a.mp_off[t]);
+      return np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
     }
-  }
+    return 6 * (a.mp_off[t + 1] - a.mp_off[t]);
+  };
+  auto visit_src = [&](int src, auto &&visit) {
+    int ent = slave ? a.s_vt[src] : a.m_vt[src];
+    int t = ent >> 2, corner = ent & 3;
+    if (slave) {
+      if (a.tri_npair[t] == 0) return;
+      const R *S = a.tri_sum + 9 * (int64_t)t;
+      for (int b = 0; b < 3; ++b) visit(a.ts[3 * (int64_t)t + b], S[sym3(corner, b)], t);
+      if (!a.kinematic) {
+        int pb = a.tri_poff[t], np = a.tri_npair[t];
+        for (int p = pb; p < pb + np; ++p) {
+          const Pair<R> &P = a.pair[p];
+          for (int m = 0; m < 3; ++m) visit((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * corner + m], t);
+        }
+      }
+    } else {
+      for (int i = a.mp_off[t]; i < a.mp_off[t + 1]; ++i) {
+        const Pair<R> &P = a.pair[a.mp_list[i]];
+        for (int m = 0; m < 3; ++m)
+          visit((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]), P.mm[sym3(corner, m)], P.T);
+        for (int s = 0; s < 3; ++s) visit(a.ts[3 * (int64_t)P.T + s], P.sm[3 * s + corner], P.T);
+      }
+    }
+  };
+
+  int n_ent = 0;
+  for (int src = sb + lane; src < se; src += kWave) n_ent += src_count(src);
   for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
   if (pass != 0 && a.grad) {
     // gradient row: slave a: sum_T -gs[T][a] n_T; master j: sum over the
@@ -491,62 +519,32 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
   }
   int tsz = 64;
   while (tsz < 2 * n_ent && tsz < slots) tsz <<= 1;
-  for (int i = lane; i < tsz; i += kWave) {
-    key[i] = -1;
-    if (pass == 1)
-      for (int c = 0; c < 6; ++c) acc[6 * i + c] = 0;
-  }
+  for (int i = lane; i < tsz; i += kWave) key[i] = -1;
   wave_sync();
-
-  // visit(col, coef, tri) for every contribution of this lane's sources
-  auto visit_all = [&](auto &&visit) {
-    for (int src = sb + lane; src < se; src += kWave) {
-      int ent = slave ? a.s_vt[src] : a.m_vt[src];
-      int t = ent >> 2, corner = ent & 3;
-      if (slave) {
-        if (a.tri_npair[t] == 0) continue;
-        const R *S = a.tri_sum + 9 * (int64_t)t;
-        for (int b = 0; b < 3; ++b) visit(a.ts[3 * (int64_t)t + b], S[sym3(corner, b)], t);
-        if (!a.kinematic) {
-          int pb = a.tri_poff[t], np = a.tri_npair[t];
-          for (int p = pb; p < pb + np; ++p) {
-            const Pair<R> &P = a.pair[p];
-            for (int m = 0; m < 3; ++m)
-              visit((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * corner + m], t);
-          }
-        }
-      } else {
-        for (int i = a.mp_off[t]; i < a.mp_off[t + 1]; ++i) {
-          const Pair<R> &P = a.pair[a.mp_list[i]];
-          for (int m = 0; m < 3; ++m)
-            visit((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]), P.mm[sym3(corner, m)], P.T);
-          for (int s = 0; s < 3; ++s) visit(a.ts[3 * (int64_t)P.T + s], P.sm[3 * s + corner], P.T);
-        }
-      }
-    }
-  };
-
-  int scale_exp = 0;
-  if (pass == 1) {
-    double sabs = 0.0;
-    visit_all([&](int32_t, R cf, int) { sabs += fabs((double)cf); });
-    for (int o = 32; o > 0; o >>= 1) sabs += __shfl_xor(sabs, o, kWave);
-    int ex = 0;
-    if (sabs > 0.0) frexp(sabs, &ex);  // sabs < 2^ex
-    scale_exp = 61 - ex;               // |sum| < 2^61
-  }
+  const bool stash = pass == 1 && n_ent <= kRowEnt;
   bool full = false;
-  visit_all([&](int32_t col, R cf, int t) {
-    int h = row_slot(key, tsz, col, &full);
-    if (pass == 1 && h >= 0) {
-      const R *nn = a.tri_nrm + 3 * (int64_t)t;
-      R v[6] = {cf * nn[0] * nn[0], cf * nn[0] * nn[1], cf * nn[0] * nn[2],
-                cf * nn[1] * nn[1], cf * nn[1] * nn[2], cf * nn[2] * nn[2]};
-      for (int c = 0; c < 6; ++c)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[6 * h + c]),
-                  (unsigned long long)llrint(ldexp((double)v[c], scale_exp)));
+  int run = 0;
+  for (int s0 = sb; s0 < se; s0 += kWave) {
+    const int src = s0 + lane;
+    const int cnt = src < se ? src_count(src) : 0;
+    int incl = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+      int v = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += v;
     }
-  });
+    int o = run + incl - cnt;
+    if (src < se)
+      visit_src(src, [&](int32_t col, R cf, int t) {
+        if (row_slot(key, tsz, col, &full) < 0) return;
+        if (stash) {
+          ecol[o] = col;
+          etri[o] = t;
+          ecoef[o] = cf;
+        }
+        ++o;
+      });
+    run += __shfl(incl, kWave - 1, kWave);
+  }
   if (__any(full)) {
     if (lane == 0) {
       atomicMax(&a.st->need_row, (unsigned long long)(2 * slots));
@@ -556,13 +554,12 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
     return;
   }
   wave_sync();
-  // compact the used slots
   int nuniq = 0;
   for (int i0 = 0; i0 < tsz; i0 += kWave) {
     int i = i0 + lane;
     bool used = i < tsz && key[i] >= 0;
     uint64_t m = __ballot(used);
-    if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = i;
+    if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = key[i];
     nuniq += __popcll(m);
   }
   if (pass == 0) {
@@ -570,20 +567,32 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int pas
     return;
   }
   wave_sync();
-  const double inv = ldexp(1.0, -scale_exp);
   for (int u = lane; u < nuniq; u += kWave) {
-    int h = dense[u];
-    int32_t c = key[h];
+    const int32_t c = dense[u];
     int r = 0;
-    for (int m = 0; m < nuniq; ++m) r += key[dense[m]] < c;
-    int64_t dst = (int64_t)a.row_ptr[row] + r;
-    R v[6];
-    for (int z = 0; z < 6; ++z) v[z] = (R)((double)acc[6 * h + z] * inv);
+    for (int m = 0; m < nuniq; ++m) r += dense[m] < c;
+    R v[6] = {0, 0, 0, 0, 0, 0};
+    auto add = [&](int32_t col, R cf, int t) {
+      if (col != c) return;
+      const R *nn = a.tri_nrm + 3 * (int64_t)t;
+      v[0] += cf * nn[0] * nn[0];
+      v[1] += cf * nn[0] * nn[1];
+      v[2] += cf * nn[0] * nn[2];
+      v[3] += cf * nn[1] * nn[1];
+      v[4] += cf * nn[1] * nn[2];
+      v[5] += cf * nn[2] * nn[2];
+    };
+    if (stash) {
+      for (int e = 0; e < n_ent; ++e) add(ecol[e], ecoef[e], etri[e]);
+    } else {
+      for (int src = sb; src < se; ++src) visit_src(src, add);
+    }
+    const int64_t dst = (int64_t)a.row_ptr[row] + r;
     a.col[dst] = c;
-    R *o = a.val + 9 * dst;
-    o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
-    o[3] = v[1]; o[4] = v[3]; o[5] = v[4];
-    o[6] = v[2]; o[7] = v[4]; o[8] = v[5];
+    R *ov = a.val + 9 * dst;
+    ov[0] = v[0]; ov[1] = v[1]; ov[2] = v[2];
+    ov[3] = v[1]; ov[4] = v[3]; ov[5] = v[4];
+    ov[6] = v[2]; ov[7] = v[4]; ov[8] = v[5];
   }
 }
 
@@ -856,27 +865,27 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   ra.grad = grad;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
     prof_mark(c, ST_GRAD, 0);
-    hipLaunchKernelGGL(k_rows<R>, dim3((unsigned)((c->V + kRowWaves - 1) / kRowWaves)), dim3(kWave * kRowWaves), 0,
-                       s, ra, 2, 64);
+    hipLaunchKernelGGL((k_rows<R, 2>), dim3((unsigned)((c->V + kRowWaves - 1) / kRowWaves)), dim3(kWave * kRowWaves),
+                       0, s, ra, 64);
     prof_mark(c, ST_GRAD, 1);
   }
   if (H) {
-    // distinct-column table per wave: <= 512 slots with two waves per block,
-    // 1024 with one (56 B per slot in the writing pass: <= 56 KiB of LDS)
+    // per wave: distinct-column set and list (8 B per slot, <= 1024 slots),
+    // plus the row's contributions in the writing pass (<= kRowEnt)
     int slots = 64;
     while (slots < c->caps.row_entries && slots < 1024) slots <<= 1;
-    int nw = slots <= 512 ? kRowWaves : 1;
+    const int nw = kRowWaves;
     unsigned rb = (unsigned)((c->V + nw - 1) / nw);
-    size_t lds0 = (size_t)nw * slots * 8, lds1 = lds0 + (size_t)nw * slots * 48;
+    size_t lds0 = (size_t)nw * slots * 8, lds1 = (size_t)nw * ((size_t)slots * 8 + (size_t)kRowEnt * (8 + sizeof(R)));
     e = fill_i32(c, b.row_cnt + c->V, 0, 1);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_COUNT, 0);
-    hipLaunchKernelGGL(k_rows<R>, dim3(rb), dim3(kWave * nw), lds0, s, ra, 0, slots);
+    hipLaunchKernelGGL((k_rows<R, 0>), dim3(rb), dim3(kWave * nw), lds0, s, ra, slots);
     prof_mark(c, ST_ROWS_COUNT, 1);
     e = scan_exclusive(c, b.row_cnt, H->row_ptr, c->V + 1);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_FILL, 0);
-    hipLaunchKernelGGL(k_rows<R>, dim3(rb), dim3(kWave * nw), lds1, s, ra, 1, slots);
+    hipLaunchKernelGGL((k_rows<R, 1>), dim3(rb), dim3(kWave * nw), lds1, s, ra, slots);
     prof_mark(c, ST_ROWS_FILL, 1);
     hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, s, H->row_ptr, c->V, b.status, H->cap_nnzb);
   }

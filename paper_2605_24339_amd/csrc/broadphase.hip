@@ -318,7 +318,7 @@ __device__ inline void slab_box(const float tlo[3], const float thi[3], const fl
 // with the slab box, facing test with slack) and insert it into an LDS hash
 // set, which removes the duplicates of overlapping cells and slabs.
 // pass 0 counts the set; pass 1 writes it sorted ascending.
-template <typename R>
+template <typename R, int PASS>
 __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, const int32_t *__restrict__ ts,
                                                      const int32_t *__restrict__ s_order,
                                                      const int32_t *__restrict__ s_env,
@@ -329,7 +329,8 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      const float4 *__restrict__ mbox, int32_t *__restrict__ cand_cnt,
                                                      const int32_t *__restrict__ cand_off, int32_t *__restrict__ cand,
                                                      int64_t cap_cand, int64_t cap_items, int64_t total_cells,
-                                                     DevStatus *st, int pass) {
+                                                     DevStatus *st) {
+  constexpr int pass = PASS;
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -378,26 +379,42 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
     if (lane >= d) incl += v;
   }
   const int work = __shfl(incl, kWave - 1, kWave);
-  for (int k = lane; k < kQuerySet; k += kWave) set[w][k] = -1;
-  wave_sync();
   const int64_t base = env[e].cell0;
+  // the lane's share of the (slab, cell) work items: fn(slab, cell)
+  auto for_cells = [&](auto &&fn) {
+    for (int w0 = 0; w0 < work; w0 += kWave) {
+      const int wi = w0 + lane;
+      int s = 0;
+      for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
+      s = min(s, kWave - 1);
+      const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
+      const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
+      const int sstart = __shfl(incl - ncs, s, kWave);
+      if (wi >= work) continue;
+      const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
+      const int li = wi - sstart;
+      const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+      fn(s, base + ((int64_t)zc * g.ny + y) * g.nx + x);
+    }
+  };
+  // items in the visited cells bound the candidates: skip empty prisms and
+  // size the set to the triangle
+  int nitems = 0;
+  for_cells([&](int, int64_t cell) { nitems += cell_start[cell + 1] - cell_start[cell]; });
+  for (int o = 32; o > 0; o >>= 1) nitems += __shfl_xor(nitems, o, kWave);
+  if (nitems == 0) {
+    if (pass == 0 && lane == 0) cand_cnt[t] = 0;
+    return;
+  }
+  int tsz = 64;
+  while (tsz < 2 * nitems && tsz < kQuerySet) tsz <<= 1;
+  for (int k = lane; k < tsz; k += kWave) set[w][k] = -1;
+  wave_sync();
   int fresh = 0;
   bool full = false;
-  for (int w0 = 0; w0 < work; w0 += kWave) {
-    const int wi = w0 + lane;
-    int s = 0;
-    for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
-    s = min(s, kWave - 1);
-    const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
-    const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
-    const int sstart = __shfl(incl - ncs, s, kWave);
-    if (wi >= work) continue;
-    const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
-    const int li = wi - sstart;
-    const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+  for_cells([&](int s, int64_t cell) {
     float lo[3], hi[3];
     slab_box(tlo, thi, n, -eps + s * dt, -eps + (s + 1) * dt, margin, lo, hi);
-    const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
     const int j1 = cell_start[cell + 1];
     for (int j = cell_start[cell]; j < j1; ++j) {
       int M = items[j];
@@ -406,20 +423,20 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
       float4 nm = mbox[3 * (int64_t)M + 2];
       // facing test with slack: the narrow phase takes the exact decision
       if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
-      uint32_t h = ((uint32_t)M * 2654435761u) & (kQuerySet - 1);
+      uint32_t h = ((uint32_t)M * 2654435761u) & (uint32_t)(tsz - 1);
       int probe = 0;
-      for (; probe < kQuerySet; ++probe) {
+      for (; probe < tsz; ++probe) {
         int prev = atomicCAS(&set[w][h], -1, M);
         if (prev == -1) {
           ++fresh;
           break;
         }
         if (prev == M) break;
-        h = (h + 1) & (kQuerySet - 1);
+        h = (h + 1) & (uint32_t)(tsz - 1);
       }
-      if (probe == kQuerySet) full = true;
+      if (probe == tsz) full = true;
     }
-  }
+  });
   if (__any(full)) {
     if (lane == 0) {
       atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
@@ -436,9 +453,9 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   }
   wave_sync();
   int nu = 0;
-  for (int k0 = 0; k0 < kQuerySet; k0 += kWave) {
+  for (int k0 = 0; k0 < tsz; k0 += kWave) {
     int k = k0 + lane;
-    bool used = set[w][k] >= 0;
+    bool used = k < tsz && set[w][k] >= 0;
     uint64_t m = __ballot(used);
     if (used) dense[w][nu + __popcll(m & ((1ull << lane) - 1))] = set[w][k];
     nu += __popcll(m);
@@ -504,9 +521,9 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   const dim3 qgrid((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves));
   prof_mark(c, ST_QUERY_COUNT, 0);
   if (c->Ts)
-    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+    hipLaunchKernelGGL((k_query<R, 0>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.status, 0);
+                       c->caps.grid_items, c->total_cells, b.status);
   prof_mark(c, ST_QUERY_COUNT, 1);
   e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
   if (e != hipSuccess) return e;
@@ -514,9 +531,9 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (e != hipSuccess) return e;
   prof_mark(c, ST_QUERY_FILL, 0);
   if (c->Ts)
-    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+    hipLaunchKernelGGL((k_query<R, 1>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.status, 1);
+                       c->caps.grid_items, c->total_cells, b.status);
   prof_mark(c, ST_QUERY_FILL, 1);
   hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
   return hipGetLastError();

@@ -24,18 +24,35 @@ template <typename R> __device__ inline float to_float_down(R v);
 template <> __device__ inline float to_float_down<float>(float v) { return v; }
 template <> __device__ inline float to_float_down<double>(double v) { return __double2float_rd(v); }
 
+// Per-environment minimum of a >= 0 (uint order of non-negative floats is
+// float order).  Waves reduce by shuffles; a block whose waves all hold one
+// environment issues a single atomic.  Every thread of the block must call.
 __device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
-  // a >= 0 here; uint order of non-negative floats is float order
+  __shared__ int wenv[kThreads / kWave];
+  __shared__ float wmin[kThreads / kWave];
+  const int w = threadIdx.x / kWave;
   uint64_t vm = __ballot(env >= 0);
-  if (!vm) return;
-  int e0 = __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave);
+  int e0 = vm ? __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave) : -1;
   bool uniform = __all(env < 0 || env == e0);
-  if (uniform) {
-    float m = env >= 0 ? a : INFINITY;
-    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, kWave));
-    if (lane == 0 && m < INFINITY) atomicMin(&bits[e0], __float_as_uint(m));
-  } else if (env >= 0 && a < INFINITY) {
-    atomicMin(&bits[env], __float_as_uint(a));
+  float m = (env >= 0 && uniform) ? a : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, kWave));
+  if (!uniform && env >= 0 && a < INFINITY) atomicMin(&bits[env], __float_as_uint(a));
+  if (lane == 0) {
+    wenv[w] = uniform ? e0 : -1;
+    wmin[w] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int nw = blockDim.x / kWave;
+  for (int v = 0; v < nw; ++v) {
+    if (wenv[v] < 0) continue;
+    float mm = wmin[v];
+    for (int u = v + 1; u < nw; ++u)
+      if (wenv[u] == wenv[v]) {
+        mm = fminf(mm, wmin[u]);
+        wenv[u] = -1;
+      }
+    if (mm < INFINITY) atomicMin(&bits[wenv[v]], __float_as_uint(mm));
   }
 }
 

@@ -157,7 +157,7 @@ def main():
     feats, targs, plain_train = [], [], []
     for j in range(args.train):
         sc = Scene(5000 + j, args.n, args.nz, device=dev)
-        recs = run_trajectory(sc, args.steps, None, keep=True)
+        recs = run_trajectory(sc, args.steps, None, keep=True, log=log)
         log(f"train trajectory {j}: {summarize(recs)['newton']}")
         for r in recs:
             feats.append(r.pop("feat"))
@@ -176,8 +176,8 @@ def main():
     plain, learned = [], []
     for j in range(args.test):
         sc = Scene(5000 + args.train + j, args.n, args.nz, device=dev)
-        p = run_trajectory(sc, args.steps, None, keep=False)
-        l = run_trajectory(sc, args.steps, net, keep=False)
+        p = run_trajectory(sc, args.steps, None, keep=False, log=log)
+        l = run_trajectory(sc, args.steps, net, keep=False, log=log)
         log(f"test trajectory {j}: plain {summarize(p)['newton']} learned {summarize(l)['newton']}")
         plain += p
         learned += l

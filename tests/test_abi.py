@@ -91,3 +91,24 @@ def test_workspace_size_and_strerror_host_only():
     assert N.strerror(N.GMCP_E_PENETRATION).startswith("penetration")
     ctx = C.c_void_p()
     assert L.gmcp_create(C.byref(ctx), C.byref(lay_bad), C.byref(caps), None, None, None, 0, None) == N.GMCP_E_ARG
+
+
+def test_dualmesh_header_symbols_exported():
+    from paper_2605_24339_amd import _native
+    lib = _native.lib()
+    names = _declared("gmcp_dualmesh.h")
+    assert set(names) == set(_native.DUALMESH_EXPORTS)
+    assert not [n for n in names if not hasattr(lib, n)]
+
+
+def test_dualmesh_argument_errors_host_only():
+    """Argument checks return before any launch (no device needed)."""
+    import ctypes as C
+    from paper_2605_24339_amd import _native as N
+    from paper_2605_24339_amd.dualmesh import _lib
+    L = _lib()
+    assert L.gmcp_dualmesh_embed(None, -1, None, None, 0, None, None, None, None, None) == N.GMCP_E_ARG
+    assert L.gmcp_dualmesh_embed(None, 0, None, None, 0, None, None, None, None, None) == N.GMCP_OK
+    assert L.gmcp_dualmesh_embed(C.c_void_p(8), 5, C.c_void_p(8), None, 0, None, None, None, None, None) == N.GMCP_E_ARG
+    assert L.gmcp_dualmesh_update(None, None, None, None, None, -3, None, 0, None) == N.GMCP_E_ARG
+    assert L.gmcp_dualmesh_update(None, None, None, None, None, 0, None, 0, None) == N.GMCP_OK

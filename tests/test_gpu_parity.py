@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from gen import meshes, workloads
-from gpu_helpers import bsr_rel_error, need_gpu, rel_fro, run_gpu, run_oracle, to_dev
+from gpu_helpers import bsr_rel_error, make_ctx, need_gpu, rel_fro, run_gpu, run_oracle, to_dev
 
 torch = pytest.importorskip("torch")
 
@@ -218,3 +218,46 @@ def test_batched_environments_match_single():
         assert al[i] == G["alpha"]
         gi = A.grad.double().cpu().numpy()[vo[i]:vo[i + 1]]
         assert rel_fro(gi, G["grad"][:w.xs.shape[0]]) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_reference_gaps_and_gap_offsets(dtype):
+    """Per-sample support radius eps_k = min(0.9 g_ref_k, dhat) (Eq.
+    (adaptive_eps)) from caller-supplied reference gaps, plus per-sample gap
+    offsets added after selection; selection, energy, gradient and Hessian
+    against the oracle given the same arrays."""
+    need_gpu()
+    import oracle
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    w = workloads.small_indent(fp32=fp32)
+    rng = np.random.default_rng(8)
+    Ns = w.ts.shape[0] * w.rule_n ** 2
+    g_ref = rng.uniform(0.2, 2.0, size=Ns) * w.dhat
+    dgap = rng.uniform(0.0, 1e-6, size=Ns)
+    if fp32:
+        g_ref = g_ref.astype(np.float32).astype(np.float64)
+        dgap = dgap.astype(np.float32).astype(np.float64)
+    ctx = make_ctx(w, tdt)
+    xs, xm = to_dev(w.xs, tdt), to_dev(w.xm, tdt)
+    ctx.build_samples(to_dev(w.xs_rest, tdt))
+    ctx.broadphase(xs, xm)
+    A = ctx.assemble(xs, xm, g_ref=to_dev(g_ref, tdt), delta_gap=to_dev(dgap, tdt))
+    Mg = ctx.sample_results()["M"].cpu().numpy()
+    P = oracle.Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, g_ref, w.xs_rest)
+    nr = oracle.narrow(P)
+    M = nr.M.copy()
+    fl = nr.flags != 0
+    M[fl] = Mg[fl]
+    assert np.array_equal(Mg[~fl], nr.M[~fl])
+    # the reference gaps removed some of the plain run's contacts
+    plain = oracle.narrow(oracle.Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, None,
+                                         w.xs_rest))
+    assert (nr.M >= 0).sum() < (plain.M >= 0).sum() and (nr.M >= 0).sum() > 100
+    O = oracle.assemble(P, M, delta_gap=dgap, project=False)
+    te, tg = (1e-5, 1e-4) if fp32 else (1e-10, 1e-10)
+    assert abs(float(A.energy.double().sum().item()) / O.energy - 1) <= te
+    assert rel_fro(A.grad.double().cpu().numpy(), O.grad) <= tg
+    H = A.hessian
+    assert bsr_rel_error(H.row_ptr.cpu().numpy(), H.col.cpu().numpy(), H.val.double().cpu().numpy(), O.row_ptr,
+                         O.col, O.val) <= tg
