@@ -1,0 +1,132 @@
+"""Pins of the clipped mortar face samples of the oracle (Sec. 4.1 face
+samples, Sec. 4.2): the clipping against hand-computed polygons, exact
+overlap areas and exact integrals of linear gaps for flat punches (which
+whole-triangle samples only approximate), the projection property of every
+sample, and the gradient against finite differences of the frozen-sample
+energy."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gen import workloads
+from oracle import mortar
+
+
+def _area(poly):
+    a = 0.0
+    for i in range(len(poly)):
+        p, q = poly[i], poly[(i + 1) % len(poly)]
+        a += p[0] * q[1] - q[0] * p[1]
+    return abs(a) / 2
+
+
+def test_clip_against_hand_polygons():
+    # a triangle containing the reference triangle clips to it
+    out = mortar.clip_by_reference([(-1, -1), (3, -1), (-1, 3)])
+    assert abs(_area(out) - 0.5) < 1e-15 and len(out) == 3
+    # a triangle inside is unchanged
+    tri = [(0.1, 0.1), (0.3, 0.1), (0.1, 0.4)]
+    out = mortar.clip_by_reference(tri)
+    assert np.allclose(np.array(out), np.array(tri))
+    # disjoint
+    assert mortar.clip_by_reference([(2, 2), (3, 2), (2, 3)]) == []
+    # the square [0.25, 0.75]^2 as two triangles: area above the diagonal u + v = 1 is cut
+    sq = [(0.25, 0.25), (0.75, 0.25), (0.75, 0.75), (0.25, 0.75)]
+    out = mortar.clip_by_reference(sq)
+    assert abs(_area(out) - (0.25 - 0.125)) < 1e-15     # half of the square lies below u + v = 1
+    # reversed orientation gives the same area
+    assert abs(_area(mortar.clip_by_reference(sq[::-1])) - 0.125) < 1e-15
+
+
+def _punch_problem(punch_length, n_pad=6, n_punch=5, gap=3e-4, rule_n=2, tilt=0.0):
+    w = workloads.flat_punch(n_pad=n_pad, n_punch=n_punch, gap=gap, punch_length=punch_length, rule_n=rule_n)
+    xm = w.xm.copy()
+    xm[:, 2] += tilt * xm[:, 0]
+    return oracle.Problem(w.xs, w.ts, xm, w.tm, rule_n, w.kappa, w.dhat, w.delta_T, None, w.xs), w
+
+
+@pytest.mark.parametrize("punch,expect", [(1.4e-2, 1e-4), (6e-3, 3.6e-5)])
+def test_flat_punch_weights_cover_the_exact_overlap(punch, expect):
+    """Punch larger than the pad: the weights sum to the pad area; a
+    smaller, shifted, independently meshed punch inside the pad: to the
+    punch area.  Every gap equals the uniform gap and E = kappa B(g0) area."""
+    P, w = _punch_problem(punch)
+    S = mortar.samples(P)
+    A = mortar.assemble(P, S)
+    tot = sum(s.w for s in A.active)
+    assert abs(tot / expect - 1) < 1e-12
+    assert all(abs(s.g - 3e-4) < 1e-15 for s in A.active)
+    assert abs(A.energy / (P.kappa * oracle.barrier(3e-4, P.dhat) * expect) - 1) < 1e-12
+    for s in A.active:        # the master point projects onto the slave point
+        xs_k = s.bs @ P.xs[P.ts[s.T]]
+        xm_k = s.bm @ P.xm[P.tm[s.M]]
+        assert np.linalg.norm(np.cross(xm_k - xs_k, s.n)) < 1e-15
+        assert s.bm.min() >= -1e-12 and s.bs.min() >= -1e-12
+
+
+def test_rotated_punch_overlap_against_lattice_count():
+    """A punch rotated by 30 degrees about the pad normal: the weights sum
+    to the overlap of the two squares, counted independently on a lattice."""
+    P, w = _punch_problem(9e-3, n_pad=5, n_punch=4)
+    c, s = math.cos(math.pi / 6), math.sin(math.pi / 6)
+    Rz = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+    P = oracle.Problem(P.xs, P.ts, P.xm @ Rz.T, P.tm, P.rule_n, P.kappa, P.dhat, 0.0, None, P.xs)
+    tot = sum(s_.w for s_ in mortar.assemble(P, mortar.samples(P)).active)
+    m = 1500
+    t = (np.arange(m) + 0.5) / m * 1e-2 - 5e-3
+    X, Y = np.meshgrid(t, t)
+    U = c * X + s * Y - 0.13 * 9e-3 / 4          # coordinates in the punch frame (inverse rotation, shift)
+    V = -s * X + c * Y - 0.07 * 9e-3 / 4
+    inside = (np.abs(U) <= 4.5e-3) & (np.abs(V) <= 4.5e-3)
+    ref = inside.mean() * 1e-4
+    assert abs(tot / ref - 1) < 2e-3
+
+
+@pytest.mark.parametrize("rule_n", [1, 2, 3])
+def test_linear_gap_integrated_exactly(rule_n):
+    """A tilted punch (gap linear in x): sum_k w_k g_k equals the exact
+    integral of the gap over the covered pad area for every rule."""
+    tilt = 0.02
+    P, w = _punch_problem(1.4e-2, rule_n=rule_n, tilt=tilt)
+    S = mortar.samples(P)
+    tot = sum(s.w * s.g for s in S)
+    # pad [-5, 5] mm^2 fully covered: integral of (g0 + tilt x) = g0 * area (x averages to 0 over the pad)
+    assert abs(tot / (3e-4 * 1e-4) - 1) < 1e-12
+    if rule_n >= 2:      # g x is quadratic: exact from degree 2n - 1 >= 2
+        tot_x = sum(s.w * s.g * (s.bs @ P.xs[P.ts[s.T]])[0] for s in S)
+        assert abs(tot_x / (tilt * (1e-2) ** 4 / 12) - 1) < 1e-10
+
+
+def test_gradient_against_frozen_energy_differences():
+    P, _ = _punch_problem(6e-3, n_pad=4, n_punch=3, gap=2e-4)
+    rng = np.random.default_rng(2)
+    P = oracle.Problem(P.xs, P.ts, P.xm + rng.uniform(-2e-5, 2e-5, size=P.xm.shape), P.tm, P.rule_n, P.kappa,
+                       P.dhat, 0.0, None, P.xs)
+    S = mortar.samples(P)
+    A = mortar.assemble(P, S)
+
+    def frozen(xs, xm):
+        E = 0.0
+        for s in A.active:
+            g = s.n @ (s.bm @ xm[P.tm[s.M]] - s.bs @ xs[P.ts[s.T]])
+            E += P.kappa * s.w * oracle.barrier(g, P.dhat)
+        return E
+
+    ds = rng.normal(size=P.xs.shape) * 1e-6
+    dm = rng.normal(size=P.xm.shape) * 1e-6
+    h = 1e-3
+    fd = (frozen(P.xs + h * ds, P.xm + h * dm) - frozen(P.xs - h * ds, P.xm - h * dm)) / (2 * h)
+    an = float(np.sum(A.grad[:P.Vs] * ds) + np.sum(A.grad[P.Vs:] * dm))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    # the Hessian blocks are symmetric PSD rank-one sums
+    for (i, j), B in A.blocks.items():
+        assert np.allclose(B, A.blocks[(j, i)].T, atol=1e-12 * np.abs(B).max())
+
+
+def test_penetration_reported():
+    P, _ = _punch_problem(6e-3, gap=-1e-5)
+    with pytest.raises(oracle.OracleError) as e:
+        mortar.samples(P)
+    assert e.value.code == oracle.E_PENETRATION
