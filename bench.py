@@ -30,7 +30,8 @@ METRIC = "GMCP samples/s (E+grad+Hess) & CCD pairs/s, % HBM peak; Newton iters l
 HBM_PEAK_GBS = 8000.0
 # kernels that one profiled stage brackets exactly (candidates for the roofline)
 KERNEL_STAGES = {"query_count": "k_query<float, 0>", "query_fill": "k_query<float, 1>", "narrow": "k_narrow<float>",
-                 "rows_count": "k_rows<float, 0>", "rows_fill": "k_rows<float, 1>",
+                 "rows_count": "k_rows<float, 0, false>", "rows_fill": "k_rows<float, 1, false>",
+                 "rows_count_heavy": "k_rows<float, 0, true>", "rows_fill_heavy": "k_rows<float, 1, true>",
                  "ccd_linear": "k_ccd_linear<float>", "ccd_accd": "k_ccd_accd<float>"}
 
 
@@ -51,17 +52,29 @@ def kernel_bytes(stage: str, sz: dict) -> int:
     V = Vs + Vm
     if stage == "narrow":
         # slave x / triangles / areas, candidate CSR, master triangles + x;
-        # records 48 B per selected sample, per-triangle normal+sums+counters
+        # records 64 B per active sample, per-triangle normal+sums+counters
         # 64 B, pairs 80 B, tile energies 8 B
-        return 12 * Vs + 16 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm + 48 * na + 64 * Ts + 80 * npair + 8 * ntile
+        return 12 * Vs + 16 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm + 64 * na + 64 * Ts + 80 * npair + 8 * ntile
     if stage in ("query_count", "query_fill"):
         out = 4 * Ts if stage == "query_count" else 4 * nc
         return 12 * Vs + 12 * Ts + 48 * Tm + 4 * (Ts + 1) + out
     if stage in ("rows_count", "rows_fill"):
-        out = 4 * V if stage == "rows_count" else 40 * nnzb + 4 * (V + 1)
-        return 48 * Ts + 84 * npair + 4 * (V + 1) + 12 * (Ts + Tm) + 4 * (Tm + 1) + out
+        # light rows: active slave triangles' sums and normals, their pairs,
+        # slave adjacency; out: counts, or blocks + row gradients
+        rl, nl = sz["rows_light"], sz["nnzb_light"]
+        ta = min(Ts, npair)
+        inp = 48 * ta + 80 * npair + 12 * Ts + 4 * (Vs + 1) + 8 * rl
+        return inp + (4 * rl if stage == "rows_count" else 40 * nl + 12 * rl)
+    if stage in ("rows_count_heavy", "rows_fill_heavy"):
+        # heavy rows: per-master-triangle blocks, bucket keys and the pairs'
+        # slave triangles, master adjacency; out: counts, or blocks + gradients
+        rh, nh = sz["rows_heavy"], sz["nnzb_heavy"]
+        tma = min(Tm, npair)
+        inp = 180 * tma + 8 * npair + 12 * npair + 4 * (Tm + 1) + 12 * Tm + 4 * (Vm + 1) + 8 * rh
+        return inp + (4 * rh if stage == "rows_count_heavy" else 40 * nh + 12 * rh)
     if stage == "ccd_linear":
-        return 48 * na + 12 * Ts + 24 * Vs + 12 * Tm + 12 * Vm
+        # records, slave normals and triangles, slave / master displacements, master triangles
+        return 64 * na + 24 * Ts + 12 * Vs + 12 * Tm + 12 * Vm
     if stage == "ccd_accd":
         return 24 * Vs + 12 * Ts + 24 * Vm + 12 * Tm + 48 * Tm
     return 0
@@ -79,7 +92,7 @@ def time_replays(g, steps: int, stream) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def measure(name, envs, batch, steps, warmup, dev, tune_cache=None):
+def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False):
     """Autotune, capture, time; per-kernel stage times; roofline of the
     dominant kernel."""
     import numpy as np
@@ -94,9 +107,10 @@ def measure(name, envs, batch, steps, warmup, dev, tune_cache=None):
         return Context(batch.ts, batch.tm, batch.slave_v_off, batch.slave_t_off, batch.master_v_off,
                        batch.master_t_off, [w.rule_n for w in envs], [w.kappa for w in envs],
                        [w.dhat for w in envs], [w.delta_T for w in envs], cells, dtype=torch.float32,
-                       device=dev)
+                       device=dev, mortar=mortar)
 
-    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache)
+    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache if not mortar else None,
+                                 scales=autotune.SCALES if not mortar else (0.0,))
     ctx = make(cells)
     ctx.build_samples(xs)
     g = ctx.capture(xs, xm, dxs, dxm)
@@ -117,7 +131,8 @@ def measure(name, envs, batch, steps, warmup, dev, tune_cache=None):
     Ns = sum(w.n_samples for w in envs)
     sz = dict(Vs=batch.xs.shape[0], Vm=batch.xm.shape[0], Ts=batch.ts.shape[0], Tm=batch.tm.shape[0],
               n_active=int(st.n_active), n_pairs=int(st.n_pairs), n_cand=int(st.n_candidates),
-              nnzb=int(st.nnzb), n_tiles=sum((w.ts.shape[0] * w.rule_n ** 2 + 63) // 64 for w in envs))
+              nnzb=int(st.nnzb), n_tiles=sum((w.ts.shape[0] * w.rule_n ** 2 + 63) // 64 for w in envs),
+              **ctx.row_classes())
     kern = {k: v for k, v in stages.items() if k in KERNEL_STAGES}
     dom = max(kern, key=kern.get)
     byts = kernel_bytes(dom, sz)
@@ -389,6 +404,10 @@ def main():
         out["autograd"] = measure_autograd(w, dev)
         out["mlp"] = measure_mlp(dev)
         out["dualmesh"] = measure_dualmesh(dev)
+        mo = measure(w.name + "/mortar", [w], workloads.concat([w]), max(10, args.steps // 5), 3, dev, mortar=True)
+        out["mortar"] = {"workload": w.name + " with clipped mortar face samples", "ms_per_step": mo["ms"],
+                         "slave_samples_per_s": mo["value"], "clipped_active_samples": mo["sizes"]["n_active"],
+                         "pairs": mo["sizes"]["n_pairs"], "stage_ms": mo["stages"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out))

@@ -22,6 +22,21 @@
  * W_i W_j; slave barycentrics (1 - xi - eta, xi, eta); sample id
  * k = sample_offset(T) + i*n + j; weight w_k = 2 A_rest(T) W_i W_j.
  *
+ * Clipped mortar samples (GMCP_MORTAR, Sec. 4.1 face samples as the paper
+ * defines them).  For every slave triangle T and opposing candidate master
+ * triangle M, M is projected along n_T onto T's plane and clipped by T
+ * (Sutherland-Hodgman); the polygon is fan-triangulated from its first
+ * vertex and each sub-triangle carries the n x n rule above.  A sample has
+ * slave barycentrics from its position in T, master barycentrics from its
+ * position in the projected M, gap g = n_T . (x_m - x_s) and weight
+ * w = 2 A_sub W_q, A_sub the sub-triangle's share of T's rest area; it is
+ * active for 0 < g < dhat (-dhat < g <= 0 is a penetration, reported with
+ * the slave triangle's index).  Every opposing pair contributes (no
+ * closest-triangle selection).  Clipped samples have no fixed ids: in this
+ * mode gmcp_assemble takes no g_ref / delta_gap, gmcp_hvp no v_d / out_d,
+ * and gmcp_sample_results is unavailable (GMCP_E_ARG); the active capacity
+ * counts clipped samples.
+ *
  * Environments.  n_env independent problems are concatenated: slave
  * vertices/triangles of environment e are [v_off[e], v_off[e+1]) and
  * [t_off[e], t_off[e+1]) (same for the master).  Triangle vertex ids are
@@ -67,7 +82,8 @@ typedef enum {
 
 enum {
   GMCP_F64 = 1,              /* positions and outputs in double              */
-  GMCP_KINEMATIC_MASTER = 2  /* master is prescribed: drop its rows/columns  */
+  GMCP_KINEMATIC_MASTER = 2, /* master is prescribed: drop its rows/columns  */
+  GMCP_MORTAR = 4            /* clipped mortar face samples (see below)      */
 };
 
 /* Problem layout (all host memory, copied by gmcp_create). */
@@ -93,7 +109,7 @@ typedef struct {
   int64_t candidates;  /* (slave triangle, master triangle) candidate pairs    */
   int64_t active;      /* active samples (0 < g < eps after selection)         */
   int64_t pairs;       /* distinct (slave triangle, master triangle) contacts  */
-  int64_t row_entries; /* per-row contribution list length (longest BSR row)   */
+  int64_t row_entries; /* distinct columns of the longest BSR row (<= 4096)      */
 } gmcp_caps;
 
 /* Read back by gmcp_status. */
@@ -211,6 +227,21 @@ int gmcp_ccd_step(gmcp_ctx *ctx, const void *x_slave, const void *x_master, cons
 int gmcp_hvp(gmcp_ctx *ctx, const void *v_x, const void *v_d, void *out_x, void *out_d);
 
 /*
+ * Energy of the last assembly's samples at new positions x_slave [Vs][3],
+ * x_master [Vm][3], every sample frozen (the reading of Sec. 4.2's gradient
+ * and Hessian approximation): slave normal n_T, rule point, master triangle
+ * and barycentric coordinates, weight w_k, face weight gamma_k and support
+ * radius eps_k stay as assembled, so g_k = n_T . (sum_j bm_j x_mj -
+ * sum_a bs_a x_sa) is affine in x and this energy's gradient at the
+ * assembly positions is the assembled gradient (gap offsets are not
+ * applied).  energy [n_env]; +inf for an environment where a frozen gap is
+ * <= 0.  The line search of an implicit step uses it so that the energy it
+ * tests and the gradient it descends belong to the same function.
+ * Deterministic.  GMCP_E_ARG before any assembly.
+ */
+int gmcp_energy_frozen(gmcp_ctx *ctx, const void *x_slave, const void *x_master, void *energy);
+
+/*
  * Per-sample export of the last assembly (for checks and pressure maps):
  *   master [Ns] int32 (-1 inactive), gap [Ns], bary_m [Ns][3], c1 [Ns],
  *   c2 [Ns], pressure [Ns] = -kappa gamma B'(g) (0 inactive).  Any may be NULL.
@@ -243,6 +274,14 @@ const char *gmcp_profile_stage_name(int stage);
  * gmcp_profile(ctx, 1).  Host arrays of at least gmcp_profile_stages().
  */
 int gmcp_profile_read(gmcp_ctx *ctx, double *ms, int64_t *count);
+
+/*
+ * Synchronises and writes host out[4] for the last assembly with a Hessian:
+ * BSR rows processed as light rows (at most 256 contributions, small LDS
+ * tables), heavy rows, and the blocks written by each class.  For
+ * per-kernel byte accounting of the profiled stages.
+ */
+int gmcp_row_classes(gmcp_ctx *ctx, int64_t *out);
 
 /* Human-readable name of a status code. */
 const char *gmcp_strerror(int code);

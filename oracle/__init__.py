@@ -263,6 +263,35 @@ def assemble(P: Problem, M, delta_gap=None, kinematic=False, project=True, hessi
                     None if val is None else val[:nb].copy(), clamped.value)
 
 
+def frozen_energy(P: Problem, M, bm, xs_new, xm_new) -> float:
+    """Energy of the samples selected at P's positions (master triangle M[k],
+    its barycentric coordinates bm[k]) evaluated at new positions with every
+    sample frozen (Sec. 4.2's gradient and Hessian approximation): the slave
+    normal n_T at P's positions, the rule point, M[k] and bm[k], the weight,
+    face weight and support radius.  Then g_k = n_T . (sum_j bm_j x_mj -
+    sum_a bs_a x_sa) is affine in the positions.  +inf if a gap is <= 0."""
+    xs_new, xm_new = _f64(xs_new), _f64(xm_new)
+    w = weights(P)
+    E = 0.0
+    for k in np.nonzero(np.asarray(M) >= 0)[0]:
+        T, q = divmod(int(k), P.nq)
+        a, b, c = P.ts[T]
+        e1, e2 = P.xs[b] - P.xs[a], P.xs[c] - P.xs[a]
+        n = np.cross(e1, e2)
+        n /= np.linalg.norm(n)
+        xi, eta = P.rule[q, 0], P.rule[q, 1]
+        xs_k = (1 - xi - eta) * xs_new[a] + xi * xs_new[b] + eta * xs_new[c]
+        xm_k = sum(bm[k][j] * xm_new[P.tm[M[k], j]] for j in range(3))
+        g = float(n @ (xm_k - xs_k))
+        eps = P.dhat if P.g_ref is None else min(0.9 * P.g_ref[k], P.dhat)
+        if g <= 0.0:
+            return float("inf")
+        if g < eps:
+            gam = hermite(min(bm[k]), P.delta_T) if P.delta_T > 0 else 1.0
+            E += P.kappa * w[k] * gam * barrier(g, eps)
+    return E
+
+
 def sample_geom(P: Problem, k: int, M: int):
     g = C.c_double(0.0)
     bm = np.empty(3)

@@ -6,8 +6,9 @@ Incremental potential of one step (target x_tilde = x_t + dt v_t):
     Psi_el = sum_tets vol (mu eps:eps + lambda/2 tr(eps)^2),  eps = sym(grad u), u = x - X
 with linear shape functions (grad N_1..3 = rows of Dm^-1, grad N_0 = -sum),
 lumped mass rho vol / 4 per tet vertex.  Newton with a direct sparse solve,
-step capped by the GMCP step bound, Armijo backtracking; stop when
-|grad E|_inf <= tol * F_ref.
+step capped by the GMCP step bound, Armijo backtracking on the energy with
+the iterate's contact samples frozen (the function the assembled gradient
+and Hessian belong to); stop when |grad E|_inf <= tol * F_ref.
 """
 from __future__ import annotations
 
@@ -115,42 +116,42 @@ def newton_step(body: Body, P_of, x_t, v_t, fixed_pos, kappa, dhat, rule_n, xm, 
         P = P_of(x)
         nr = oracle.narrow(P)
         A = oracle.assemble(P, nr.M, kinematic=True, project=False, hessian=need_h)
-        return P, nr.M, A
+        return P, nr, A
 
-    P, M, _ = gmcp(x_t, False)
-    a0 = oracle.ccd_step(P, M, y - x_t, None).alpha
+    P, nr, _ = gmcp(x_t, False)
+    a0 = oracle.ccd_step(P, nr.M, y - x_t, None).alpha
     x = x_t + a0 * (y - x_t)
     x[fx] = fixed_pos[fx]
     stats = dict(newton_iters=0, assemblies=0, energy_evals=0, start_alpha=a0, residual=np.inf)
     V = x.shape[0]
     for _ in range(max_newton):
         Ef, gf = body.fem_energy_grad(x, x_tilde)
-        P, M, A = gmcp(x, True)
+        P, nr, A = gmcp(x, True)
         stats["assemblies"] += 1
         g = gf + A.grad[:V]
         g[fx] = 0.0
-        E = Ef + A.energy
         stats["residual"] = np.abs(g).max() / f_ref
         if stats["residual"] <= tol:
             break
         stats["newton_iters"] += 1
-        rows = np.repeat(np.arange(V), np.diff(A.row_ptr[:V + 1]))
         Hb = sp.bsr_matrix((A.val, A.col, A.row_ptr[:V + 1]), shape=(3 * V, 3 * V)) if A.col.size else \
             sp.csr_matrix((3 * V, 3 * V))
-        del rows
         Asys = sp.diags(np.repeat(body.m, 3) / dt ** 2) + body.K + Hb
         fr = body.free
         d = np.zeros(3 * V)
         d[fr] = spla.spsolve(Asys.tocsr()[fr][:, fr].tocsc(), -g.ravel()[fr])
         d = d.reshape(-1, 3)
         slope = float(np.sum(g * d))
-        alpha = min(1.0, oracle.ccd_step(P, M, d, None).alpha)
+        alpha = min(1.0, oracle.ccd_step(P, nr.M, d, None).alpha)
+        # Armijo on the energy with this iterate's samples frozen: the function
+        # whose gradient and Hessian the assembly gave (Sec. 4.2)
+        E0 = Ef + oracle.frozen_energy(P, nr.M, nr.bm, x, xm)
         while True:
             xn = x + alpha * d
             Efn, _ = body.fem_energy_grad(xn, x_tilde)
-            _, _, An = gmcp(xn, False)
+            En = Efn + oracle.frozen_energy(P, nr.M, nr.bm, xn, xm)
             stats["energy_evals"] += 1
-            if Efn + An.energy <= E + armijo * alpha * slope or alpha < 1e-14:
+            if En <= E0 + armijo * alpha * slope or alpha < 1e-14:
                 break
             alpha *= 0.5
         x = xn

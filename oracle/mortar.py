@@ -168,3 +168,16 @@ def assemble(P: "oracle.Problem", smps, kinematic: bool = False, with_hessian: b
                 for j, cj in zip(ids, coef):
                     blocks[(i, j)] = blocks.get((i, j), 0.0) + c2 * ci * cj * nn
     return MortarAssembly(E, grad, blocks, act, np.array(c1s), np.array(c2s))
+
+
+def linear_step(P: "oracle.Problem", active, dxs, dxm=None) -> float:
+    """Eq. (ccd) over clipped samples: min over active samples with
+    grad g . dx < 0 of 0.9 g / (-grad g . dx) (inf if none), samples frozen."""
+    a = np.inf
+    for s in active:
+        gd = -s.n @ (s.bs @ dxs[P.ts[s.T]])
+        if dxm is not None:
+            gd += s.n @ (s.bm @ dxm[P.tm[s.M]])
+        if gd < 0.0:
+            a = min(a, 0.9 * s.g / (-gd))
+    return a

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libgmcp.so")
 
 GMCP_OK, GMCP_E_ARG, GMCP_E_CAPACITY, GMCP_E_PENETRATION = 0, 1, 2, 3
 GMCP_E_DEGENERATE, GMCP_E_NONFINITE, GMCP_E_HIP = 4, 5, 6
-GMCP_F64, GMCP_KINEMATIC_MASTER = 1, 2
+GMCP_F64, GMCP_KINEMATIC_MASTER, GMCP_MORTAR = 1, 2, 4
 
 P = C.c_void_p
 i32p = C.POINTER(C.c_int32)
@@ -45,9 +45,9 @@ class Bsr(C.Structure):
 
 EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_stream",
            "gmcp_build_samples", "gmcp_num_samples", "gmcp_broadphase", "gmcp_assemble",
-           "gmcp_ccd_step", "gmcp_hvp", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
+           "gmcp_ccd_step", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
            "gmcp_strerror", "gmcp_profile", "gmcp_profile_stages", "gmcp_profile_stage_name",
-           "gmcp_profile_read", "gmcp_rule"]
+           "gmcp_profile_read", "gmcp_rule", "gmcp_row_classes"]
 # include/gmcp_mlp.h
 MLP_EXPORTS = ["gmcp_mlp_param_count", "gmcp_mlp_work_bytes", "gmcp_mlp_forward", "gmcp_mlp_backward",
                "gmcp_mlp_mse", "gmcp_mlp_adam", "gmcp_gemm_bf16"]
@@ -93,6 +93,8 @@ def lib():
         L.gmcp_ccd_step.argtypes = [P, P, P, P, P, P]
         L.gmcp_hvp.restype = C.c_int
         L.gmcp_hvp.argtypes = [P, P, P, P, P]
+        L.gmcp_energy_frozen.restype = C.c_int
+        L.gmcp_energy_frozen.argtypes = [P, P, P, P]
         L.gmcp_sample_results.restype = C.c_int
         L.gmcp_sample_results.argtypes = [P, P, P, P, P, P, P]
         L.gmcp_candidates.restype = C.c_int
@@ -103,6 +105,8 @@ def lib():
         L.gmcp_strerror.argtypes = [C.c_int]
         L.gmcp_rule.restype = C.c_int
         L.gmcp_rule.argtypes = [C.c_int, C.POINTER(C.c_double)]
+        L.gmcp_row_classes.restype = C.c_int
+        L.gmcp_row_classes.argtypes = [P, C.POINTER(C.c_int64)]
         L.gmcp_profile.restype = C.c_int
         L.gmcp_profile.argtypes = [P, C.c_int]
         L.gmcp_profile_stages.restype = C.c_int

@@ -89,6 +89,23 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
   const int T = valid ? a.s_order[tl.first + j] : 0;
   const R dhat = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
 
+  // ---- a tile without candidates selects nothing: empty bookkeeping only
+  // (the broad phase has already checked its triangles' frames)
+  {
+    int cn = valid ? a.cand_off[T + 1] - a.cand_off[T] : 0;
+    for (int o = 32; o > 0; o >>= 1) cn = max(cn, __shfl_xor(cn, o, kWave));
+    if (cn == 0) {
+      if (valid && q == 0) {
+        a.tri_npair[T] = 0;
+        a.tri_rcnt[T] = 0;
+        a.tri_poff[T] = 0;
+        a.tri_roff[T] = 0;
+      }
+      if (lane == 0) a.tile_E[tile_id] = 0.0;
+      return;
+    }
+  }
+
   // ---- slave frame: first vertex, edges, unit normal (A2)
   R s0[3] = {0, 0, 0}, e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0}, n[3] = {0, 0, 1};
   bool degen = false;
@@ -196,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
 
   // ---- barrier, weight, sample scalars (A5)
   const bool sel = valid && bM >= 0;
-  R g = 0, c1 = 0, c2 = 0, pr = 0;
+  R g = 0, c1 = 0, c2 = 0, pr = 0, kw = 0;
   double E = 0.0;
   if (sel) {
     g = bt;
@@ -211,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
       R B = -dd * dd * L;
       R B1 = -R(2) * dd * L - dd * dd / g;
       R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
-      R kw = kappa * wk * gam;
+      kw = kappa * wk * gam;
       E = (double)(kw * B);
       c1 = kw * B1;
       c2 = fmax(kw * B2, R(0));  // PSD projection of the rank-one block
@@ -284,6 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
     r.c1 = c1;
     r.c2 = c2;
     r.p = pr;
+    r.eps = eps;
+    r.s1 = xi;
+    r.s2 = eta;
+    r.kwg = kw;
     r.pad = 0;
     a.rec[rbase + rpre] = r;
   }
@@ -346,6 +367,336 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
   }
 }
 
+// ----------------------------------------------------------- mortar samples
+// Clipped mortar face samples (Sec. 4.1, face samples): for a slave
+// triangle T and an opposing candidate master triangle M, M is projected
+// along n_T onto T's plane, expressed in T's barycentric pair (u, v) (T is
+// the reference triangle u, v >= 0, u + v <= 1), clipped by T
+// (Sutherland-Hodgman in LDS, at most 6 vertices), fan-triangulated from
+// its first vertex, and every sub-triangle carries the n x n rule.  Sample:
+// beta^s = (1 - u - v, u, v), beta^m = barycentric coordinates of the point
+// in the projected master triangle, gap g = sum_j beta^m_j h_j with h_j the
+// master vertices' heights above T's plane (= n_T . (x_m - x_s), Eq. (gap)),
+// weight w = 2 A_sub W_q with A_sub the sub-triangle's share of T's rest
+// area.  One wave per work tile, the tile's triangles in turn, lane = one
+// candidate pair (chunks of 64): a counting pass sizes the triangle's
+// records and pairs (one allocation each, so they stay contiguous and in
+// candidate order), a writing pass recomputes and writes them.  Per
+// triangle and per pair sums, energy: lane order and fixed butterflies.
+constexpr int kMortarChunks = 8;  // candidates per slave triangle <= 512 (the broad phase's set)
+
+template <typename R>
+struct MortarPair {   // one (T, M) pair, projected into T's (u, v) coordinates
+  R q[3][2];          // projected master vertices
+  R h[3];             // master vertex heights above T's plane
+  R qi[2][2];         // inverse of [q1 - q0, q2 - q0]
+  bool ok;
+};
+
+template <typename R>
+__device__ inline MortarPair<R> mortar_pair(const NarrowArgs<R> &a, int M, const R s0[3], const R e1[3],
+                                            const R e2[3], const R n[3], R gi11, R gi12, R gi22, R eps) {
+  MortarPair<R> P;
+  P.ok = false;
+  R p[3][3];
+  for (int j = 0; j < 3; ++j) {
+    const int64_t v = a.tm[3 * (int64_t)M + j];
+    for (int d = 0; d < 3; ++d) p[j][d] = a.xm[3 * v + d] - s0[d];
+  }
+  R f1[3], f2[3];
+  for (int d = 0; d < 3; ++d) {
+    f1[d] = p[1][d] - p[0][d];
+    f2[d] = p[2][d] - p[0][d];
+  }
+  const R N[3] = {f1[1] * f2[2] - f1[2] * f2[1], f1[2] * f2[0] - f1[0] * f2[2], f1[0] * f2[1] - f1[1] * f2[0]};
+  if (!(n[0] * N[0] + n[1] * N[1] + n[2] * N[2] < R(0))) return P;  // not opposing
+  R hmin = INFINITY, hmax = -INFINITY;
+  for (int j = 0; j < 3; ++j) {
+    P.h[j] = n[0] * p[j][0] + n[1] * p[j][1] + n[2] * p[j][2];
+    hmin = fmin(hmin, P.h[j]);
+    hmax = fmax(hmax, P.h[j]);
+    const R r1 = p[j][0] * e1[0] + p[j][1] * e1[1] + p[j][2] * e1[2];
+    const R r2 = p[j][0] * e2[0] + p[j][1] * e2[1] + p[j][2] * e2[2];
+    P.q[j][0] = gi11 * r1 + gi12 * r2;
+    P.q[j][1] = gi12 * r1 + gi22 * r2;
+  }
+  if (!(hmin < eps && hmax > -eps)) return P;  // every gap beyond the support band
+  const R a00 = P.q[1][0] - P.q[0][0], a01 = P.q[2][0] - P.q[0][0];
+  const R a10 = P.q[1][1] - P.q[0][1], a11 = P.q[2][1] - P.q[0][1];
+  const R det = a00 * a11 - a01 * a10;
+  if (!(fabs(det) > R(1e-14))) return P;  // master edge-on to the slave plane
+  const R id = R(1) / det;
+  P.qi[0][0] = a11 * id;
+  P.qi[0][1] = -a01 * id;
+  P.qi[1][0] = -a10 * id;
+  P.qi[1][1] = a00 * id;
+  P.ok = true;
+  return P;
+}
+
+// Sutherland-Hodgman clip of the projected master triangle by the reference
+// triangle (at most 6 vertices); the polygon lives in LDS (lane-minor),
+// returns its vertex count
+template <typename R>
+__device__ inline int mortar_clip(const MortarPair<R> &P, R (*buf)[6][2][kWave], int lane) {
+  int cnt = 3;
+  for (int j = 0; j < 3; ++j) {
+    buf[0][j][0][lane] = P.q[j][0];
+    buf[0][j][1][lane] = P.q[j][1];
+  }
+  int src = 0;
+  for (int plane = 0; plane < 3; ++plane) {
+    int out = 0;
+    const int dst = src ^ 1;
+    for (int i = 0; i < cnt; ++i) {
+      const int i1 = i + 1 == cnt ? 0 : i + 1;
+      const R pu = buf[src][i][0][lane], pv = buf[src][i][1][lane];
+      const R qu = buf[src][i1][0][lane], qv = buf[src][i1][1][lane];
+      const R fp = plane == 0 ? pu : (plane == 1 ? pv : R(1) - pu - pv);
+      const R fq = plane == 0 ? qu : (plane == 1 ? qv : R(1) - qu - qv);
+      if (fp >= R(0)) {
+        buf[dst][out][0][lane] = pu;
+        buf[dst][out][1][lane] = pv;
+        ++out;
+        if (fq < R(0)) {
+          const R t = fp / (fp - fq);
+          buf[dst][out][0][lane] = pu + (qu - pu) * t;
+          buf[dst][out][1][lane] = pv + (qv - pv) * t;
+          ++out;
+        }
+      } else if (fq >= R(0)) {
+        const R t = fp / (fp - fq);
+        buf[dst][out][0][lane] = pu + (qu - pu) * t;
+        buf[dst][out][1][lane] = pv + (qv - pv) * t;
+        ++out;
+      }
+    }
+    cnt = out;
+    src = dst;
+    if (cnt == 0) break;
+  }
+  if (src != 0)  // leave the result in buffer 0
+    for (int i = 0; i < cnt; ++i) {
+      buf[0][i][0][lane] = buf[1][i][0][lane];
+      buf[0][i][1][lane] = buf[1][i][1][lane];
+    }
+  return cnt;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
+  __shared__ R poly[2][6][2][kWave];
+  __shared__ uint64_t maskbuf[kMortarChunks][kWave];  // accepted samples of each lane's pair (bit (s-1) nq + q)
+  const int lane = threadIdx.x;
+  const int tile_id = xcd_block(blockIdx.x, gridDim.x);
+  if (tile_id >= a.n_tiles) return;
+  if (a.cand_off[a.Ts] > a.cap_cand) return;
+  const Tile tl = a.tiles[tile_id];
+  const EnvInfo &ev = a.env[tl.env];
+  const R eps = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
+  const int nq = ev.nq;
+  const double *rule = a.rule + (ev.rule_n - 1) * 16 * 3;
+  R(*buf)[6][2][kWave] = poly;
+  double E = 0.0;
+  const uint64_t below = (1ull << lane) - 1;
+  for (int j = 0; j < tl.count; ++j) {
+    const int T = a.s_order[tl.first + j];
+    const int cb = a.cand_off[T], cn = a.cand_off[T + 1] - cb;
+    // slave frame
+    R s0[3], e1[3], e2[3], n[3];
+    {
+      const int64_t v0 = a.ts[3 * (int64_t)T], v1 = a.ts[3 * (int64_t)T + 1], v2 = a.ts[3 * (int64_t)T + 2];
+      for (int d = 0; d < 3; ++d) {
+        s0[d] = a.xs[3 * v0 + d];
+        e1[d] = a.xs[3 * v1 + d] - s0[d];
+        e2[d] = a.xs[3 * v2 + d] - s0[d];
+      }
+    }
+    const R c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const R len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    const R g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    const R g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+    const R g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const bool good = cn > 0 && isfinite(len) && len > R(1e-14) * (g11 + g22);
+    if (cn > 0 && !good && lane == 0)
+      set_error(a.st, isfinite(len) ? GMCP_E_DEGENERATE : GMCP_E_NONFINITE, (unsigned long long)T);
+    if (!good) {
+      if (lane == 0) {
+        a.tri_npair[T] = 0;
+        a.tri_rcnt[T] = 0;
+        a.tri_poff[T] = 0;
+        a.tri_roff[T] = 0;
+      }
+      continue;
+    }
+    for (int d = 0; d < 3; ++d) n[d] = c[d] / len;
+    const R gdet = g11 * g22 - g12 * g12;
+    const R gi11 = g22 / gdet, gi12 = -g12 / gdet, gi22 = g11 / gdet;
+    const R area = a.area[T];
+    const int nchunk = (cn + kWave - 1) / kWave;
+
+    // ---- counting pass: active samples per candidate pair
+    int nrec = 0, npair = 0;
+    bool pen = false;
+    for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
+      const int ci = ch * kWave + lane;
+      uint64_t mask = 0;
+      if (ci < cn) {
+        const MortarPair<R> P = mortar_pair(a, a.cand[cb + ci], s0, e1, e2, n, gi11, gi12, gi22, eps);
+        if (P.ok) {
+          const int m = mortar_clip(P, buf, lane);
+          for (int s = 1; s + 1 < m; ++s) {
+            const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
+            const R Bu = buf[0][s][0][lane] - Au, Bv = buf[0][s][1][lane] - Av;
+            const R Cu = buf[0][s + 1][0][lane] - Au, Cv = buf[0][s + 1][1][lane] - Av;
+            if (Bu * Cv - Bv * Cu == R(0)) continue;
+            for (int qq = 0; qq < nq; ++qq) {
+              const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1];
+              const R u = Au + xi * Bu + eta * Cu, v = Av + xi * Bv + eta * Cv;
+              const R yu = u - P.q[0][0], yv = v - P.q[0][1];
+              const R b1 = P.qi[0][0] * yu + P.qi[0][1] * yv, b2 = P.qi[1][0] * yu + P.qi[1][1] * yv;
+              const R g = (R(1) - b1 - b2) * P.h[0] + b1 * P.h[1] + b2 * P.h[2];
+              if (g > R(0) && g < eps) mask |= 1ull << ((s - 1) * nq + qq);
+              else if (g > -eps && g <= R(0)) pen = true;
+            }
+          }
+        }
+      }
+      maskbuf[ch][lane] = mask;
+      const int cntl = __popcll(mask);
+      const uint64_t pm = __ballot(cntl > 0);
+      npair += __popcll(pm);
+      int tot = cntl;
+      for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
+      nrec += tot;
+    }
+    if (__any(pen) && lane == 0) set_error(a.st, GMCP_E_PENETRATION, (unsigned long long)T);
+    if (nchunk > kMortarChunks && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
+    unsigned long long rbase = 0, pbase = 0;
+    if (lane == 0) {
+      if (nrec) rbase = atomicAdd(&a.st->n_active, (unsigned long long)nrec);
+      if (npair) pbase = atomicAdd(&a.st->n_pairs, (unsigned long long)npair);
+    }
+    rbase = __shfl(rbase, 0, kWave);
+    pbase = __shfl(pbase, 0, kWave);
+    const bool rec_ok = rbase + nrec <= (unsigned long long)a.cap_active;
+    const bool pair_ok = pbase + npair <= (unsigned long long)a.cap_pairs;
+    if (lane == 0 && ((nrec && !rec_ok) || (npair && !pair_ok))) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
+    if (lane == 0) {
+      a.tri_npair[T] = npair;
+      a.tri_poff[T] = (int32_t)pbase;
+      a.tri_rcnt[T] = nrec;
+      a.tri_roff[T] = (int32_t)rbase;
+    }
+    if (nrec == 0 || !rec_ok || !pair_ok) continue;
+
+    // ---- writing pass
+    R ts_[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // c2 bs_a bs_b (00 01 02 11 12 22), c1 bs_a
+    unsigned long long roff = rbase, poff = pbase;
+    for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
+      const int ci = ch * kWave + lane;
+      const uint64_t mask = maskbuf[ch][lane];
+      const int cntl = __popcll(mask);
+      int incl = cntl;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int v = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += v;
+      }
+      const uint64_t pm = __ballot(cntl > 0);
+      unsigned long long r = roff + (unsigned long long)(incl - cntl);
+      const unsigned long long pslot = poff + __popcll(pm & below);
+      roff += __shfl(incl, kWave - 1, kWave);
+      poff += __popcll(pm);
+      if (cntl == 0) continue;
+      const int M = a.cand[cb + ci];
+      const MortarPair<R> P = mortar_pair(a, M, s0, e1, e2, n, gi11, gi12, gi22, eps);
+      mortar_clip(P, buf, lane);
+      Pair<R> pr;
+      pr.T = T;
+      pr.M = M;
+      for (int z = 0; z < 6; ++z) pr.mm[z] = 0;
+      for (int z = 0; z < 9; ++z) pr.sm[z] = 0;
+      for (int z = 0; z < 3; ++z) pr.gm[z] = 0;
+      // exactly the samples the counting pass accepted (the mask), so the
+      // records written always fill the allocated range
+      for (uint64_t bits = mask; bits; bits &= bits - 1) {
+        const int idx = __ffsll((unsigned long long)bits) - 1;
+        const int s = idx / nq + 1, qq = idx - (s - 1) * nq;
+        const int s1i = s < 5 ? s : 4, s2i = s + 1 < 6 ? s + 1 : 5;  // in-range LDS reads
+        const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
+        const R Bu = buf[0][s1i][0][lane] - Au, Bv = buf[0][s1i][1][lane] - Av;
+        const R Cu = buf[0][s2i][0][lane] - Au, Cv = buf[0][s2i][1][lane] - Av;
+        const R a2 = fabs(Bu * Cv - Bv * Cu);  // twice the (u, v) area
+        {
+          const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1], wq = (R)rule[3 * qq + 2];
+          const R u = Au + xi * Bu + eta * Cu, v = Av + xi * Bv + eta * Cv;
+          const R yu = u - P.q[0][0], yv = v - P.q[0][1];
+          const R b1 = P.qi[0][0] * yu + P.qi[0][1] * yv, b2 = P.qi[1][0] * yu + P.qi[1][1] * yv;
+          const R b0 = R(1) - b1 - b2;
+          // the counting pass accepted 0 < g < eps; a recomputation that
+          // rounds differently is clamped into the band
+          const R g = fmin(fmax(b0 * P.h[0] + b1 * P.h[1] + b2 * P.h[2], eps * R(1e-6)), eps);
+          const R gam = deltaT > R(0) ? hermite(fmin(b0, fmin(b1, b2)), deltaT) : R(1);
+          const R wk = R(2) * (a2 * area) * wq;
+          const R dd = g - eps;
+          const R L = log1p_r<R>(dd / eps);
+          const R B = -dd * dd * L;
+          const R B1 = -R(2) * dd * L - dd * dd / g;
+          const R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
+          const R kw = kappa * wk * gam;
+          const R c1 = kw * B1, c2 = fmax(kw * B2, R(0));
+          E += (double)(kw * B);
+          const R bs[3] = {R(1) - u - v, u, v}, bm[3] = {b0, b1, b2};
+          ts_[0] += c2 * bs[0] * bs[0];
+          ts_[1] += c2 * bs[0] * bs[1];
+          ts_[2] += c2 * bs[0] * bs[2];
+          ts_[3] += c2 * bs[1] * bs[1];
+          ts_[4] += c2 * bs[1] * bs[2];
+          ts_[5] += c2 * bs[2] * bs[2];
+          for (int z = 0; z < 3; ++z) ts_[6 + z] += c1 * bs[z];
+          pr.mm[0] += c2 * bm[0] * bm[0];
+          pr.mm[1] += c2 * bm[0] * bm[1];
+          pr.mm[2] += c2 * bm[0] * bm[2];
+          pr.mm[3] += c2 * bm[1] * bm[1];
+          pr.mm[4] += c2 * bm[1] * bm[2];
+          pr.mm[5] += c2 * bm[2] * bm[2];
+          for (int s2 = 0; s2 < 3; ++s2)
+            for (int m2 = 0; m2 < 3; ++m2) pr.sm[3 * s2 + m2] -= c2 * bs[s2] * bm[m2];
+          for (int m2 = 0; m2 < 3; ++m2) pr.gm[m2] += c1 * bm[m2];
+          Rec<R> rc;
+          rc.k = -1;
+          rc.M = M;
+          rc.T = T;
+          rc.q = -1;
+          rc.g = g;
+          rc.b0 = b0;
+          rc.b1 = b1;
+          rc.b2 = b2;
+          rc.c1 = c1;
+          rc.c2 = c2;
+          rc.p = -kappa * gam * B1;
+          rc.eps = eps;
+          rc.s1 = u;
+          rc.s2 = v;
+          rc.kwg = kw;
+          rc.pad = 0;
+          a.rec[r++] = rc;
+        }
+      }
+      a.pair[pslot] = pr;
+    }
+    for (int z = 0; z < 9; ++z)
+      for (int o = 32; o > 0; o >>= 1) ts_[z] += __shfl_xor(ts_[z], o, kWave);
+    if (lane == 0) {
+      for (int z = 0; z < 9; ++z) a.tri_sum[9 * (int64_t)T + z] = ts_[z];
+      for (int d = 0; d < 3; ++d) a.tri_nrm[3 * (int64_t)T + d] = n[d];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, kWave);
+  if (lane == 0) a.tile_E[tile_id] = E;
+}
+
+
 // ---------------------------------------------------- pairs by master tri
 // pass 0: count pairs per master triangle; pass 1: place (slave triangle,
 // pair) keys into the buckets in arrival order (counters return to zero)
@@ -391,6 +742,8 @@ struct RowArgs {
   const R *tri_sum, *tri_nrm;
   const Pair<R> *pair;
   const int32_t *mp_off, *mp_list;
+  const long long *mp_key;   // bucket slots: slave triangle << 32 | pair
+  const R *mtri;             // per-master-triangle blocks and gradient (k_mtri)
   const DevStatus *st_r;
   DevStatus *st;
   int64_t cap_pairs;
@@ -403,6 +756,7 @@ struct RowArgs {
 };
 
 constexpr int kRowWaves = 2;
+constexpr int kRowBlocks = 4096;  // fixed grid of the list-walking row kernels
 
 // slot of column `col` in an open-addressing table of `slots` (power of 2)
 __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full) {
@@ -416,19 +770,115 @@ __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full)
   return -1;
 }
 
-// One wave per BSR row.  pass 0 counts the distinct columns, pass 1 writes
-// them, pass 2 only computes the gradient row.  The row's contributions
-// (column, coef, slave triangle whose normal n_T it carries; block =
-// coef n_T n_T^T) are enumerated in a canonical order - source by source,
-// sources in adjacency order - and their columns inserted into an LDS hash
-// set.  In pass 1 the contributions are also kept in LDS (rows longer than
-// kRowEnt re-walk their sources instead); each lane then owns one distinct
-// column and sums its contributions in the canonical order, so the float
-// sums are the same on every run.  Columns are ranked and written ascending.
+// One wave per master triangle with contact pairs: the sum over its pairs
+// (bucket order: sorted by slave triangle) of the master-master sums times
+// n_T n_T^T - six vertex pairs (00 01 02 11 12 22) of six symmetric entries -
+// and of the gradient sums gm_j n_T (three vertices).  Lane partials are
+// combined by a fixed butterfly, so the result is the same on every run.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ pair,
+                                                    const int32_t *__restrict__ mp_off,
+                                                    const int32_t *__restrict__ mp_list,
+                                                    const R *__restrict__ tri_nrm, int64_t Tm, const DevStatus *st,
+                                                    int64_t cap_pairs, R *__restrict__ mtri) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t t = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (t >= Tm || (int64_t)st->n_pairs > cap_pairs) return;
+  const int b = mp_off[t], e = mp_off[t + 1];
+  if (b == e) return;
+  R h[36], g[9];
+  for (int z = 0; z < 36; ++z) h[z] = 0;
+  for (int z = 0; z < 9; ++z) g[z] = 0;
+  for (int i = b + lane; i < e; i += kWave) {
+    const Pair<R> &P = pair[mp_list[i]];
+    const R *nn = tri_nrm + 3 * (int64_t)P.T;
+    const R n0 = nn[0], n1 = nn[1], n2 = nn[2];
+    const R o[6] = {n0 * n0, n0 * n1, n0 * n2, n1 * n1, n1 * n2, n2 * n2};
+    for (int v = 0; v < 6; ++v)
+      for (int c = 0; c < 6; ++c) h[6 * v + c] += P.mm[v] * o[c];
+    for (int m = 0; m < 3; ++m) {
+      g[3 * m + 0] += P.gm[m] * n0;
+      g[3 * m + 1] += P.gm[m] * n1;
+      g[3 * m + 2] += P.gm[m] * n2;
+    }
+  }
+  for (int z = 0; z < 36; ++z)
+    for (int o = 32; o > 0; o >>= 1) h[z] += __shfl_xor(h[z], o, kWave);
+  for (int z = 0; z < 9; ++z)
+    for (int o = 32; o > 0; o >>= 1) g[z] += __shfl_xor(g[z], o, kWave);
+  if (lane == 0) {
+    R *out = mtri + 45 * t;
+    for (int z = 0; z < 36; ++z) out[z] = h[z];
+    for (int z = 0; z < 9; ++z) out[36 + z] = g[z];
+  }
+}
+
+// Thread per BSR row: counts the row's contributions (the entries the row
+// kernel enumerates).  Rows without any get their count and gradient zeroed
+// here; the others are listed for the wave kernels - light rows (at most
+// kLightEnt entries, the common case) and heavy rows (master vertices under
+// a much finer slave mesh) in separate lists, so that the light rows run
+// with small LDS tables and full occupancy.  Nothing is listed when the
+// pair records overflowed.
+constexpr int kLightEnt = 256;
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__restrict__ rlist,
+                                                       int32_t *__restrict__ rcount, int zero_cnt) {
+  const int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  int n_ent = 0;
+  if (row < a.V) {
+    if ((int64_t)a.st_r->n_pairs <= a.cap_pairs) {
+      const bool slave = row < a.Vs;
+      const int64_t vid = slave ? row : row - a.Vs;
+      const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
+      const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
+      for (int src = sb; src < se; ++src) {
+        const int t = (slave ? a.s_vt[src] : a.m_vt[src]) >> 2;
+        const int np = slave ? a.tri_npair[t] : a.mp_off[t + 1] - a.mp_off[t];
+        if (np > 0) n_ent += 3 + ((slave && a.kinematic) ? 0 : 3 * np);
+      }
+    }
+    if (n_ent == 0) {
+      if (zero_cnt) a.row_cnt[row] = 0;
+      if (a.grad)
+        for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = R(0);
+    }
+  }
+  const uint64_t ml = __ballot(n_ent > 0 && n_ent <= kLightEnt), mh = __ballot(n_ent > kLightEnt);
+  int bl = 0, bh = 0;
+  if (lane == 0 && ml) bl = atomicAdd(&rcount[0], __popcll(ml));
+  if (lane == 0 && mh) bh = atomicAdd(&rcount[1], __popcll(mh));
+  bl = __shfl(bl, 0, kWave);
+  bh = __shfl(bh, 0, kWave);
+  const uint64_t below = (1ull << lane) - 1;
+  if (n_ent > 0 && n_ent <= kLightEnt) rlist[bl + __popcll(ml & below)] = (int32_t)row;
+  if (n_ent > kLightEnt) rlist[a.V + bh + __popcll(mh & below)] = (int32_t)row;
+}
+
+// One wave per listed BSR row (k_row_pre), a fixed grid walking the list.
+//   PASS 0 counts the distinct columns, PASS 1 writes columns and values,
+//   PASS 2 only computes the gradient row, PASS 3 fills the slave columns of
+//   master rows.
+// Slave row a: its contributions (column, coef, slave triangle T whose
+// n_T n_T^T the coef multiplies) are enumerated in a canonical order - the
+// incident triangles in adjacency order, each with its own three vertices
+// and then its pairs' master vertices - and their columns inserted into an
+// LDS hash set; in PASS 1 the contributions are also kept in LDS (rows
+// longer than kRowEnt re-walk their sources), each lane owns one distinct
+// column and sums its contributions in the canonical order.
+// Master row j: master columns take the per-master-triangle blocks of
+// k_mtri, summed over the incident triangles in adjacency order; slave
+// columns a are the slave vertices of the pairs of those triangles, and
+// their blocks equal block (a, j) of slave row a (each contribution is a
+// symmetric coef n n^T), so PASS 3 copies them after PASS 1 has written the
+// slave rows.  Columns are ranked and written ascending.
 constexpr int kRowEnt = 512;
 
-template <typename R, int PASS>
-__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots) {
+template <typename R, int PASS, bool HEAVY>  // HEAVY: the heavy-row list (large LDS tables), same code
+__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots, const int32_t *__restrict__ rlist,
+                                                           int32_t *__restrict__ rcount) {
   constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -438,47 +888,148 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   int32_t *ecol = dense + slots;
   int32_t *etri = ecol + kRowEnt;
   R *ecoef = reinterpret_cast<R *>(etri + kRowEnt);
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
-  if (row >= a.V) return;
-  if ((int64_t)a.st_r->n_pairs > a.cap_pairs) {
-    if (pass == 0 && lane == 0) a.row_cnt[row] = 0;
+  if ((pass == 1 || pass == 3) && (int64_t)a.row_ptr[a.V] > a.cap_nnzb) return;
+  // the waves walk the list of rows with contributions (k_row_pre)
+  const int64_t nlist = *rcount;
+  const int nw = blockDim.x / kWave;
+  for (int64_t li = (int64_t)blockIdx.x * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
+    [&](const int64_t row) {
+  wave_sync();  // the previous row's LDS reads are done
+  const bool slave = row < a.Vs;
+
+  if (pass == 3) {
+    if (slave) return;
+    const int64_t e1 = a.row_ptr[row + 1];
+    for (int64_t e = a.row_ptr[row] + lane; e < e1; e += kWave) {
+      const int32_t c = a.col[e];
+      if (c >= a.Vs) break;  // columns ascend: the slave columns come first
+      int64_t lo = a.row_ptr[c], hi = a.row_ptr[c + 1];
+      const int64_t end = hi;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.col[mid] < row) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < end && a.col[lo] == row) {
+        for (int z = 0; z < 9; ++z) a.val[9 * e + z] = a.val[9 * lo + z];
+      } else {
+        set_error(a.st, GMCP_E_CAPACITY, (unsigned long long)row);  // unreachable: the patterns are symmetric
+      }
+    }
     return;
   }
-  if (pass == 1 && (int64_t)a.row_ptr[a.V] > a.cap_nnzb) return;
-  const bool slave = row < a.Vs;
+
   const int64_t vid = slave ? row : row - a.Vs;
   const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
   const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
 
-  // contributions of one source (incident triangle), in canonical order
-  auto src_count = [&](int src) -> int {
-    int t = (slave ? a.s_vt[src] : a.m_vt[src]) >> 2;
-    if (slave) {
-      int np = a.tri_npair[t];
-      return np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
+  if (!slave) {
+    // ------------------------------------------------------ master row
+    if (pass != 0 && a.grad && lane == 0) {
+      R gr[3] = {0, 0, 0};
+      for (int src = sb; src < se; ++src) {
+        const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
+        if (a.mp_off[t] == a.mp_off[t + 1]) continue;
+        const R *G = a.mtri + 45 * (int64_t)t + 36 + 3 * corner;
+        for (int d = 0; d < 3; ++d) gr[d] += G[d];
+      }
+      for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = gr[d];
     }
-    return 6 * (a.mp_off[t + 1] - a.mp_off[t]);
-  };
-  auto visit_src = [&](int src, auto &&visit) {
-    int ent = slave ? a.s_vt[src] : a.m_vt[src];
-    int t = ent >> 2, corner = ent & 3;
-    if (slave) {
-      if (a.tri_npair[t] == 0) return;
-      const R *S = a.tri_sum + 9 * (int64_t)t;
-      for (int b = 0; b < 3; ++b) visit(a.ts[3 * (int64_t)t + b], S[sym3(corner, b)], t);
-      if (!a.kinematic) {
-        int pb = a.tri_poff[t], np = a.tri_npair[t];
-        for (int p = pb; p < pb + np; ++p) {
-          const Pair<R> &P = a.pair[p];
-          for (int m = 0; m < 3; ++m) visit((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * corner + m], t);
+    if (pass == 2) return;
+    int n_ent = 0;
+    for (int src = sb + lane; src < se; src += kWave) {
+      const int t = a.m_vt[src] >> 2;
+      const int np = a.mp_off[t + 1] - a.mp_off[t];
+      n_ent += np ? 3 + 3 * np : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
+    if (n_ent == 0) {
+      if (pass == 0 && lane == 0) a.row_cnt[row] = 0;
+      return;
+    }
+    int tsz = 64;
+    while (tsz < 2 * n_ent && tsz < slots) tsz <<= 1;
+    for (int i = lane; i < tsz; i += kWave) key[i] = -1;
+    wave_sync();
+    bool full = false;
+    for (int src = sb; src < se; ++src) {
+      const int t = a.m_vt[src] >> 2;
+      const int pb = a.mp_off[t], pe = a.mp_off[t + 1];
+      if (pb == pe) continue;
+      if (lane < 3) row_slot(key, tsz, (int32_t)(a.Vs + a.tm[3 * (int64_t)t + lane]), &full);
+      for (int i = pb + lane; i < pe; i += kWave) {
+        const int64_t T = a.mp_key[i] >> 32;
+        for (int s = 0; s < 3; ++s) row_slot(key, tsz, a.ts[3 * T + s], &full);
+      }
+    }
+    if (__any(full)) {
+      if (lane == 0) {
+        atomicMax(&a.st->need_row, (unsigned long long)(2 * slots));
+        atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
+        if (pass == 0) a.row_cnt[row] = 0;
+      }
+      return;
+    }
+    wave_sync();
+    int nuniq = 0;
+    for (int i0 = 0; i0 < tsz; i0 += kWave) {
+      const int i = i0 + lane;
+      const bool used = i < tsz && key[i] >= 0;
+      const uint64_t m = __ballot(used);
+      if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = key[i];
+      nuniq += __popcll(m);
+    }
+    if (pass == 0) {
+      if (lane == 0) {
+        a.row_cnt[row] = nuniq;
+        atomicAdd(&rcount[2 + (HEAVY ? 1 : 0)], nuniq);  // blocks per row class
+      }
+      return;
+    }
+    wave_sync();
+    for (int u = lane; u < nuniq; u += kWave) {
+      const int32_t c = dense[u];
+      int r = 0;
+      for (int m = 0; m < nuniq; ++m) r += dense[m] < c;
+      const int64_t dst = (int64_t)a.row_ptr[row] + r;
+      a.col[dst] = c;
+      if (c < a.Vs) continue;  // slave column: PASS 3
+      R v[6] = {0, 0, 0, 0, 0, 0};
+      for (int src = sb; src < se; ++src) {
+        const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
+        if (a.mp_off[t] == a.mp_off[t + 1]) continue;
+        for (int m = 0; m < 3; ++m) {
+          if ((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]) != c) continue;
+          const R *B = a.mtri + 45 * (int64_t)t + 6 * sym3(corner, m);
+          for (int z = 0; z < 6; ++z) v[z] += B[z];
         }
       }
-    } else {
-      for (int i = a.mp_off[t]; i < a.mp_off[t + 1]; ++i) {
-        const Pair<R> &P = a.pair[a.mp_list[i]];
-        for (int m = 0; m < 3; ++m)
-          visit((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]), P.mm[sym3(corner, m)], P.T);
-        for (int s = 0; s < 3; ++s) visit(a.ts[3 * (int64_t)P.T + s], P.sm[3 * s + corner], P.T);
+      R *ov = a.val + 9 * dst;
+      ov[0] = v[0]; ov[1] = v[1]; ov[2] = v[2];
+      ov[3] = v[1]; ov[4] = v[3]; ov[5] = v[4];
+      ov[6] = v[2]; ov[7] = v[4]; ov[8] = v[5];
+    }
+    return;
+  }
+
+  // -------------------------------------------------------- slave row
+  // contributions of one source (incident triangle), in canonical order
+  auto src_count = [&](int src) -> int {
+    const int t = a.s_vt[src] >> 2;
+    const int np = a.tri_npair[t];
+    return np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
+  };
+  auto visit_src = [&](int src, auto &&visit) {
+    const int ent = a.s_vt[src];
+    const int t = ent >> 2, corner = ent & 3;
+    if (a.tri_npair[t] == 0) return;
+    const R *S = a.tri_sum + 9 * (int64_t)t;
+    for (int b = 0; b < 3; ++b) visit(a.ts[3 * (int64_t)t + b], S[sym3(corner, b)], t);
+    if (!a.kinematic) {
+      const int pb = a.tri_poff[t], np = a.tri_npair[t];
+      for (int p = pb; p < pb + np; ++p) {
+        const Pair<R> &P = a.pair[p];
+        for (int m = 0; m < 3; ++m) visit((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * corner + m], t);
       }
     }
   };
@@ -487,25 +1038,15 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   for (int src = sb + lane; src < se; src += kWave) n_ent += src_count(src);
   for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
   if (pass != 0 && a.grad) {
-    // gradient row: slave a: sum_T -gs[T][a] n_T; master j: sum over the
-    // pairs of its master triangles of gm[j] n_T (lane partials, fixed-order
-    // butterfly)
+    // gradient row: sum over incident triangles of -gs[T][a] n_T (lane
+    // partials, fixed-order butterfly)
     R gr[3] = {0, 0, 0};
     for (int src = sb + lane; src < se; src += kWave) {
-      int ent = slave ? a.s_vt[src] : a.m_vt[src];
-      int t = ent >> 2, corner = ent & 3;
-      if (slave) {
-        if (a.tri_npair[t] == 0) continue;
-        R cf = -a.tri_sum[9 * (int64_t)t + 6 + corner];
-        const R *nn = a.tri_nrm + 3 * (int64_t)t;
-        for (int d = 0; d < 3; ++d) gr[d] += cf * nn[d];
-      } else {
-        for (int i = a.mp_off[t]; i < a.mp_off[t + 1]; ++i) {
-          const Pair<R> &P = a.pair[a.mp_list[i]];
-          const R *nn = a.tri_nrm + 3 * (int64_t)P.T;
-          for (int d = 0; d < 3; ++d) gr[d] += P.gm[corner] * nn[d];
-        }
-      }
+      const int ent = a.s_vt[src], t = ent >> 2, corner = ent & 3;
+      if (a.tri_npair[t] == 0) continue;
+      const R cf = -a.tri_sum[9 * (int64_t)t + 6 + corner];
+      const R *nn = a.tri_nrm + 3 * (int64_t)t;
+      for (int d = 0; d < 3; ++d) gr[d] += cf * nn[d];
     }
     for (int d = 0; d < 3; ++d)
       for (int o = 32; o > 0; o >>= 1) gr[d] += __shfl_xor(gr[d], o, kWave);
@@ -529,7 +1070,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     const int cnt = src < se ? src_count(src) : 0;
     int incl = cnt;
     for (int d = 1; d < kWave; d <<= 1) {
-      int v = __shfl_up(incl, d, kWave);
+      const int v = __shfl_up(incl, d, kWave);
       if (lane >= d) incl += v;
     }
     int o = run + incl - cnt;
@@ -556,14 +1097,17 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   wave_sync();
   int nuniq = 0;
   for (int i0 = 0; i0 < tsz; i0 += kWave) {
-    int i = i0 + lane;
-    bool used = i < tsz && key[i] >= 0;
-    uint64_t m = __ballot(used);
+    const int i = i0 + lane;
+    const bool used = i < tsz && key[i] >= 0;
+    const uint64_t m = __ballot(used);
     if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = key[i];
     nuniq += __popcll(m);
   }
   if (pass == 0) {
-    if (lane == 0) a.row_cnt[row] = nuniq;
+    if (lane == 0) {
+      a.row_cnt[row] = nuniq;
+      atomicAdd(&rcount[2 + (HEAVY ? 1 : 0)], nuniq);  // blocks per row class
+    }
     return;
   }
   wave_sync();
@@ -594,6 +1138,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     ov[3] = v[1]; ov[4] = v[3]; ov[5] = v[4];
     ov[6] = v[2]; ov[7] = v[4]; ov[8] = v[5];
   }
+    }(rlist[li]);
 }
 
 
@@ -722,7 +1267,6 @@ __global__ void k_hvp_tri(const Rec<R> *__restrict__ rec, const int32_t *__restr
   if (rc == 0) return;
   int rb = tri_roff[T];
   const R *nn = tri_nrm + 3 * T;
-  const EnvInfo &ev = env[s_env[T]];
   R vs[3];
   for (int a = 0; a < 3; ++a) {
     const R *v = vx + 3 * (int64_t)ts[3 * T + a];
@@ -745,8 +1289,7 @@ __global__ void k_hvp_tri(const Rec<R> *__restrict__ rec, const int32_t *__restr
     for (int i = rb; i < rb + rc; ++i) {
       const Rec<R> &r = rec[i];
       if (r.M != P.M) continue;
-      const double *rq = rule + ((ev.rule_n - 1) * 16 + r.q) * 3;
-      R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
+      R bs[3] = {R(1) - r.s1 - r.s2, r.s1, r.s2};
       R bm[3] = {r.b0, r.b1, r.b2};
       R dot = -(bs[0] * vs[0] + bs[1] * vs[1] + bs[2] * vs[2]) + bm[0] * vm[0] + bm[1] * vm[1] + bm[2] * vm[2];
       if (vd) dot += vd[r.k];
@@ -784,6 +1327,8 @@ RowArgs<R> row_args(gmcp_ctx *c, const gmcp_bsr *H) {
   ra.pair = (const Pair<R> *)b.pair;
   ra.mp_off = b.mp_off;
   ra.mp_list = b.mp_list;
+  ra.mp_key = b.mp_key;
+  ra.mtri = (const R *)b.mtri;
   ra.st_r = b.status;
   ra.st = b.status;
   ra.cap_pairs = c->caps.pairs;
@@ -844,8 +1389,12 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.tile_E = b.tile_E;
   na.st = b.status;
   prof_mark(c, ST_NARROW, 0);
-  if (c->n_tiles)
-    hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, kTilePerBlock)), dim3(kThreads), 0, s, na);
+  if (c->n_tiles) {
+    if (c->mortar)
+      hipLaunchKernelGGL(k_mortar<R>, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
+    else
+      hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, kTilePerBlock)), dim3(kThreads), 0, s, na);
+  }
   prof_mark(c, ST_NARROW, 1);
   hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(256), 0, s, b.tile_E, b.env, energy);
   // bucket pairs by master triangle (needed for master rows and the HVP)
@@ -863,30 +1412,65 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   prof_mark(c, ST_BUCKET, 1);
   RowArgs<R> ra = row_args<R>(c, H);
   ra.grad = grad;
+  const int nw = kRowWaves;
+  if (!c->kinematic && (grad || H) && c->Tm) {
+    prof_mark(c, ST_MTRI, 0);
+    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads / kWave)), dim3(kThreads), 0, s, pr, b.mp_off,
+                       b.mp_list, (const R *)b.tri_nrm, c->Tm, b.status, c->caps.pairs, (R *)b.mtri);
+    prof_mark(c, ST_MTRI, 1);
+  }
+  if (grad || H) {
+    e = fill_i32(c, b.rcount, 0, 4);
+    if (e != hipSuccess) return e;
+    prof_mark(c, ST_ROWS_PRE, 0);
+    if (c->V)
+      hipLaunchKernelGGL(k_row_pre<R>, dim3(nblk(c->V)), dim3(kThreads), 0, s, ra, b.rlist, b.rcount, H ? 1 : 0);
+    prof_mark(c, ST_ROWS_PRE, 1);
+  }
+  // the row kernels walk the two row lists with fixed grids: light rows with
+  // small LDS tables, heavy rows with tables of up to 4096 slots
+  const int64_t rneed = (c->V + nw - 1) / nw;
+  const dim3 rgrid((unsigned)(rneed < kRowBlocks ? (rneed > 0 ? rneed : 1) : kRowBlocks));
+  const dim3 hgrid(256);
+  const int32_t *light = b.rlist, *heavy = b.rlist + c->V;
+  int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
     prof_mark(c, ST_GRAD, 0);
-    hipLaunchKernelGGL((k_rows<R, 2>), dim3((unsigned)((c->V + kRowWaves - 1) / kRowWaves)), dim3(kWave * kRowWaves),
-                       0, s, ra, 64);
+    hipLaunchKernelGGL((k_rows<R, 2, false>), rgrid, dim3(kWave * nw), 0, s, ra, 64, light, nlight);
+    hipLaunchKernelGGL((k_rows<R, 2, true>), hgrid, dim3(kWave * nw), 0, s, ra, 64, heavy, nheavy);
     prof_mark(c, ST_GRAD, 1);
   }
   if (H) {
-    // per wave: distinct-column set and list (8 B per slot, <= 1024 slots),
-    // plus the row's contributions in the writing pass (<= kRowEnt)
-    int slots = 64;
-    while (slots < c->caps.row_entries && slots < 1024) slots <<= 1;
-    const int nw = kRowWaves;
-    unsigned rb = (unsigned)((c->V + nw - 1) / nw);
-    size_t lds0 = (size_t)nw * slots * 8, lds1 = (size_t)nw * ((size_t)slots * 8 + (size_t)kRowEnt * (8 + sizeof(R)));
+    // per wave: distinct-column set and list (8 B per slot) plus, in the
+    // writing pass, the row's contributions (<= kRowEnt)
+    const int lslots = 2 * kLightEnt;
+    int hslots = 1024;
+    while (hslots < c->caps.row_entries && hslots < 4096) hslots <<= 1;
+    auto lds = [&](int sl, int pass) {
+      return (size_t)nw * ((size_t)sl * 8 + (pass == 1 ? (size_t)kRowEnt * (8 + sizeof(R)) : 0));
+    };
     e = fill_i32(c, b.row_cnt + c->V, 0, 1);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_COUNT, 0);
-    hipLaunchKernelGGL((k_rows<R, 0>), dim3(rb), dim3(kWave * nw), lds0, s, ra, slots);
+    hipLaunchKernelGGL((k_rows<R, 0, false>), rgrid, dim3(kWave * nw), lds(lslots, 0), s, ra, lslots, light, nlight);
     prof_mark(c, ST_ROWS_COUNT, 1);
+    prof_mark(c, ST_ROWS_COUNT_H, 0);
+    hipLaunchKernelGGL((k_rows<R, 0, true>), hgrid, dim3(kWave * nw), lds(hslots, 0), s, ra, hslots, heavy, nheavy);
+    prof_mark(c, ST_ROWS_COUNT_H, 1);
     e = scan_exclusive(c, b.row_cnt, H->row_ptr, c->V + 1);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_FILL, 0);
-    hipLaunchKernelGGL((k_rows<R, 1>), dim3(rb), dim3(kWave * nw), lds1, s, ra, slots);
+    hipLaunchKernelGGL((k_rows<R, 1, false>), rgrid, dim3(kWave * nw), lds(lslots, 1), s, ra, lslots, light, nlight);
     prof_mark(c, ST_ROWS_FILL, 1);
+    prof_mark(c, ST_ROWS_FILL_H, 0);
+    hipLaunchKernelGGL((k_rows<R, 1, true>), hgrid, dim3(kWave * nw), lds(hslots, 1), s, ra, hslots, heavy, nheavy);
+    prof_mark(c, ST_ROWS_FILL_H, 1);
+    if (c->V > c->Vs) {
+      prof_mark(c, ST_ROWS_COPY, 0);
+      hipLaunchKernelGGL((k_rows<R, 3, false>), rgrid, dim3(kWave * nw), 0, s, ra, lslots, light, nlight);
+      hipLaunchKernelGGL((k_rows<R, 3, true>), hgrid, dim3(kWave * nw), 0, s, ra, hslots, heavy, nheavy);
+      prof_mark(c, ST_ROWS_COPY, 1);
+    }
     hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, s, H->row_ptr, c->V, b.status, H->cap_nnzb);
   }
   return hipGetLastError();
@@ -925,12 +1509,92 @@ hipError_t launch_sample_results(gmcp_ctx *c, int32_t *M, R *g, R *bm, R *c1, R 
   return hipGetLastError();
 }
 
+
+// Energy of the last assembly's samples at new positions, every sample
+// frozen: slave triangle normal n_T, rule point, master triangle and its
+// barycentric coordinates, weight, face weight and support radius.  The gap
+// is then affine in x, g = n_T . (sum_j bm_j x_mj - sum_a bs_a x_sa), and the
+// gradient of this energy at the assembly positions is the assembled
+// gradient (Sec. 4.2's gradient and Hessian approximation).  One wave per
+// work tile, lane = triangle of the tile looping over its records (in lane
+// order), a fixed butterfly per tile: deterministic.  A gap <= 0 gives +inf.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_energy_frozen(const R *__restrict__ xs, const R *__restrict__ xm,
+                                                             const int32_t *__restrict__ ts,
+                                                             const int32_t *__restrict__ tm,
+                                                             const Tile *__restrict__ tiles, int n_tiles,
+                                                             const int32_t *__restrict__ s_order,
+                                                             const EnvInfo *__restrict__ env,
+                                                             const double *__restrict__ rule, const R *__restrict__ area,
+                                                             const Rec<R> *__restrict__ rec,
+                                                             const int32_t *__restrict__ tri_roff,
+                                                             const int32_t *__restrict__ tri_rcnt,
+                                                             const R *__restrict__ tri_nrm, const DevStatus *st,
+                                                             int64_t cap_active, double *__restrict__ tile_E) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int tile_id = blockIdx.x * kTilePerBlock + w;
+  if (tile_id >= n_tiles) return;
+  if ((int64_t)st->n_active > cap_active) {
+    if (lane == 0) tile_E[tile_id] = NAN;
+    return;
+  }
+  const Tile tl = tiles[tile_id];
+  double E = 0.0;
+  if (lane < tl.count) {
+    const int T = s_order[tl.first + lane];
+    const int r0 = tri_roff[T], r1 = r0 + tri_rcnt[T];
+    if (r1 > r0) {
+      R s0[3], e1[3], e2[3];
+      const int64_t v0 = ts[3 * (int64_t)T], v1 = ts[3 * (int64_t)T + 1], v2 = ts[3 * (int64_t)T + 2];
+      for (int d = 0; d < 3; ++d) {
+        s0[d] = xs[3 * v0 + d];
+        e1[d] = xs[3 * v1 + d] - s0[d];
+        e2[d] = xs[3 * v2 + d] - s0[d];
+      }
+      const R n0 = tri_nrm[3 * (int64_t)T], n1 = tri_nrm[3 * (int64_t)T + 1], n2 = tri_nrm[3 * (int64_t)T + 2];
+      for (int r = r0; r < r1; ++r) {
+        const Rec<R> rc = rec[r];
+        const R xi = rc.s1, eta = rc.s2;
+        const int64_t m0 = tm[3 * (int64_t)rc.M], m1 = tm[3 * (int64_t)rc.M + 1], m2 = tm[3 * (int64_t)rc.M + 2];
+        R dv[3];
+        for (int d = 0; d < 3; ++d)
+          dv[d] = rc.b0 * (xm[3 * m0 + d] - s0[d]) + rc.b1 * (xm[3 * m1 + d] - s0[d]) +
+                  rc.b2 * (xm[3 * m2 + d] - s0[d]) - (xi * e1[d] + eta * e2[d]);
+        const R g = n0 * dv[0] + n1 * dv[1] + n2 * dv[2];
+        const R eps = rc.eps;
+        if (!(g > R(0))) {
+          E = INFINITY;
+        } else if (g < eps) {
+          const R dd = g - eps;
+          const R B = -dd * dd * log1p_r<R>(dd / eps);
+          E += (double)(rc.kwg * B);
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, kWave);
+  if (lane == 0) tile_E[tile_id] = E;
+}
+
+template <typename R>
+hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy) {
+  Buffers &b = c->b;
+  if (c->n_tiles)
+    hipLaunchKernelGGL(k_energy_frozen<R>, dim3(nblk(c->n_tiles, kTilePerBlock)), dim3(kThreads), 0, c->stream, xs, xm,
+                       c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order, b.env, b.rule, (const R *)b.area,
+                       (const Rec<R> *)b.rec, b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, b.status, c->caps.active,
+                       b.tile_E);
+  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(256), 0, c->stream, b.tile_E, b.env, energy);
+  return hipGetLastError();
+}
+
 #define GMCP_INST(R)                                                                                            \
   template hipError_t launch_rest_area<R>(gmcp_ctx *, const R *, R *);                                          \
   template hipError_t launch_assemble<R>(gmcp_ctx *, const R *, const R *, const R *, const R *, R *, R *,      \
                                          const gmcp_bsr *);                                                     \
   template hipError_t launch_hvp<R>(gmcp_ctx *, const R *, const R *, R *, R *);                                \
-  template hipError_t launch_sample_results<R>(gmcp_ctx *, int32_t *, R *, R *, R *, R *, R *);
+  template hipError_t launch_sample_results<R>(gmcp_ctx *, int32_t *, R *, R *, R *, R *, R *);                \
+  template hipError_t launch_energy_frozen<R>(gmcp_ctx *, const R *, const R *, R *);
 GMCP_INST(float)
 GMCP_INST(double)
 

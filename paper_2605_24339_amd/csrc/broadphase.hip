@@ -275,6 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
 constexpr int kQueryWaves = kThreads / kWave;
 constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS set)
 constexpr int kMaxSlabs = 64;
+constexpr int kQueryBlocks = 2048;  // fixed grid of the list-walking query (8 blocks of 4 waves per CU)
 
 // vertex box and unit normal of slave triangle t (float, grown outward)
 template <typename R>
@@ -312,6 +313,82 @@ __device__ inline void slab_box(const float tlo[3], const float thi[3], const fl
   }
 }
 
+// Thread per slave triangle (Morton order): the slave frame check
+// (degenerate / non-finite triangles go to the status word, with the same
+// criterion as the narrow phase), the box of the whole support prism
+// {p + t n : p in T, |t| <= dhat} and the number of (master triangle, cell)
+// incidences in the grid cells it covers.  Triangles with none get an empty
+// candidate list at once; the others are appended to the query list that
+// the per-triangle wave kernel walks.  The prism box is widened by a few
+// ulps so that it covers the union of the query's slab boxes.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs, const int32_t *__restrict__ ts,
+                                                         const int32_t *__restrict__ s_order,
+                                                         const int32_t *__restrict__ s_env,
+                                                         const EnvInfo *__restrict__ env,
+                                                         const GridEnv *__restrict__ grid, int64_t Ts,
+                                                         const int32_t *__restrict__ cell_start, int64_t cap_items,
+                                                         int64_t total_cells, int32_t *__restrict__ cand_cnt,
+                                                         int32_t *__restrict__ qlist, int32_t *__restrict__ qcount,
+                                                         DevStatus *st) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  bool active = false;
+  int64_t t = -1;
+  if (i < Ts) {
+    t = s_order[i];
+    R e1[3], e2[3], s0[3];
+    for (int d = 0; d < 3; ++d) {
+      s0[d] = xs[3 * (int64_t)ts[3 * t] + d];
+      e1[d] = xs[3 * (int64_t)ts[3 * t + 1] + d] - s0[d];
+      e2[d] = xs[3 * (int64_t)ts[3 * t + 2] + d] - s0[d];
+    }
+    const R c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const R len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    const R ref = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2] + e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const bool finite = isfinite(len) && isfinite(ref) && isfinite(s0[0]) && isfinite(s0[1]) && isfinite(s0[2]);
+    if (!finite) {
+      set_error(st, GMCP_E_NONFINITE, (unsigned long long)t);
+    } else if (!(len > R(1e-14) * ref)) {
+      set_error(st, GMCP_E_DEGENERATE, (unsigned long long)t);
+    } else if (cell_start[total_cells] <= cap_items) {
+      const int e = s_env[t];
+      const GridEnv g = grid[e];
+      const float eps = (float)env[e].dhat;
+      float tlo[3], thi[3], n[3];
+      if (g.valid && tri_frame(xs, ts, t, tlo, thi, n)) {
+        float lo[3], hi[3];
+        const float ew = eps * (1.0f + 1e-5f);
+        slab_box(tlo, thi, n, -ew, ew, 4.0f * eps * 1e-6f, lo, hi);
+        if (box_hits_grid(g, lo, hi)) {
+          int c0[3], c1[3];
+          for (int d = 0; d < 3; ++d) {
+            c0[d] = cell_coord(g, lo[d], d);
+            c1[d] = cell_coord(g, hi[d], d);
+          }
+          const int64_t ncell = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+          if (ncell > 4096) {
+            active = true;  // too many cells to count here: let the wave kernel decide
+          } else {
+            const int64_t base = env[e].cell0;
+            for (int z = c0[2]; z <= c1[2] && !active; ++z)
+              for (int y = c0[1]; y <= c1[1] && !active; ++y) {
+                const int64_t row = base + ((int64_t)z * g.ny + y) * g.nx;
+                active = cell_start[row + c1[0] + 1] > cell_start[row + c0[0]];  // x-run of cells is contiguous
+              }
+          }
+        }
+      }
+    }
+    if (!active) cand_cnt[t] = 0;
+  }
+  const uint64_t m = __ballot(active);
+  int qb = 0;
+  if (lane == 0 && m) qb = atomicAdd(qcount, __popcll(m));
+  qb = __shfl(qb, 0, kWave);
+  if (active) qlist[qb + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
+}
+
 // One wave per slave triangle.  The support prism (|t| <= eps_max along n_T)
 // is covered by up to 64 slabs about one cell thick; the lanes split the
 // cells of all slab boxes, test each master triangle in them (box overlap
@@ -329,28 +406,34 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      const float4 *__restrict__ mbox, int32_t *__restrict__ cand_cnt,
                                                      const int32_t *__restrict__ cand_off, int32_t *__restrict__ cand,
                                                      int64_t cap_cand, int64_t cap_items, int64_t total_cells,
-                                                     DevStatus *st) {
+                                                     const int32_t *__restrict__ qlist,
+                                                     const int32_t *__restrict__ qcount, DevStatus *st) {
   constexpr int pass = PASS;
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kQueryWaves + w;
-  if (i >= Ts) return;
-  const int64_t t = s_order[i];
+  const int64_t nlist = *qcount;
   if (cell_start[total_cells] > cap_items) {  // grid incomplete
-    if (pass == 0 && lane == 0) cand_cnt[t] = 0;
+    if (pass == 0)
+      for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
+        if (lane == 0) cand_cnt[qlist[li]] = 0;
     return;
   }
+  if (pass == 1 && cand_off[Ts] > cap_cand) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      atomicMax(&st->need_cand, (unsigned long long)cand_off[Ts]);
+      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+    }
+    return;
+  }
+  // the waves walk the query list (triangles whose prism meets occupied cells)
+  for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
+    [&](const int64_t t) {
+  wave_sync();  // the previous triangle's LDS reads are done
   int64_t out = 0;
   if (pass == 1) {
     out = cand_off[t];
-    if (cand_off[Ts] > cap_cand) {
-      if (i == 0 && lane == 0) {
-        atomicMax(&st->need_cand, (unsigned long long)cand_off[Ts]);
-        atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
-      }
-      return;
-    }
+    if (cand_off[t + 1] == out) return;
   }
   const int e = s_env[t];
   const GridEnv g = grid[e];
@@ -467,6 +550,8 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
     for (int m = 0; m < nu; ++m) r += dense[w][m] < v;
     l[r] = v;
   }
+  wave_sync();  // the set is reused by the wave's next triangle
+    }(qlist[li]);
 }
 
 
@@ -518,12 +603,22 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   e = build_grid<R>(c, xs, xm, nullptr, nullptr, false);
   prof_mark(c, ST_GRID, 1);
   if (e != hipSuccess) return e;
-  const dim3 qgrid((unsigned)((c->Ts + kQueryWaves - 1) / kQueryWaves));
+  e = fill_i32(c, b.qcount, 0, 1);
+  if (e != hipSuccess) return e;
+  prof_mark(c, ST_QUERY_PRE, 0);
+  if (c->Ts)
+    hipLaunchKernelGGL(k_query_pre<R>, dim3(nblk(c->Ts)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
+                       b.grid, c->Ts, b.cell_start, c->caps.grid_items, c->total_cells, b.cand_cnt, b.qlist, b.qcount,
+                       b.status);
+  prof_mark(c, ST_QUERY_PRE, 1);
+  // the wave kernels walk the query list with a fixed grid
+  const int64_t qb = (c->Ts + kQueryWaves - 1) / kQueryWaves;
+  const dim3 qgrid((unsigned)(qb < kQueryBlocks ? qb : kQueryBlocks));
   prof_mark(c, ST_QUERY_COUNT, 0);
   if (c->Ts)
     hipLaunchKernelGGL((k_query<R, 0>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.status);
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
   prof_mark(c, ST_QUERY_COUNT, 1);
   e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
   if (e != hipSuccess) return e;
@@ -533,7 +628,7 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (c->Ts)
     hipLaunchKernelGGL((k_query<R, 1>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.status);
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
   prof_mark(c, ST_QUERY_FILL, 1);
   hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
   return hipGetLastError();

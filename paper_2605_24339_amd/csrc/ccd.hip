@@ -56,40 +56,52 @@ __device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
   }
 }
 
-// Eq. (ccd): alpha_k = 0.9 g_k / (-grad g_k . dx) for grad g_k . dx < 0
+// Eq. (ccd): alpha_k = 0.9 g_k / (-grad g_k . dx) for grad g_k . dx < 0.
+// One wave per work tile (the narrow phase's Morton tiles): lane (j, r) takes
+// record r of the tile's triangle j (a triangle's records are contiguous),
+// so the triangle's normal and slave displacements are shared loads and the
+// wave belongs to one environment (one atomic per block and environment).
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restrict__ rec, const DevStatus *st,
-                                                          int64_t cap_active, const R *__restrict__ tri_nrm,
+                                                          int64_t cap_active, const Tile *__restrict__ tiles,
+                                                          int n_tiles, const int32_t *__restrict__ s_order,
+                                                          const int32_t *__restrict__ tri_roff,
+                                                          const int32_t *__restrict__ tri_rcnt,
+                                                          const R *__restrict__ tri_nrm,
                                                           const int32_t *__restrict__ ts,
                                                           const int32_t *__restrict__ tm,
-                                                          const int32_t *__restrict__ s_env,
                                                           const EnvInfo *__restrict__ env,
                                                           const double *__restrict__ rule, const R *__restrict__ dxs,
                                                           const R *__restrict__ dxm, uint32_t *bits) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t na = (int64_t)st->n_active;
-  bool ok = na <= cap_active && i < na;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tile_id = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  const bool ok = tile_id < n_tiles && (int64_t)st->n_active <= cap_active;
   float a = INFINITY;
   int e = -1;
   if (ok) {
-    Rec<R> r = rec[i];
-    e = s_env[r.T];
-    const R *n = tri_nrm + 3 * (int64_t)r.T;
-    const double *rq = rule + ((env[e].rule_n - 1) * 16 + r.q) * 3;
-    R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
-    R bm[3] = {r.b0, r.b1, r.b2};
-    R gd = 0;
-    for (int s = 0; s < 3; ++s) {
-      const R *d = dxs + 3 * (int64_t)ts[3 * (int64_t)r.T + s];
-      gd -= bs[s] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
-    }
-    if (dxm)
-      for (int m = 0; m < 3; ++m) {
-        const R *d = dxm + 3 * (int64_t)tm[3 * (int64_t)r.M + m];
-        gd += bm[m] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+    const Tile tl = tiles[tile_id];
+    e = tl.env;
+    const int j = lane / tl.nq, r = lane - j * tl.nq;
+    if (j < tl.count) {
+      const int T = s_order[tl.first + j];
+      if (r < tri_rcnt[T]) {
+        const Rec<R> rc = rec[tri_roff[T] + r];
+        const R *n = tri_nrm + 3 * (int64_t)T;
+        const R bs[3] = {R(1) - rc.s1 - rc.s2, rc.s1, rc.s2};
+        const R bm[3] = {rc.b0, rc.b1, rc.b2};
+        R gd = 0;
+        for (int k = 0; k < 3; ++k) {
+          const R *d = dxs + 3 * (int64_t)ts[3 * (int64_t)T + k];
+          gd -= bs[k] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+        }
+        if (dxm)
+          for (int m = 0; m < 3; ++m) {
+            const R *d = dxm + 3 * (int64_t)tm[3 * (int64_t)rc.M + m];
+            gd += bm[m] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
+          }
+        if (gd < R(0)) a = to_float_down<R>(R(0.9) * rc.g / (-gd));
       }
-    if (gd < R(0)) a = to_float_down<R>(R(0.9) * r.g / (-gd));
+    }
   }
   env_min(bits, e, a, lane);
 }
@@ -198,28 +210,29 @@ __device__ inline int cell_coord(const GridEnv &g, float x, int d) {
   return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-// one thread per (slave triangle, rule point)
+// one wave per work tile, lane = (slave triangle, rule point) as in the
+// narrow phase: Morton-ordered triangles, no idle lanes for small rules,
+// one environment per wave
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     const R *__restrict__ xs, const R *__restrict__ xm, const R *__restrict__ dxs, const R *__restrict__ dxm,
-    const int32_t *__restrict__ ts, const int32_t *__restrict__ tm, const int32_t *__restrict__ s_order,
-    const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const double *__restrict__ rule,
+    const int32_t *__restrict__ ts, const int32_t *__restrict__ tm, const Tile *__restrict__ tiles, int n_tiles,
+    const int32_t *__restrict__ s_order, const EnvInfo *__restrict__ env, const double *__restrict__ rule,
     const GridEnv *__restrict__ grid, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items,
-    const float4 *__restrict__ smbox, int64_t Ts, int64_t cap_items, int64_t total_cells, uint32_t *bits,
-    DevStatus *st) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t ti = i / 16;
-  int q = (int)(i % 16);
+    const float4 *__restrict__ smbox, int64_t cap_items, int64_t total_cells, uint32_t *bits, DevStatus *st) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tile_id = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
   float amin = INFINITY;
   int e = -1;
   unsigned long long npairs = 0;
-  if (ti < Ts && cell_start[total_cells] <= cap_items) {
-    int64_t T = s_order[ti];
-    e = s_env[T];
+  if (tile_id < n_tiles && cell_start[total_cells] <= cap_items) {
+    const Tile tl = tiles[tile_id];
+    e = tl.env;
+    const int j = lane / tl.nq, q = lane - j * tl.nq;
+    const int64_t T = j < tl.count ? s_order[tl.first + j] : 0;
     const EnvInfo &ev = env[e];
     GridEnv g = grid[e];
-    if (q < ev.nq && g.valid) {
+    if (j < tl.count && g.valid) {
       const double *rq = rule + ((ev.rule_n - 1) * 16 + q) * 3;
       R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
       int64_t v[3] = {ts[3 * T], ts[3 * T + 1], ts[3 * T + 2]};
@@ -297,7 +310,6 @@ __global__ void k_alpha_final(const uint32_t *bits, int n_env, R *alpha) {
   alpha[e] = (R)r;
 }
 
-inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
 
@@ -310,19 +322,23 @@ hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   hipLaunchKernelGGL(k_alpha_init, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env);
   const R *dm = dxm;
   prof_mark(c, ST_CCD_LINEAR, 0);
-  hipLaunchKernelGGL(k_ccd_linear<R>, dim3(nblk(c->caps.active)), dim3(kThreads), 0, s, (const Rec<R> *)b.rec,
-                     b.status, c->caps.active, (const R *)b.tri_nrm, c->ts, c->tm, b.s_env, b.env, b.rule, dxs, dm,
-                     b.alpha_bits);
+  if (c->n_tiles)
+    hipLaunchKernelGGL(k_ccd_linear<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
+                       dim3(kThreads), 0, s,
+                       (const Rec<R> *)b.rec, b.status, c->caps.active, b.tiles, (int)c->n_tiles, b.s_order,
+                       b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, c->ts, c->tm, b.env, b.rule, dxs, dm,
+                       b.alpha_bits);
   prof_mark(c, ST_CCD_LINEAR, 1);
   prof_mark(c, ST_CCD_GRID, 0);
   e = build_grid<R>(c, xs, xm, dxs, dm, true);
   prof_mark(c, ST_CCD_GRID, 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_CCD_ACCD, 0);
-  if (c->Ts)
-    hipLaunchKernelGGL(k_ccd_accd<R>, dim3(nblk(c->Ts * 16)), dim3(kThreads), 0, s, xs, xm, dxs, dm, c->ts, c->tm,
-                       b.s_order, b.s_env, b.env, b.rule, b.sgrid, b.scell_start, b.sitems, b.smbox, c->Ts,
-                       c->caps.grid_items, c->total_cells, b.alpha_bits, b.status);
+  if (c->n_tiles)
+    hipLaunchKernelGGL(k_ccd_accd<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
+                       dim3(kThreads), 0, s, xs, xm, dxs, dm, c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order,
+                       b.env, b.rule, b.sgrid, b.scell_start, b.sitems, b.smbox, c->caps.grid_items, c->total_cells,
+                       b.alpha_bits, b.status);
   prof_mark(c, ST_CCD_ACCD, 1);
   hipLaunchKernelGGL(k_alpha_final<R>, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env, alpha);
   return hipGetLastError();

@@ -53,9 +53,11 @@ struct Tile {              // narrow-phase work item: tris [first, first+count) 
 };
 
 template <typename R>
-struct Rec {               // selected sample record
-  int32_t k, M, T, q;
-  R g, b0, b1, b2, c1, c2, p, pad;
+struct Rec {               // active sample record
+  int32_t k, M, T, q;      // sample id (-1 for clipped mortar samples), master / slave triangle, rule point
+  R g, b0, b1, b2;         // gap, master barycentrics
+  R c1, c2, p, eps;        // kappa w gamma B', clamped kappa w gamma B'', pressure, support radius
+  R s1, s2, kwg, pad;      // slave barycentrics beta^s_1, beta^s_2; kappa w gamma
 };
 
 template <typename R>
@@ -81,6 +83,7 @@ struct Buffers {
   int32_t *cell_cnt, *cell_start, *items;
   float4 *mbox;                                 // [Tm][3]: lo, hi, unit normal
   int32_t *cand_cnt, *cand_off, *cand;
+  int32_t *qlist, *qcount;                      // [Ts], [1]: slave triangles whose prism meets occupied cells
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
   void *tri_nrm;                                // [Ts][3] R
@@ -90,7 +93,11 @@ struct Buffers {
   double *tile_E;
   int32_t *mp_cnt, *mp_off, *mp_list;
   long long *mp_key;                            // [pairs] (slave triangle << 32 | pair)
+  void *mtri;                                   // [Tm][45] R: per master triangle, sum over its
+                                                // pairs of mm n n^T (6 vertex pairs x 6) and gm n (3 x 3)
   int32_t *row_cnt;                             // [V+1]
+  int32_t *rlist, *rcount;                      // [2V]: BSR rows with contributions (light | heavy);
+                                                // [4]: light rows, heavy rows, light blocks, heavy blocks
   // step bound
   GridEnv *sgrid;
   uint32_t *sbox;
@@ -114,11 +121,17 @@ enum Stage {
   ST_NARROW,       // kernel k_narrow: narrow phase + barrier + sums
   ST_BUCKET,       // pairs bucketed by master triangle (count, scan, place, sort)
   ST_GRAD,         // kernel k_grad: gradient rows
-  ST_ROWS_COUNT,   // kernel k_rows, counting pass
-  ST_ROWS_FILL,    // kernel k_rows, writing pass
+  ST_ROWS_COUNT,   // kernel k_rows, counting pass (light rows)
+  ST_ROWS_FILL,    // kernel k_rows, writing pass (light rows)
   ST_CCD_LINEAR,   // kernel k_ccd_linear
   ST_CCD_GRID,     // swept grid build
   ST_CCD_ACCD,     // kernel k_ccd_accd
+  ST_MTRI,         // kernel k_mtri: per-master-triangle Hessian blocks and gradient
+  ST_ROWS_COPY,    // kernel k_rows, master rows' slave columns copied from the slave rows
+  ST_QUERY_PRE,    // kernel k_query_pre: frame checks, prism boxes, query list
+  ST_ROWS_PRE,     // kernel k_row_pre: list of rows with contributions
+  ST_ROWS_COUNT_H, // kernel k_rows, counting pass, heavy rows
+  ST_ROWS_FILL_H,  // kernel k_rows, writing pass, heavy rows
   ST_COUNT
 };
 
@@ -135,7 +148,7 @@ struct Prof {
 struct gmcp_ctx {
   gmcp::Prof prof;
   hipStream_t stream;
-  bool f64, kinematic;
+  bool f64, kinematic, mortar;
   int n_env;
   int64_t Vs, Vm, Ts, Tm, Ns, V, n_tiles, total_cells;
   gmcp_caps caps;
@@ -169,6 +182,8 @@ template <typename R>
 hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha);
 template <typename R>
 hipError_t launch_hvp(gmcp_ctx *c, const R *vx, const R *vd, R *ox, R *od);
+template <typename R>
+hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy);
 template <typename R>
 hipError_t launch_sample_results(gmcp_ctx *c, int32_t *M, R *g, R *bm, R *c1, R *c2, R *p);
 

@@ -186,6 +186,8 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.cand_cnt = p.take<int32_t>(s.Ts + 1);
   t.cand_off = p.take<int32_t>(s.Ts + 1);
   t.cand = p.take<int32_t>(cp.candidates);
+  t.qlist = p.take<int32_t>(s.Ts);
+  t.qcount = p.take<int32_t>(1);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
   t.tri_nrm = p.take<char>(rsz * 3 * s.Ts);
   t.tri_sum = p.take<char>(rsz * 9 * s.Ts);
@@ -199,7 +201,10 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.mp_off = p.take<int32_t>(s.Tm + 1);
   t.mp_list = p.take<int32_t>(cp.pairs);
   t.mp_key = p.take<long long>(cp.pairs);
+  t.mtri = p.take<char>(s.kin ? 0 : rsz * 45 * s.Tm);
   t.row_cnt = p.take<int32_t>(s.V + 1);
+  t.rlist = p.take<int32_t>(2 * s.V);
+  t.rcount = p.take<int32_t>(4);
   t.sgrid = p.take<GridEnv>(s.n_env);
   t.sbox = p.take<uint32_t>(6 * s.n_env);
   t.scell_cnt = p.take<int32_t>(cp.grid_cells + 1);
@@ -290,6 +295,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->stream = (hipStream_t)stream;
   c->f64 = s.f64;
   c->kinematic = s.kin;
+  c->mortar = (L->flags & GMCP_MORTAR) != 0;
   c->n_env = s.n_env;
   c->Vs = s.Vs;
   c->Vm = s.Vm;
@@ -521,6 +527,7 @@ int gmcp_assemble(gmcp_ctx *c, const void *xs, const void *xm, const void *g_ref
                   void *energy, void *grad, const gmcp_bsr *H) {
   if (!c || !xs || (c->Tm > 0 && !xm) || !energy || !c->samples_built || !c->broadphase_done)
     return GMCP_E_ARG;
+  if (c->mortar && (g_ref || dgap)) return GMCP_E_ARG;  // clipped samples have no fixed ids
   if (H && (!H->row_ptr || (H->cap_nnzb > 0 && (!H->col || !H->val)) || H->cap_nnzb < 0 ||
             H->cap_nnzb >= (int64_t(1) << 31)))
     return GMCP_E_ARG;
@@ -545,13 +552,21 @@ int gmcp_ccd_step(gmcp_ctx *c, const void *xs, const void *xm, const void *dxs, 
 
 int gmcp_hvp(gmcp_ctx *c, const void *vx, const void *vd, void *ox, void *od) {
   if (!c || !vx || !ox || !c->assembled) return GMCP_E_ARG;
+  if (c->mortar && (vd || od)) return GMCP_E_ARG;
   hipError_t e = c->f64 ? launch_hvp<double>(c, (const double *)vx, (const double *)vd, (double *)ox, (double *)od)
                         : launch_hvp<float>(c, (const float *)vx, (const float *)vd, (float *)ox, (float *)od);
   return fail(c, e);
 }
 
+int gmcp_energy_frozen(gmcp_ctx *c, const void *xs, const void *xm, void *energy) {
+  if (!c || !xs || !xm || !energy || !c->assembled) return GMCP_E_ARG;
+  hipError_t e = c->f64 ? launch_energy_frozen<double>(c, (const double *)xs, (const double *)xm, (double *)energy)
+                        : launch_energy_frozen<float>(c, (const float *)xs, (const float *)xm, (float *)energy);
+  return fail(c, e);
+}
+
 int gmcp_sample_results(gmcp_ctx *c, int32_t *M, void *g, void *bm, void *c1, void *c2, void *p) {
-  if (!c || !c->assembled) return GMCP_E_ARG;
+  if (!c || !c->assembled || c->mortar) return GMCP_E_ARG;
   hipError_t e = c->f64 ? launch_sample_results<double>(c, M, (double *)g, (double *)bm, (double *)c1,
                                                         (double *)c2, (double *)p)
                         : launch_sample_results<float>(c, M, (float *)g, (float *)bm, (float *)c1, (float *)c2,
@@ -602,7 +617,7 @@ int gmcp_status(gmcp_ctx *c, gmcp_status_info *info) {
 
 static const char *kStageNames[gmcp::ST_COUNT] = {
     "grid_build", "query_count", "query_fill", "narrow",     "pair_bucket", "grad_rows",
-    "rows_count", "rows_fill",   "ccd_linear", "ccd_grid",   "ccd_accd"};
+    "rows_count", "rows_fill",   "ccd_linear", "ccd_grid",   "ccd_accd",  "master_tri_sums", "rows_copy", "query_pre", "rows_pre", "rows_count_heavy", "rows_fill_heavy"};
 
 int gmcp_profile(gmcp_ctx *c, int enable) {
   if (!c) return GMCP_E_ARG;
@@ -633,6 +648,16 @@ int gmcp_profile_read(gmcp_ctx *c, double *ms, int64_t *count) {
     ms[c->prof.stage[i]] += t;
     count[c->prof.stage[i]] += 1;
   }
+  return GMCP_OK;
+}
+
+int gmcp_row_classes(gmcp_ctx *c, int64_t *out) {
+  if (!c || !out || !c->assembled) return GMCP_E_ARG;
+  int32_t h[4];
+  if (hipMemcpyAsync(h, c->b.rcount, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return GMCP_E_HIP;
+  for (int i = 0; i < 4; ++i) out[i] = h[i];
   return GMCP_OK;
 }
 

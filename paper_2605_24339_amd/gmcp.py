@@ -62,18 +62,21 @@ class Context:
     (slave ids in [0, Vs), master ids in [0, Vm)).  Per-environment arrays:
     rule_n (n in 1..4, n*n samples per slave triangle), kappa, dhat
     (eps_max), delta_T (face transition width), cell (broad-phase cell size,
-    0 = automatic).
+    0 = automatic).  mortar=True uses clipped mortar face samples (every
+    opposing pair's projected overlap, fan-triangulated, n x n rule per
+    sub-triangle) instead of one whole-triangle rule per slave triangle.
     """
 
     def __init__(self, slave_tri, master_tri, slave_v_off, slave_t_off, master_v_off, master_t_off,
                  rule_n, kappa, dhat, delta_T, cell=None, dtype=torch.float32, kinematic=False,
-                 caps: dict | None = None, device="cuda"):
+                 caps: dict | None = None, device="cuda", mortar: bool = False):
         N.lib()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         self.kinematic = bool(kinematic)
+        self.mortar = bool(mortar)
         self.ts = torch.as_tensor(slave_tri, dtype=torch.int32).to(self.device).contiguous()
         self.tm = torch.as_tensor(master_tri, dtype=torch.int32).to(self.device).contiguous()
         self.n_env = len(rule_n)
@@ -84,7 +87,8 @@ class Context:
                           dhat=as_f64(dhat), dT=as_f64(delta_T),
                           cell=as_f64(cell if cell is not None else [0.0] * self.n_env))
         k = self._keep
-        flags = (N.GMCP_F64 if dtype == torch.float64 else 0) | (N.GMCP_KINEMATIC_MASTER if kinematic else 0)
+        flags = ((N.GMCP_F64 if dtype == torch.float64 else 0) | (N.GMCP_KINEMATIC_MASTER if kinematic else 0)
+                 | (N.GMCP_MORTAR if mortar else 0))
         cast = lambda a, t: C.cast(a, C.POINTER(t))
         self.layout = N.Layout(self.n_env, cast(k["svo"], C.c_int32), cast(k["sto"], C.c_int32),
                                cast(k["mvo"], C.c_int32), cast(k["mto"], C.c_int32),
@@ -187,10 +191,10 @@ class Context:
             self.cap_nnzb = int(info.nnzb * 1.25) + 1024
             grew = True
         if need.row_entries > self.caps["row_entries"]:
-            if self.caps["row_entries"] >= 1024:
+            if self.caps["row_entries"] >= 4096:
                 raise GMCPError(N.GMCP_E_CAPACITY, -1,
-                                f"{where}: a BSR row has more than 1024 distinct columns")
-            self.caps["row_entries"] = min(1024, int(need.row_entries))
+                                f"{where}: a BSR row has more than 4096 distinct columns")
+            self.caps["row_entries"] = min(4096, int(need.row_entries))
             grew = True
         if not grew:
             raise GMCPError(info.code, info.index, where)
@@ -288,10 +292,28 @@ class Context:
         vx = self._x(vx, self.V, "v_x")
         vd = self._vec(vd, self.Ns, "v_d")
         ox = torch.empty(self.V, 3, dtype=self.dtype, device=self.device)
-        od = torch.empty(self.Ns, dtype=self.dtype, device=self.device)
+        # clipped mortar samples have no fixed ids: no per-sample part
+        od = None if self.mortar else torch.empty(self.Ns, dtype=self.dtype, device=self.device)
         self._bind()
         _check(N.lib().gmcp_hvp(self._ctx, _ptr(vx), _ptr(vd), _ptr(ox), _ptr(od)), "gmcp_hvp")
         return ox, od
+
+    def row_classes(self) -> dict:
+        """Light / heavy BSR rows and their blocks in the last assembly (synchronises)."""
+        out = (C.c_int64 * 4)()
+        self._bind()
+        _check(N.lib().gmcp_row_classes(self._ctx, out), "gmcp_row_classes")
+        return dict(rows_light=out[0], rows_heavy=out[1], nnzb_light=out[2], nnzb_heavy=out[3])
+
+    def energy_frozen(self, xs, xm) -> torch.Tensor:
+        """Energy [n_env] of the last assembly's samples at positions (xs, xm),
+        every sample frozen (gradient at the assembly point = assembled gradient)."""
+        xs = self._x(xs, self.Vs, "x_slave")
+        xm = self._x(xm, self.Vm, "x_master")
+        out = torch.empty(self.n_env, dtype=self.dtype, device=self.device)
+        self._bind()
+        _check(N.lib().gmcp_energy_frozen(self._ctx, _ptr(xs), _ptr(xm), _ptr(out)), "gmcp_energy_frozen")
+        return out
 
     def sample_results(self):
         M = torch.empty(self.Ns, dtype=torch.int32, device=self.device)
@@ -327,9 +349,9 @@ class Context:
     @classmethod
     def single(cls, slave_tri, master_tri, n_slave_verts: int, n_master_verts: int, rule_n: int = 2,
                kappa: float = 1e5, dhat: float = 1e-3, delta_T: float = 0.0, cell: float = 0.0,
-               dtype=torch.float32, kinematic: bool = False, caps=None, device="cuda"):
+               dtype=torch.float32, kinematic: bool = False, caps=None, device="cuda", mortar: bool = False):
         Ts = int(len(slave_tri))
         Tm = int(len(master_tri))
         return cls(slave_tri, master_tri, [0, n_slave_verts], [0, Ts], [0, n_master_verts], [0, Tm],
                    [rule_n], [kappa], [dhat], [delta_T], [cell], dtype=dtype, kinematic=kinematic, caps=caps,
-                   device=device)
+                   device=device, mortar=mortar)

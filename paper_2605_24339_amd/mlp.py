@@ -114,8 +114,7 @@ class MLP:
         act = torch.empty(batch, 6 * 128, dtype=torch.float32, device=self.dev)
         for ep in range(epochs):
             perm = torch.randperm(R, generator=gen).to(self.dev)
-            tot = 0.0
-            nb = 0
+            tot, ns, nb = 0.0, 0, 0
             for i in range(0, R - batch + 1, batch):
                 idx = perm[i:i + batch]
                 xb, tb = X[idx].contiguous(), T[idx].contiguous()
@@ -123,9 +122,11 @@ class MLP:
                 loss, dy = self.mse(y, tb)
                 g = self.backward(xb, a, dy)
                 self.adam(g, lr=lr)
-                tot += float(loss.item()) if (nb % 50 == 0) else 0.0
+                if nb % 16 == 0:          # sampled batch losses (a host sync each)
+                    tot += float(loss.item())
+                    ns += 1
                 nb += 1
-            hist.append(tot)
+            hist.append(tot / max(ns, 1))
             if log:
                 log(f"epoch {ep}: {nb} batches")
         return hist

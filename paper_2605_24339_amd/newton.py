@@ -1,6 +1,9 @@
 """Implicit Euler step of a linear-elastic tet body in contact through GMCP:
 Newton on the incremental potential with a CCD-capped backtracking line
 search (the IPC solver structure the paper's contact model plugs into).
+Each Newton iteration re-selects the contact samples (assembly at the
+iterate); the line search tests the energy with those samples frozen, the
+function whose gradient and Hessian the assembly returned.
 
     E(x) = 1/2 |x - x_tilde|^2_M / dt^2 + 1/2 (x - X)^T K (x - X) + Psi_GMCP(x)
 
@@ -32,6 +35,7 @@ class StepStats:
     converged: bool = False
     alphas: list = field(default_factory=list)
     x0: object = None          # the (filtered) starting point of the Newton iteration
+    used_start: bool | None = None  # safeguarded start: the given start beat the plain one
 
 
 class ImplicitSolver:
@@ -50,10 +54,19 @@ class ImplicitSolver:
 
     # -------------------------------------------------------------- pieces
     def energy(self, x, x_tilde, xm) -> float:
+        """Incremental potential with the contact samples re-selected at x."""
         e_fem, _ = self.fem.energy(x, x_tilde, grad=False)
         self.contact.broadphase(x, xm)
         A = self.contact.assemble(x, xm, grad=False, hessian=False)
         return float(e_fem.item() + A.energy.sum().item())
+
+    def model_energy(self, x, x_tilde, xm) -> float:
+        """Incremental potential with the contact samples of the last
+        assembly frozen: the function whose gradient and Hessian the
+        assembly returned, so the Armijo test and the descent direction
+        agree."""
+        e_fem, _ = self.fem.energy(x, x_tilde, grad=False)
+        return float(e_fem.item() + self.contact.energy_frozen(x, xm).sum().item())
 
     def gradient_system(self, x, x_tilde, xm):
         e_fem, g = self.fem.energy(x, x_tilde, grad=True)
@@ -74,11 +87,14 @@ class ImplicitSolver:
         return x_t + a * d, a
 
     # ---------------------------------------------------------------- step
-    def solve_step(self, x_t, v_t, xm, fixed_pos, x_start=None) -> tuple:
+    def solve_step(self, x_t, v_t, xm, fixed_pos, x_start=None, safeguard=False) -> tuple:
         """One implicit step.  fixed_pos: positions of the Dirichlet vertices
         at the end of the step ([V, 3] tensor, only fixed rows are read).
         x_start: optional starting guess (the plain start is x_t + dt v_t);
-        it passes the same feasibility filter as the plain start."""
+        it passes the same feasibility filter as the plain start.  With
+        safeguard, both filtered starts are evaluated (two energy-only
+        evaluations) and the one with the lower incremental potential is
+        used."""
         st = StepStats()
         fx = self.fem.fixed
         x_tilde = x_t + self.fem.dt * v_t
@@ -87,6 +103,15 @@ class ImplicitSolver:
         y[fx] = fixed_pos[fx]
         x, st.start_alpha = self.feasible_start(x_t, y, xm)
         x[fx] = fixed_pos[fx]
+        if x_start is not None and safeguard:
+            xp, ap = self.feasible_start(x_t, x_tilde.clone(), xm)
+            xp[fx] = fixed_pos[fx]
+            e_given = self.energy(x.contiguous(), x_tilde, xm)
+            e_plain = self.energy(xp.contiguous(), x_tilde, xm)
+            st.energy_evals += 2
+            st.used_start = bool(e_given < e_plain)
+            if not st.used_start:
+                x, st.start_alpha = xp, ap
         x = x.contiguous()
         st.x0 = x.clone()
         for it in range(self.max_newton):
@@ -105,14 +130,14 @@ class ImplicitSolver:
             if not slope < 0.0:      # not a descent direction: fall back to steepest descent
                 d = -g / max(gn, 1e-300)
                 slope = float((g * d).sum().item())
-            self.contact.broadphase(x, xm)
             a = float(self.contact.ccd_step(x, xm, d.contiguous()).min().item())
             a = min(1.0, a)
+            E0 = self.model_energy(x, x_tilde, xm)
             while True:
                 xn = (x + a * d).contiguous()
-                En = self.energy(xn, x_tilde, xm)
+                En = self.model_energy(xn, x_tilde, xm)
                 st.energy_evals += 1
-                if En <= E + self.armijo * a * slope or a < 1e-14:
+                if En <= E0 + self.armijo * a * slope or a < 1e-14:
                     break
                 a *= 0.5
             st.alphas.append(a)

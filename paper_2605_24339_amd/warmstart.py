@@ -14,6 +14,12 @@ sphere at U[5, 20] mm/s with a lateral drift of at most 20 mm/s.  The
 tactile surface (slave) is the top face, 2 x 2 samples per triangle,
 dhat = 1 mm, kappa = 1e5.
 
+The network's inputs are standardised and its outputs scaled by the
+targets' RMS (fitted on the training rows).  With the safeguard (default)
+the learned and the plain start are both filtered and the one with the
+lower incremental potential starts Newton (two energy-only evaluations,
+counted separately from assemblies).
+
     python -m paper_2605_24339_amd.warmstart --train 20 --test 5 --steps 100
 """
 from __future__ import annotations
@@ -66,7 +72,32 @@ class Scene:
         return ImplicitSolver(fem, ctx, E_Y * self.h * self.h, tol=tol)
 
 
-def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, log=None):
+class Scaler:
+    """Standardisation of the network's inputs (mean / std of the nine
+    features) and outputs (per-component RMS of the targets), fitted on the
+    training rows, so that the bf16 network works with O(1) values."""
+
+    def __init__(self, X, T):
+        self.mu = X[:, :9].mean(0)
+        self.sd = X[:, :9].std(0).clamp_min(1e-12)
+        self.ts = T[:, :3].pow(2).mean(0).sqrt().clamp_min(1e-12)
+
+    def x(self, X):
+        out = torch.zeros_like(X)
+        out[:, :9] = (X[:, :9] - self.mu) / self.sd
+        return out
+
+    def t(self, T):
+        out = torch.zeros_like(T)
+        out[:, :3] = T[:, :3] / self.ts
+        return out
+
+    def y(self, Y):
+        return Y[:, :3] * self.ts
+
+
+def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, log=None, scaler=None,
+                   safeguard=True):
     """Simulate; returns per-step records (positions kept on the device)."""
     dev = scene.device
     solver = scene.make_solver()
@@ -84,13 +115,13 @@ def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, 
         feat = None
         if net is not None or keep:
             feat = features(x, v, d_prev, center, scene.L, scene.h, DT)
+        t0 = time.perf_counter()
         if net is not None:
-            y, _ = net.forward(feat)
-            pred = y[:, :3].double() * scene.h
+            y, _ = net.forward(scaler.x(feat).contiguous())
+            pred = scaler.y(y).double() * scene.h
             if torch.isfinite(pred).all():
                 x_start = x + DT * v + pred
-        t0 = time.perf_counter()
-        xn, st = solver.solve_step(x, v, xm, plate, x_start=x_start)
+        xn, st = solver.solve_step(x, v, xm, plate, x_start=x_start, safeguard=safeguard)
         if net is not None and (not st.converged or st.start_alpha < 1e-3):
             xn, st = solver.solve_step(x, v, xm, plate)     # fall back to the plain start
             st.fallback = True
@@ -99,7 +130,8 @@ def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, 
         start_err = float((st.x0 - xn).abs().max().item()) / scene.h
         rec = dict(step=s, newton=st.newton_iters, assemblies=st.assemblies, energy_evals=st.energy_evals,
                    cg=st.cg_iters, residual=st.residual, converged=st.converged, start_alpha=st.start_alpha,
-                   start_err=start_err, seconds=el, fallback=getattr(st, "fallback", False))
+                   start_err=start_err, seconds=el, fallback=getattr(st, "fallback", False),
+                   used_learned=st.used_start, n_active=int(solver.contact.status().n_active))
         if keep:
             rec["feat"] = feat
             rec["target"] = targets(xn, x, v, DT, scene.h)
@@ -122,6 +154,13 @@ def summarize(recs):
     out["all_converged"] = bool(all(r["converged"] for r in recs))
     out["max_residual"] = float(max(r["residual"] for r in recs))
     out["fallbacks"] = int(sum(r["fallback"] for r in recs))
+    used = [r["used_learned"] for r in recs if r.get("used_learned") is not None]
+    out["learned_start_chosen"] = (sum(used) / len(used)) if used else None
+    contact = [r for r in recs if r.get("n_active", 0) > 0]
+    out["contact_steps"] = len(contact)
+    if contact:
+        out["newton_in_contact"] = float(np.mean([r["newton"] for r in contact]))
+        out["assemblies_in_contact"] = float(np.mean([r["assemblies"] for r in contact]))
     out["seconds_per_step"] = float(a("seconds").mean())
     return out
 
@@ -150,6 +189,8 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--nz", type=int, default=8)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--no-safeguard", action="store_true",
+                    help="always start from the network's prediction (no energy comparison with the plain start)")
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)
     dev = "cuda"
@@ -167,9 +208,10 @@ def main():
     T = torch.cat(targs)
     del feats, targs
     gen_s = time.perf_counter() - t0
+    scaler = Scaler(X, T)
     net = MLP(init_params(0, dev))
     t1 = time.perf_counter()
-    hist = net.train(X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    hist = net.train(scaler.x(X), scaler.t(T), epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     # held-out evaluation
@@ -177,7 +219,7 @@ def main():
     for j in range(args.test):
         sc = Scene(5000 + args.train + j, args.n, args.nz, device=dev)
         p = run_trajectory(sc, args.steps, None, keep=False, log=log)
-        l = run_trajectory(sc, args.steps, net, keep=False, log=log)
+        l = run_trajectory(sc, args.steps, net, keep=False, log=log, scaler=scaler, safeguard=not args.no_safeguard)
         log(f"test trajectory {j}: plain {summarize(p)['newton']} learned {summarize(l)['newton']}")
         plain += p
         learned += l
@@ -187,6 +229,9 @@ def main():
         "training_rows": int(X.shape[0]), "epochs": args.epochs, "train_seconds": train_s,
         "generation_seconds": gen_s, "loss_history": hist,
         "plain_train": summarize(plain_train), "plain_test": summarize(plain), "learned_test": summarize(learned),
+        "safeguard": not args.no_safeguard,
+        "per_step_test": [{"plain_newton": p["newton"], "learned_newton": l["newton"], "n_active": p["n_active"],
+                           "learned_chosen": l["used_learned"]} for p, l in zip(plain, learned)],
     }
     pa, la = report["plain_test"]["assemblies"]["mean"], report["learned_test"]["assemblies"]["mean"]
     report["assemblies_ratio_learned_over_plain"] = la / pa if pa else None

@@ -261,3 +261,30 @@ def test_reference_gaps_and_gap_offsets(dtype):
     H = A.hessian
     assert bsr_rel_error(H.row_ptr.cpu().numpy(), H.col.cpu().numpy(), H.val.double().cpu().numpy(), O.row_ptr,
                          O.col, O.val) <= tg
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_frozen_energy_matches_oracle(dtype):
+    """gmcp_energy_frozen: at the assembly point it is the assembled energy;
+    at displaced positions it matches the oracle's frozen-sample energy
+    evaluated on the same selection."""
+    need_gpu()
+    import oracle
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    w = workloads.small_indent(fp32=fp32)
+    G = run_gpu(w, tdt, ccd=False)
+    ctx = G["ctx"]
+    tol = 1e-5 if fp32 else 1e-10
+    e0 = float(ctx.energy_frozen(G["xs"], G["xm"]).double().sum().item())
+    assert abs(e0 / G["energy"].sum() - 1) <= tol
+    rng = np.random.default_rng(9)
+    xs1 = w.xs + rng.uniform(-2e-6, 2e-6, size=w.xs.shape)
+    xm1 = w.xm + rng.uniform(-2e-6, 2e-6, size=w.xm.shape)
+    if fp32:
+        xs1, xm1 = xs1.astype(np.float32).astype(np.float64), xm1.astype(np.float32).astype(np.float64)
+    e1 = float(ctx.energy_frozen(to_dev(xs1, tdt), to_dev(xm1, tdt)).double().sum().item())
+    P = oracle.Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, None, w.xs_rest)
+    ref = oracle.frozen_energy(P, G["M"], G["bm"], xs1, xm1)
+    assert abs(e1 / ref - 1) <= (1e-4 if fp32 else 1e-10)
+    assert abs(e1 / e0 - 1) > 1e-4        # the displacement changed the energy

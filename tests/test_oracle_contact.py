@@ -321,3 +321,28 @@ def test_penetration_and_degenerate_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.narrow(P2)
     assert e.value.code == oracle.E_DEGENERATE and e.value.index == 5
+
+
+def test_frozen_energy_is_the_assembled_energy_and_gradient():
+    """The frozen-sample energy equals the assembled energy at the assembly
+    point, its central finite differences give the assembled (frozen)
+    gradient, and it is unchanged by a common translation."""
+    import oracle
+    from gen import workloads
+    w = workloads.small_indent(fp32=False)
+    P = workloads.to_problem(w)
+    nr = oracle.narrow(P)
+    A = oracle.assemble(P, nr.M, hessian=False)
+    E0 = oracle.frozen_energy(P, nr.M, nr.bm, P.xs, P.xm)
+    assert abs(E0 / A.energy - 1) < 1e-12
+    rng = np.random.default_rng(5)
+    ds = rng.normal(size=P.xs.shape) * 1e-6
+    dm = rng.normal(size=P.xm.shape) * 1e-6
+    h = 1e-3
+    Ep = oracle.frozen_energy(P, nr.M, nr.bm, P.xs + h * ds, P.xm + h * dm)
+    Em = oracle.frozen_energy(P, nr.M, nr.bm, P.xs - h * ds, P.xm - h * dm)
+    fd = (Ep - Em) / (2 * h)
+    an = float(np.sum(A.grad[:P.Vs] * ds) + np.sum(A.grad[P.Vs:] * dm))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    t = np.array([1e-3, -2e-3, 5e-4])
+    assert abs(oracle.frozen_energy(P, nr.M, nr.bm, P.xs + t, P.xm + t) / E0 - 1) < 1e-12
