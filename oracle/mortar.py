@@ -14,6 +14,9 @@ beta^m = the barycentric coordinates of y in the projected master triangle
 (projection along n is affine, so they are the master triangle's own), and
 the signed gap (Eq. (gap)) g = n . (sum_j beta^m_j m_j - x_s).
 
+Edge and point samples (Sec. 4.1) are generated from the edges and
+vertices of the opposing master triangles (feature_samples).
+
 Readings (the paper does not fix them):
 * weight w = 2 A_sub W_q with A_sub the sub-triangle's share of the slave
   triangle's REST area (2 |area in (u, v)| A_rest(T_s)), so the weights of a
@@ -58,12 +61,15 @@ def clip_by_reference(poly):
 @dataclass
 class Sample:
     T: int
-    M: int
+    M: int              # master triangle (face samples), -1 for edge / point samples
     bs: np.ndarray      # slave barycentrics (3)
-    bm: np.ndarray      # master barycentrics (3)
+    bm: np.ndarray      # coefficients of the master vertices mv
     w: float
     g: float
     n: np.ndarray       # slave unit normal
+    mv: np.ndarray = None   # master vertex ids (3 face, 2 edge, 1 point)
+    kind: int = 2           # 2 face, 1 edge, 0 point (Eq. (gmcp_potential))
+    eta: float = 0.0        # edge parameter (edge samples)
 
 
 def pair_samples(P: "oracle.Problem", T: int, M: int, area_rest: float, rule):
@@ -95,35 +101,116 @@ def pair_samples(P: "oracle.Problem", T: int, M: int, area_rest: float, rule):
             bm = np.array([1.0 - b12[0] - b12[1], b12[0], b12[1]])
             xs_k = s[0] + y[0] * e1 + y[1] * e2
             g = float(n @ (bm @ m - xs_k))
-            out.append(Sample(T, M, bs, bm, 2.0 * (a2 * area_rest) * wq, g, n))
+            out.append(Sample(T, M, bs, bm, 2.0 * (a2 * area_rest) * wq, g, n, np.asarray(P.tm[M])))
     return out
 
 
-def samples(P: "oracle.Problem", tris=None):
+def clip_segment(qa, qb):
+    """Parameter interval (t0, t1) of the segment qa + t (qb - qa), t in
+    [0, 1], inside the reference triangle, or None (Liang-Barsky)."""
+    t0, t1 = 0.0, 1.0
+    for f in (lambda p: p[0], lambda p: p[1], lambda p: 1.0 - p[0] - p[1]):
+        fa, fb = f(qa), f(qb)
+        d = fb - fa
+        if d == 0.0:
+            if fa < 0.0:
+                return None
+            continue
+        t = -fa / d
+        if d > 0.0:
+            t0 = max(t0, t)
+        else:
+            t1 = min(t1, t)
+    return (t0, t1) if t1 > t0 else None
+
+
+def _frame(P, T):
+    s = P.xs[P.ts[T]]
+    e1, e2 = s[1] - s[0], s[2] - s[0]
+    c = np.cross(e1, e2)
+    n = c / np.linalg.norm(c)
+    G = np.array([[e1 @ e1, e1 @ e2], [e1 @ e2, e2 @ e2]])
+    return s[0], e1, e2, n, G
+
+
+def feature_samples(P: "oracle.Problem", T: int, opposing):
+    """Edge and point samples (Sec. 4.1) of slave triangle T against the
+    edges and vertices of the opposing master triangles `opposing` (each
+    feature once).  Edge (a, b): projected along n_T, clipped by T to the
+    parameter interval [t0, t1], Gauss-Legendre with rule_n points: eta,
+    x_m = (1 - eta) x_a + eta x_b, weight |x_b - x_a| (t1 - t0) W_j (a
+    length), gap (1 - eta) h_a + eta h_b.  Vertex p: its projection strictly
+    inside T (a point on a slave edge belongs to no triangle), weight 1,
+    gap h_p."""
+    s0, e1, e2, n, G = _frame(P, T)
+    proj = lambda x: np.linalg.solve(G, np.array([(x - s0) @ e1, (x - s0) @ e2]))
+    xg, wg = np.polynomial.legendre.leggauss(P.rule_n)
+    xg, wg = (xg + 1.0) / 2.0, wg / 2.0
+    edges, verts = set(), set()
+    for M in opposing:
+        a, b, c = (int(v) for v in P.tm[M])
+        for u, v in ((a, b), (b, c), (c, a)):
+            edges.add((min(u, v), max(u, v)))
+        verts.update((a, b, c))
+    out = []
+    for a, b in sorted(edges):
+        xa, xb = P.xm[a], P.xm[b]
+        ha, hb = (xa - s0) @ n, (xb - s0) @ n
+        if min(ha, hb) >= P.dhat or max(ha, hb) <= -P.dhat:
+            continue
+        qa, qb = proj(xa), proj(xb)
+        seg = clip_segment(qa, qb)
+        if seg is None:
+            continue
+        t0, t1 = seg
+        L = float(np.linalg.norm(xb - xa))
+        for xj, wj in zip(xg, wg):
+            eta = t0 + (t1 - t0) * xj
+            y = qa + eta * (qb - qa)
+            bs = np.array([1.0 - y[0] - y[1], y[0], y[1]])
+            out.append(Sample(T, -1, bs, np.array([1.0 - eta, eta]), L * (t1 - t0) * wj,
+                              float((1.0 - eta) * ha + eta * hb), n, np.array([a, b]), 1, float(eta)))
+    for p in sorted(verts):
+        h = float((P.xm[p] - s0) @ n)
+        if not (-P.dhat < h < P.dhat):
+            continue
+        y = proj(P.xm[p])
+        if y[0] > 0.0 and y[1] > 0.0 and 1.0 - y[0] - y[1] > 0.0:
+            out.append(Sample(T, -1, np.array([1.0 - y[0] - y[1], y[0], y[1]]), np.array([1.0]), 1.0, h, n,
+                              np.array([p]), 0))
+    return out
+
+
+def samples(P: "oracle.Problem", tris=None, features: bool = False):
     """All clipped face samples of the slave triangles `tris` (default all)
-    against every master triangle.  Raises OracleError(PENETRATION) for a
-    sample with -eps < g <= 0 (index = slave triangle)."""
+    against every opposing master triangle, and with `features` the edge
+    and point samples of those triangles' edges and vertices.  Raises
+    OracleError(PENETRATION) for a sample with -eps < g <= 0 (index = slave
+    triangle)."""
     area = oracle.rest_area(P.xs_rest, P.ts)
     rule = P.rule
     eps = P.dhat
     tris = range(P.ts.shape[0]) if tris is None else tris
-    hm = None
     out = []
     for T in tris:
-        s = P.xs[P.ts[T]]
-        c = np.cross(s[1] - s[0], s[2] - s[0])
-        n = c / np.linalg.norm(c)
+        s0, e1, e2, n, _ = _frame(P, T)
         # heights of the master vertices above the slave plane: the gap is
         # their barycentric combination, so a master triangle entirely
         # beyond +eps or below -eps has no sample in range
-        hm = (P.xm - s[0]) @ n
-        h = hm[P.tm]
+        h = ((P.xm - s0) @ n)[P.tm]
         near = np.nonzero((h.min(1) < eps) & (h.max(1) > -eps))[0]
+        got = []
         for M in near:
-            for smp in pair_samples(P, T, int(M), area[T], rule):
-                if -eps < smp.g <= 0.0:
-                    raise oracle.OracleError(oracle.E_PENETRATION, T)
-                out.append(smp)
+            got += pair_samples(P, T, int(M), area[T], rule)
+        if features:
+            mm = P.xm[P.tm]
+            N = np.cross(mm[:, 1] - mm[:, 0], mm[:, 2] - mm[:, 0])
+            opposing = np.nonzero(N @ n < 0.0)[0]
+            got += feature_samples(P, T, opposing)
+        for smp in got:
+            if -eps < smp.g <= 0.0:
+                raise oracle.OracleError(oracle.E_PENETRATION, T)
+        out += got
     return out
 
 
@@ -137,29 +224,42 @@ class MortarAssembly:
     c2: np.ndarray
 
 
-def assemble(P: "oracle.Problem", smps, kinematic: bool = False, with_hessian: bool = True):
+def gamma(P: "oracle.Problem", smp, delta_e: float = 0.0) -> float:
+    """Master-feature weight, Eq. (gamma): f_T = H(min beta^m, delta_T) for
+    face samples, f_e = H(eta, delta_e) H(1 - eta, delta_e) for edge samples,
+    1 for point samples (H = 1 for a zero width)."""
+    if smp.kind == 2:
+        return oracle.hermite(min(smp.bm), P.delta_T) if P.delta_T > 0 else 1.0
+    if smp.kind == 1:
+        return (oracle.hermite(smp.eta, delta_e) * oracle.hermite(1.0 - smp.eta, delta_e)) if delta_e > 0 else 1.0
+    return 1.0
+
+
+def assemble(P: "oracle.Problem", smps, kinematic: bool = False, with_hessian: bool = True,
+             kappa_edge: float = 0.0, kappa_point: float = 0.0, delta_e: float = 0.0):
     """Energy, gradient and PSD Hessian of the active samples (Sec. 4.2,
     samples frozen): grad g = -bs_a n at slave vertex a, +bm_j n at master
-    vertex j; E_k = kappa w gamma B, c1 = kappa w gamma B', c2 = max(kappa
-    w gamma B'', 0)."""
+    vertex mv_j; E_k = kappa_q w gamma B, c1 = kappa_q w gamma B', c2 =
+    max(kappa_q w gamma B'', 0), kappa_q = P.kappa (faces), kappa_edge,
+    kappa_point (Eq. (gmcp_potential))."""
     Vs = P.Vs
     V = Vs + P.Vm
     grad = np.zeros((V, 3))
     blocks = {}
     E = 0.0
     act, c1s, c2s = [], [], []
+    kap = {2: P.kappa, 1: kappa_edge, 0: kappa_point}
     for smp in smps:
         if not (0.0 < smp.g < P.dhat):
             continue
-        gam = oracle.hermite(min(smp.bm), P.delta_T) if P.delta_T > 0 else 1.0
-        kw = P.kappa * smp.w * gam
+        kw = kap[smp.kind] * smp.w * gamma(P, smp, delta_e)
         E += kw * oracle.barrier(smp.g, P.dhat)
         c1 = kw * oracle.barrier_d1(smp.g, P.dhat)
         c2 = max(kw * oracle.barrier_d2(smp.g, P.dhat), 0.0)
         act.append(smp)
         c1s.append(c1)
         c2s.append(c2)
-        ids = [int(v) for v in P.ts[smp.T]] + ([] if kinematic else [Vs + int(v) for v in P.tm[smp.M]])
+        ids = [int(v) for v in P.ts[smp.T]] + ([] if kinematic else [Vs + int(v) for v in smp.mv])
         coef = list(-smp.bs) + ([] if kinematic else list(smp.bm))
         nn = np.outer(smp.n, smp.n)
         for i, ci in zip(ids, coef):
@@ -177,7 +277,7 @@ def linear_step(P: "oracle.Problem", active, dxs, dxm=None) -> float:
     for s in active:
         gd = -s.n @ (s.bs @ dxs[P.ts[s.T]])
         if dxm is not None:
-            gd += s.n @ (s.bm @ dxm[P.tm[s.M]])
+            gd += s.n @ (s.bm @ dxm[s.mv])
         if gd < 0.0:
             a = min(a, 0.9 * s.g / (-gd))
     return a

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gen import workloads
+from gen import meshes, workloads
 from oracle import mortar
 
 
@@ -130,3 +130,70 @@ def test_penetration_reported():
     with pytest.raises(oracle.OracleError) as e:
         mortar.samples(P)
     assert e.value.code == oracle.E_PENETRATION
+
+
+def _single_master(heights=(3e-4, 3e-4, 3e-4)):
+    """A flat pad under one opposing master triangle (vertices off the pad's edges)."""
+    xs, ts = meshes.pad(6, 1e-2)
+    xm = np.array([[-3.1e-3, -2.7e-3, heights[0]], [3.3e-3, -1.9e-3, heights[1]], [0.4e-3, 3.6e-3, heights[2]]])
+    tm = np.array([[0, 2, 1]])      # normal along -z: opposing the pad
+    return oracle.Problem(xs, ts, xm, tm, 2, 1e5, 1e-3, 0.0, None, xs)
+
+
+def test_edge_and_point_samples_of_one_triangle():
+    """Point samples: one per master vertex, at its height, weight 1; edge
+    samples: the weights of every edge sum to its length over the pad, and
+    sum w g integrates the (linear) gap along the edge exactly."""
+    P = _single_master((3e-4, 5e-4, 4e-4))
+    S = mortar.samples(P, features=True)
+    pts = [s for s in S if s.kind == 0]
+    assert sorted(int(s.mv[0]) for s in pts) == [0, 1, 2]
+    for s in pts:
+        assert s.w == 1.0 and abs(s.g - P.xm[s.mv[0], 2]) < 1e-15
+    for a, b in ((0, 1), (1, 2), (0, 2)):
+        es = [s for s in S if s.kind == 1 and sorted(s.mv.tolist()) == [a, b]]
+        L = np.linalg.norm(P.xm[b] - P.xm[a])
+        assert abs(sum(s.w for s in es) / L - 1) < 1e-12
+        ref = L * (P.xm[a, 2] + P.xm[b, 2]) / 2
+        assert abs(sum(s.w * s.g for s in es) / ref - 1) < 1e-12
+        # the master point of every edge sample projects onto its slave point
+        for s in es:
+            xm_k = s.bm @ P.xm[s.mv]
+            xs_k = s.bs @ P.xs[P.ts[s.T]]
+            assert np.linalg.norm(np.cross(xm_k - xs_k, s.n)) < 1e-15
+
+
+def test_edge_weight_vanishes_at_endpoints():
+    P = _single_master()
+    S = [s for s in mortar.samples(P, features=True) if s.kind == 1]
+    for s in S:
+        f = mortar.gamma(P, s, delta_e=0.2)
+        ref = oracle.hermite(s.eta, 0.2) * oracle.hermite(1 - s.eta, 0.2)
+        assert abs(f - ref) < 1e-15
+    assert abs(mortar.gamma(P, S[0], delta_e=0.0) - 1.0) == 0.0
+    assert oracle.hermite(0.0, 0.2) == 0.0 and oracle.hermite(0.5, 0.2) == 1.0
+
+
+def test_feature_gradient_against_frozen_energy_differences():
+    P = _single_master((3e-4, 5e-4, 4e-4))
+    S = mortar.samples(P, features=True)
+    ke, kp = 2e2, 1e-2
+    A = mortar.assemble(P, S, kappa_edge=ke, kappa_point=kp, delta_e=0.1)
+    kap = {2: P.kappa, 1: ke, 0: kp}
+
+    def frozen(xs, xm):
+        E = 0.0
+        for s in A.active:
+            g = s.n @ (s.bm @ xm[s.mv] - s.bs @ xs[P.ts[s.T]])
+            E += kap[s.kind] * s.w * mortar.gamma(P, s, 0.1) * oracle.barrier(g, P.dhat)
+        return E
+
+    rng = np.random.default_rng(4)
+    ds = rng.normal(size=P.xs.shape) * 1e-6
+    dm = rng.normal(size=P.xm.shape) * 1e-6
+    h = 1e-3
+    fd = (frozen(P.xs + h * ds, P.xm + h * dm) - frozen(P.xs - h * ds, P.xm - h * dm)) / (2 * h)
+    an = float(np.sum(A.grad[:P.Vs] * ds) + np.sum(A.grad[P.Vs:] * dm))
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    kinds = {s.kind for s in A.active}
+    assert kinds == {0, 1, 2}
