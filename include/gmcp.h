@@ -37,6 +37,18 @@
  * and gmcp_sample_results is unavailable (GMCP_E_ARG); the active capacity
  * counts clipped samples.
  *
+ * Edge and point samples (GMCP_FEATURES with GMCP_MORTAR, Sec. 4.1).  The
+ * edges and vertices of the opposing candidate master triangles of a slave
+ * triangle T (each feature once) are projected along n_T into T: an edge is
+ * clipped by T to a parameter interval [t0, t1] and carries rule_n
+ * Gauss-Legendre points eta (master point (1 - eta) x_a + eta x_b, weight
+ * |x_b - x_a| (t1 - t0) W_j, a length, gamma = H(eta, delta_e) H(1 - eta,
+ * delta_e), stiffness kappa_edge); a vertex whose projection lies strictly
+ * inside T is one point sample (weight 1, gamma 1, stiffness kappa_point).
+ * Gaps, activity, gradient and Hessian as for face samples; each feature
+ * sample joins the (T, M) pair of the master triangle that owns the feature
+ * (the smallest-index opposing candidate containing it; manifold edges).
+ *
  * Environments.  n_env independent problems are concatenated: slave
  * vertices/triangles of environment e are [v_off[e], v_off[e+1]) and
  * [t_off[e], t_off[e+1]) (same for the master).  Triangle vertex ids are
@@ -83,7 +95,8 @@ typedef enum {
 enum {
   GMCP_F64 = 1,              /* positions and outputs in double              */
   GMCP_KINEMATIC_MASTER = 2, /* master is prescribed: drop its rows/columns  */
-  GMCP_MORTAR = 4            /* clipped mortar face samples (see below)      */
+  GMCP_MORTAR = 4,           /* clipped mortar face samples (see below)      */
+  GMCP_FEATURES = 8          /* plus edge and point samples (needs MORTAR)   */
 };
 
 /* Problem layout (all host memory, copied by gmcp_create). */
@@ -98,7 +111,10 @@ typedef struct {
   const double *dhat;          /* [n_env] host, support-radius bound eps_max            */
   const double *delta_T;       /* [n_env] host, face transition width; 0 => gamma = 1   */
   const double *cell;          /* [n_env] host or NULL, broad-phase cell size (m); 0 = auto */
-  uint32_t flags;              /* GMCP_F64 | GMCP_KINEMATIC_MASTER */
+  uint32_t flags;              /* GMCP_F64 | GMCP_KINEMATIC_MASTER | GMCP_MORTAR | GMCP_FEATURES */
+  const double *kappa_edge;    /* [n_env] host or NULL (0): kappa of edge samples (GMCP_FEATURES)  */
+  const double *kappa_point;   /* [n_env] host or NULL (0): kappa of point samples (GMCP_FEATURES) */
+  const double *delta_e;       /* [n_env] host or NULL (0): edge transition width, Eq. (gamma)     */
 } gmcp_layout;
 
 /* Capacities of the data-dependent buffers carved from the workspace.

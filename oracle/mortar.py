@@ -146,18 +146,18 @@ def feature_samples(P: "oracle.Problem", T: int, opposing):
     proj = lambda x: np.linalg.solve(G, np.array([(x - s0) @ e1, (x - s0) @ e2]))
     xg, wg = np.polynomial.legendre.leggauss(P.rule_n)
     xg, wg = (xg + 1.0) / 2.0, wg / 2.0
-    edges, verts = set(), set()
-    for M in opposing:
-        a, b, c = (int(v) for v in P.tm[M])
-        for u, v in ((a, b), (b, c), (c, a)):
-            edges.add((min(u, v), max(u, v)))
-        verts.update((a, b, c))
+    tri = P.tm[np.asarray(opposing, dtype=np.int64)]
+    ed = np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1)
+    ed = np.unique(ed, axis=0) if ed.size else ed.reshape(0, 2)
+    hv = (P.xm - s0) @ n
+    # an edge entirely beyond +eps or below -eps has no sample in range
+    keep = (np.minimum(hv[ed[:, 0]], hv[ed[:, 1]]) < P.dhat) & (np.maximum(hv[ed[:, 0]], hv[ed[:, 1]]) > -P.dhat)
+    verts = np.unique(tri)
     out = []
-    for a, b in sorted(edges):
+    for a, b in ed[keep]:
+        a, b = int(a), int(b)
         xa, xb = P.xm[a], P.xm[b]
         ha, hb = (xa - s0) @ n, (xb - s0) @ n
-        if min(ha, hb) >= P.dhat or max(ha, hb) <= -P.dhat:
-            continue
         qa, qb = proj(xa), proj(xb)
         seg = clip_segment(qa, qb)
         if seg is None:
@@ -170,7 +170,8 @@ def feature_samples(P: "oracle.Problem", T: int, opposing):
             bs = np.array([1.0 - y[0] - y[1], y[0], y[1]])
             out.append(Sample(T, -1, bs, np.array([1.0 - eta, eta]), L * (t1 - t0) * wj,
                               float((1.0 - eta) * ha + eta * hb), n, np.array([a, b]), 1, float(eta)))
-    for p in sorted(verts):
+    for p in verts[np.abs(hv[verts]) < P.dhat]:
+        p = int(p)
         h = float((P.xm[p] - s0) @ n)
         if not (-P.dhat < h < P.dhat):
             continue

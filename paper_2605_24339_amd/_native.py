@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libgmcp.so")
 
 GMCP_OK, GMCP_E_ARG, GMCP_E_CAPACITY, GMCP_E_PENETRATION = 0, 1, 2, 3
 GMCP_E_DEGENERATE, GMCP_E_NONFINITE, GMCP_E_HIP = 4, 5, 6
-GMCP_F64, GMCP_KINEMATIC_MASTER, GMCP_MORTAR = 1, 2, 4
+GMCP_F64, GMCP_KINEMATIC_MASTER, GMCP_MORTAR, GMCP_FEATURES = 1, 2, 4, 8
 
 P = C.c_void_p
 i32p = C.POINTER(C.c_int32)
@@ -25,7 +25,8 @@ class Layout(C.Structure):
                 ("slave_v_off", i32p), ("slave_t_off", i32p),
                 ("master_v_off", i32p), ("master_t_off", i32p),
                 ("rule_n", i32p), ("kappa", f64p), ("dhat", f64p), ("delta_T", f64p),
-                ("cell", f64p), ("flags", C.c_uint32)]
+                ("cell", f64p), ("flags", C.c_uint32),
+                ("kappa_edge", f64p), ("kappa_point", f64p), ("delta_e", f64p)]
 
 
 class Caps(C.Structure):

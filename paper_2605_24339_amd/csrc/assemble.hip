@@ -71,6 +71,8 @@ struct NarrowArgs {
   int64_t cap_pairs;
   double *tile_E;
   DevStatus *st;
+  bool features;                                   // clipped samples: edge and point samples too
+  const int32_t *m_opp, *m_vt_off, *m_vt;          // master edge neighbours, vertex adjacency
 };
 
 template <typename R>
@@ -390,7 +392,9 @@ struct MortarPair {   // one (T, M) pair, projected into T's (u, v) coordinates
   R q[3][2];          // projected master vertices
   R h[3];             // master vertex heights above T's plane
   R qi[2][2];         // inverse of [q1 - q0, q2 - q0]
-  bool ok;
+  R len[3];           // master edge lengths, edge k = (vertex k, vertex k+1)
+  bool opposing;      // n_T . N_M < 0 (q, h, len are set)
+  bool ok;            // face overlap possible (opposing, in the band, not edge-on)
 };
 
 template <typename R>
@@ -398,6 +402,7 @@ __device__ inline MortarPair<R> mortar_pair(const NarrowArgs<R> &a, int M, const
                                             const R e2[3], const R n[3], R gi11, R gi12, R gi22, R eps) {
   MortarPair<R> P;
   P.ok = false;
+  P.opposing = false;
   R p[3][3];
   for (int j = 0; j < 3; ++j) {
     const int64_t v = a.tm[3 * (int64_t)M + j];
@@ -410,6 +415,12 @@ __device__ inline MortarPair<R> mortar_pair(const NarrowArgs<R> &a, int M, const
   }
   const R N[3] = {f1[1] * f2[2] - f1[2] * f2[1], f1[2] * f2[0] - f1[0] * f2[2], f1[0] * f2[1] - f1[1] * f2[0]};
   if (!(n[0] * N[0] + n[1] * N[1] + n[2] * N[2] < R(0))) return P;  // not opposing
+  P.opposing = true;
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = k == 2 ? 0 : k + 1;
+    const R dx = p[k1][0] - p[k][0], dy = p[k1][1] - p[k][1], dz = p[k1][2] - p[k][2];
+    P.len[k] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
   R hmin = INFINITY, hmax = -INFINITY;
   for (int j = 0; j < 3; ++j) {
     P.h[j] = n[0] * p[j][0] + n[1] * p[j][1] + n[2] * p[j][2];
@@ -454,17 +465,21 @@ __device__ inline int mortar_clip(const MortarPair<R> &P, R (*buf)[6][2][kWave],
       const R qu = buf[src][i1][0][lane], qv = buf[src][i1][1][lane];
       const R fp = plane == 0 ? pu : (plane == 1 ? pv : R(1) - pu - pv);
       const R fq = plane == 0 ? qu : (plane == 1 ? qv : R(1) - qu - qv);
+      // a convex polygon gains at most one vertex per half-plane (6 in
+      // all); the cap only guards rounding-made non-convex inputs
       if (fp >= R(0)) {
-        buf[dst][out][0][lane] = pu;
-        buf[dst][out][1][lane] = pv;
-        ++out;
-        if (fq < R(0)) {
+        if (out < 6) {
+          buf[dst][out][0][lane] = pu;
+          buf[dst][out][1][lane] = pv;
+          ++out;
+        }
+        if (fq < R(0) && out < 6) {
           const R t = fp / (fp - fq);
           buf[dst][out][0][lane] = pu + (qu - pu) * t;
           buf[dst][out][1][lane] = pv + (qv - pv) * t;
           ++out;
         }
-      } else if (fq >= R(0)) {
+      } else if (fq >= R(0) && out < 6) {
         const R t = fp / (fp - fq);
         buf[dst][out][0][lane] = pu + (qu - pu) * t;
         buf[dst][out][1][lane] = pv + (qv - pv) * t;
@@ -483,10 +498,33 @@ __device__ inline int mortar_clip(const MortarPair<R> &P, R (*buf)[6][2][kWave],
   return cnt;
 }
 
+// parameter interval [t0, t1] of qa + t (qb - qa), t in [0, 1], inside the
+// reference triangle (Liang-Barsky); false if empty
+template <typename R>
+__device__ inline bool clip_seg(const R qa[2], const R qb[2], R &t0, R &t1) {
+  t0 = R(0);
+  t1 = R(1);
+  for (int f = 0; f < 3; ++f) {
+    const R fa = f == 0 ? qa[0] : (f == 1 ? qa[1] : R(1) - qa[0] - qa[1]);
+    const R fb = f == 0 ? qb[0] : (f == 1 ? qb[1] : R(1) - qb[0] - qb[1]);
+    const R d = fb - fa;
+    if (d == R(0)) {
+      if (fa < R(0)) return false;
+      continue;
+    }
+    const R t = -fa / d;
+    if (d > R(0)) t0 = fmax(t0, t);
+    else t1 = fmin(t1, t);
+  }
+  return t1 > t0;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   __shared__ R poly[2][6][2][kWave];
-  __shared__ uint64_t maskbuf[kMortarChunks][kWave];  // accepted samples of each lane's pair (bit (s-1) nq + q)
+  __shared__ uint64_t maskbuf[kMortarChunks][kWave];   // accepted face samples of each lane's pair
+  __shared__ uint32_t fmaskbuf[kMortarChunks][kWave];  // accepted edge (bit 4k + j) / point (bit 12 + k) samples
+  __shared__ uint8_t oflag[kMortarChunks * kWave];     // candidate i of the triangle is opposing
   const int lane = threadIdx.x;
   const int tile_id = xcd_block(blockIdx.x, gridDim.x);
   if (tile_id >= a.n_tiles) return;
@@ -494,8 +532,11 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   const Tile tl = a.tiles[tile_id];
   const EnvInfo &ev = a.env[tl.env];
   const R eps = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
-  const int nq = ev.nq;
+  const R kappa_e = (R)ev.kappa_e, kappa_p = (R)ev.kappa_p, delta_e = (R)ev.delta_e;
+  const int nq = ev.nq, ng = ev.rule_n;
   const double *rule = a.rule + (ev.rule_n - 1) * 16 * 3;
+  const double *gl = a.rule + kGaussOff + (ev.rule_n - 1) * 4 * 2;
+  const bool features = a.features;
   R(*buf)[6][2][kWave] = poly;
   double E = 0.0;
   const uint64_t below = (1ull << lane) - 1;
@@ -534,15 +575,76 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
     const R gi11 = g22 / gdet, gi12 = -g12 / gdet, gi22 = g11 / gdet;
     const R area = a.area[T];
     const int nchunk = (cn + kWave - 1) / kWave;
+    auto pair_of = [&](int M) { return mortar_pair(a, M, s0, e1, e2, n, gi11, gi12, gi22, eps); };
 
-    // ---- counting pass: active samples per candidate pair
+    // ---- feature ownership: an edge or vertex belongs to the smallest-index
+    // opposing candidate master triangle that contains it
+    if (features) {
+      wave_sync();
+      for (int ci = lane; ci < cn && ci < kMortarChunks * kWave; ci += kWave)
+        oflag[ci] = pair_of(a.cand[cb + ci]).opposing ? 1 : 0;
+      wave_sync();
+    }
+    auto cand_opposing = [&](int t) -> bool {
+      int lo = 0, hi = cn < kMortarChunks * kWave ? cn : kMortarChunks * kWave;
+      const int end = hi;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.cand[cb + mid] < t) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo < end && a.cand[cb + lo] == t && oflag[lo];
+    };
+    auto owns_edge = [&](int M, int k) -> bool {
+      const int o = a.m_opp[3 * (int64_t)M + k];
+      return o < 0 || o > M || !cand_opposing(o);
+    };
+    auto owns_vertex = [&](int M, int k) -> bool {
+      const int v = a.tm[3 * (int64_t)M + k];
+      for (int i = a.m_vt_off[v]; i < a.m_vt_off[v + 1]; ++i) {  // incident triangles, ascending
+        const int t = a.m_vt[i] >> 2;
+        if (t == M) return true;
+        if (cand_opposing(t)) return false;
+      }
+      return true;
+    };
+    // edge / point samples of an opposing pair: bit 4k + j (edge k, Gauss
+    // point j), bit 12 + k (vertex k)
+    auto feature_mask = [&](const MortarPair<R> &P, int M, bool &pen_) -> uint32_t {
+      uint32_t fm = 0;
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        if (!(fmin(P.h[k], P.h[k1]) < eps && fmax(P.h[k], P.h[k1]) > -eps)) continue;
+        R t0, t1;
+        if (!clip_seg(P.q[k], P.q[k1], t0, t1)) continue;
+        if (!owns_edge(M, k)) continue;
+        for (int jj = 0; jj < ng; ++jj) {
+          const R eta = t0 + (t1 - t0) * (R)gl[2 * jj];
+          const R g = (R(1) - eta) * P.h[k] + eta * P.h[k1];
+          if (g > R(0) && g < eps) fm |= 1u << (4 * k + jj);
+          else if (g > -eps && g <= R(0)) pen_ = true;
+        }
+      }
+      for (int k = 0; k < 3; ++k) {
+        const R h = P.h[k], u = P.q[k][0], v = P.q[k][1];
+        if (!(h > -eps && h < eps) || !(u > R(0) && v > R(0) && R(1) - u - v > R(0))) continue;
+        if (!owns_vertex(M, k)) continue;
+        if (h > R(0)) fm |= 1u << (12 + k);
+        else pen_ = true;
+      }
+      return fm;
+    };
+
+    // ---- counting pass: accepted samples per candidate pair (bit masks)
     int nrec = 0, npair = 0;
     bool pen = false;
     for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
       const int ci = ch * kWave + lane;
       uint64_t mask = 0;
+      uint32_t fmask = 0;
       if (ci < cn) {
-        const MortarPair<R> P = mortar_pair(a, a.cand[cb + ci], s0, e1, e2, n, gi11, gi12, gi22, eps);
+        const int M = a.cand[cb + ci];
+        const MortarPair<R> P = pair_of(M);
         if (P.ok) {
           const int m = mortar_clip(P, buf, lane);
           for (int s = 1; s + 1 < m; ++s) {
@@ -561,9 +663,11 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
             }
           }
         }
+        if (features && P.opposing) fmask = feature_mask(P, M, pen);
       }
       maskbuf[ch][lane] = mask;
-      const int cntl = __popcll(mask);
+      fmaskbuf[ch][lane] = fmask;
+      const int cntl = __popcll(mask) + __popc(fmask);
       const uint64_t pm = __ballot(cntl > 0);
       npair += __popcll(pm);
       int tot = cntl;
@@ -582,21 +686,26 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
     const bool rec_ok = rbase + nrec <= (unsigned long long)a.cap_active;
     const bool pair_ok = pbase + npair <= (unsigned long long)a.cap_pairs;
     if (lane == 0 && ((nrec && !rec_ok) || (npair && !pair_ok))) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
+    // every allocated pair slot is written whenever the pairs fit (the
+    // bucket kernels read all n_pairs slots); records only when they fit too
+    const bool write_rec = rec_ok && pair_ok;
     if (lane == 0) {
-      a.tri_npair[T] = npair;
+      a.tri_npair[T] = pair_ok ? npair : 0;
       a.tri_poff[T] = (int32_t)pbase;
-      a.tri_rcnt[T] = nrec;
+      a.tri_rcnt[T] = write_rec ? nrec : 0;
       a.tri_roff[T] = (int32_t)rbase;
     }
-    if (nrec == 0 || !rec_ok || !pair_ok) continue;
+    if (nrec == 0 || !pair_ok) continue;
 
-    // ---- writing pass
+    // ---- writing pass: exactly the samples of the masks, so the records
+    // written always fill the allocated range
     R ts_[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // c2 bs_a bs_b (00 01 02 11 12 22), c1 bs_a
     unsigned long long roff = rbase, poff = pbase;
     for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
       const int ci = ch * kWave + lane;
       const uint64_t mask = maskbuf[ch][lane];
-      const int cntl = __popcll(mask);
+      const uint32_t fmask = fmaskbuf[ch][lane];
+      const int cntl = __popcll(mask) + __popc(fmask);
       int incl = cntl;
       for (int d = 1; d < kWave; d <<= 1) {
         const int v = __shfl_up(incl, d, kWave);
@@ -609,78 +718,100 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
       poff += __popcll(pm);
       if (cntl == 0) continue;
       const int M = a.cand[cb + ci];
-      const MortarPair<R> P = mortar_pair(a, M, s0, e1, e2, n, gi11, gi12, gi22, eps);
-      mortar_clip(P, buf, lane);
+      const MortarPair<R> P = pair_of(M);
       Pair<R> pr;
       pr.T = T;
       pr.M = M;
       for (int z = 0; z < 6; ++z) pr.mm[z] = 0;
       for (int z = 0; z < 9; ++z) pr.sm[z] = 0;
       for (int z = 0; z < 3; ++z) pr.gm[z] = 0;
-      // exactly the samples the counting pass accepted (the mask), so the
-      // records written always fill the allocated range
-      for (uint64_t bits = mask; bits; bits &= bits - 1) {
-        const int idx = __ffsll((unsigned long long)bits) - 1;
-        const int s = idx / nq + 1, qq = idx - (s - 1) * nq;
-        const int s1i = s < 5 ? s : 4, s2i = s + 1 < 6 ? s + 1 : 5;  // in-range LDS reads
-        const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
-        const R Bu = buf[0][s1i][0][lane] - Au, Bv = buf[0][s1i][1][lane] - Av;
-        const R Cu = buf[0][s2i][0][lane] - Au, Cv = buf[0][s2i][1][lane] - Av;
-        const R a2 = fabs(Bu * Cv - Bv * Cu);  // twice the (u, v) area
-        {
+      // one active sample: slave point (u, v), master coefficients on M's
+      // vertices, gap, kappa_q w gamma
+      auto emit = [&](R u, R v, const R bm[3], R graw, R kw, R kap, R gam) {
+        // the counting pass accepted 0 < g < eps; a recomputation that rounds
+        // differently is clamped into the band
+        const R g = fmin(fmax(graw, eps * R(1e-6)), eps);
+        const R dd = g - eps;
+        const R L = log1p_r<R>(dd / eps);
+        const R B = -dd * dd * L;
+        const R B1 = -R(2) * dd * L - dd * dd / g;
+        const R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
+        const R c1 = kw * B1, c2 = fmax(kw * B2, R(0));
+        E += (double)(kw * B);
+        const R bs[3] = {R(1) - u - v, u, v};
+        ts_[0] += c2 * bs[0] * bs[0];
+        ts_[1] += c2 * bs[0] * bs[1];
+        ts_[2] += c2 * bs[0] * bs[2];
+        ts_[3] += c2 * bs[1] * bs[1];
+        ts_[4] += c2 * bs[1] * bs[2];
+        ts_[5] += c2 * bs[2] * bs[2];
+        for (int z = 0; z < 3; ++z) ts_[6 + z] += c1 * bs[z];
+        pr.mm[0] += c2 * bm[0] * bm[0];
+        pr.mm[1] += c2 * bm[0] * bm[1];
+        pr.mm[2] += c2 * bm[0] * bm[2];
+        pr.mm[3] += c2 * bm[1] * bm[1];
+        pr.mm[4] += c2 * bm[1] * bm[2];
+        pr.mm[5] += c2 * bm[2] * bm[2];
+        for (int s2 = 0; s2 < 3; ++s2)
+          for (int m2 = 0; m2 < 3; ++m2) pr.sm[3 * s2 + m2] -= c2 * bs[s2] * bm[m2];
+        for (int m2 = 0; m2 < 3; ++m2) pr.gm[m2] += c1 * bm[m2];
+        Rec<R> rc;
+        rc.k = -1;
+        rc.M = M;
+        rc.T = T;
+        rc.q = -1;
+        rc.g = g;
+        rc.b0 = bm[0];
+        rc.b1 = bm[1];
+        rc.b2 = bm[2];
+        rc.c1 = c1;
+        rc.c2 = c2;
+        rc.p = -kap * gam * B1;
+        rc.eps = eps;
+        rc.s1 = u;
+        rc.s2 = v;
+        rc.kwg = kw;
+        rc.pad = 0;
+        if (write_rec) a.rec[r++] = rc;
+      };
+      if (mask) {
+        mortar_clip(P, buf, lane);
+        for (uint64_t bits = mask; bits; bits &= bits - 1) {
+          const int idx = __ffsll((unsigned long long)bits) - 1;
+          const int s = idx / nq + 1, qq = idx - (s - 1) * nq;
+          const int s1i = s < 5 ? s : 4, s2i = s + 1 < 6 ? s + 1 : 5;  // in-range LDS reads
+          const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
+          const R Bu = buf[0][s1i][0][lane] - Au, Bv = buf[0][s1i][1][lane] - Av;
+          const R Cu = buf[0][s2i][0][lane] - Au, Cv = buf[0][s2i][1][lane] - Av;
+          const R a2 = fabs(Bu * Cv - Bv * Cu);  // twice the (u, v) area
           const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1], wq = (R)rule[3 * qq + 2];
           const R u = Au + xi * Bu + eta * Cu, v = Av + xi * Bv + eta * Cv;
           const R yu = u - P.q[0][0], yv = v - P.q[0][1];
           const R b1 = P.qi[0][0] * yu + P.qi[0][1] * yv, b2 = P.qi[1][0] * yu + P.qi[1][1] * yv;
-          const R b0 = R(1) - b1 - b2;
-          // the counting pass accepted 0 < g < eps; a recomputation that
-          // rounds differently is clamped into the band
-          const R g = fmin(fmax(b0 * P.h[0] + b1 * P.h[1] + b2 * P.h[2], eps * R(1e-6)), eps);
-          const R gam = deltaT > R(0) ? hermite(fmin(b0, fmin(b1, b2)), deltaT) : R(1);
-          const R wk = R(2) * (a2 * area) * wq;
-          const R dd = g - eps;
-          const R L = log1p_r<R>(dd / eps);
-          const R B = -dd * dd * L;
-          const R B1 = -R(2) * dd * L - dd * dd / g;
-          const R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
-          const R kw = kappa * wk * gam;
-          const R c1 = kw * B1, c2 = fmax(kw * B2, R(0));
-          E += (double)(kw * B);
-          const R bs[3] = {R(1) - u - v, u, v}, bm[3] = {b0, b1, b2};
-          ts_[0] += c2 * bs[0] * bs[0];
-          ts_[1] += c2 * bs[0] * bs[1];
-          ts_[2] += c2 * bs[0] * bs[2];
-          ts_[3] += c2 * bs[1] * bs[1];
-          ts_[4] += c2 * bs[1] * bs[2];
-          ts_[5] += c2 * bs[2] * bs[2];
-          for (int z = 0; z < 3; ++z) ts_[6 + z] += c1 * bs[z];
-          pr.mm[0] += c2 * bm[0] * bm[0];
-          pr.mm[1] += c2 * bm[0] * bm[1];
-          pr.mm[2] += c2 * bm[0] * bm[2];
-          pr.mm[3] += c2 * bm[1] * bm[1];
-          pr.mm[4] += c2 * bm[1] * bm[2];
-          pr.mm[5] += c2 * bm[2] * bm[2];
-          for (int s2 = 0; s2 < 3; ++s2)
-            for (int m2 = 0; m2 < 3; ++m2) pr.sm[3 * s2 + m2] -= c2 * bs[s2] * bm[m2];
-          for (int m2 = 0; m2 < 3; ++m2) pr.gm[m2] += c1 * bm[m2];
-          Rec<R> rc;
-          rc.k = -1;
-          rc.M = M;
-          rc.T = T;
-          rc.q = -1;
-          rc.g = g;
-          rc.b0 = b0;
-          rc.b1 = b1;
-          rc.b2 = b2;
-          rc.c1 = c1;
-          rc.c2 = c2;
-          rc.p = -kappa * gam * B1;
-          rc.eps = eps;
-          rc.s1 = u;
-          rc.s2 = v;
-          rc.kwg = kw;
-          rc.pad = 0;
-          a.rec[r++] = rc;
+          const R bm[3] = {R(1) - b1 - b2, b1, b2};
+          const R gam = deltaT > R(0) ? hermite(fmin(bm[0], fmin(bm[1], bm[2])), deltaT) : R(1);
+          emit(u, v, bm, bm[0] * P.h[0] + bm[1] * P.h[1] + bm[2] * P.h[2], kappa * R(2) * (a2 * area) * wq * gam,
+               kappa, gam);
+        }
+      }
+      for (uint32_t bits = fmask; bits; bits &= bits - 1) {
+        const int idx = __ffs(bits) - 1;
+        R bm[3] = {0, 0, 0};
+        if (idx < 12) {  // edge k, Gauss point jj
+          const int k = idx >> 2, jj = idx & 3, k1 = k == 2 ? 0 : k + 1;
+          R t0, t1;
+          clip_seg(P.q[k], P.q[k1], t0, t1);
+          const R eta = t0 + (t1 - t0) * (R)gl[2 * jj];
+          bm[k] = R(1) - eta;
+          bm[k1] = eta;
+          const R u = P.q[k][0] + eta * (P.q[k1][0] - P.q[k][0]), v = P.q[k][1] + eta * (P.q[k1][1] - P.q[k][1]);
+          const R gam = delta_e > R(0) ? hermite(eta, delta_e) * hermite(R(1) - eta, delta_e) : R(1);
+          const R w = P.len[k] * (t1 - t0) * (R)gl[2 * jj + 1];
+          emit(u, v, bm, (R(1) - eta) * P.h[k] + eta * P.h[k1], kappa_e * w * gam, kappa_e, gam);
+        } else {  // vertex k: one point sample, weight 1
+          const int k = idx - 12;
+          bm[k] = R(1);
+          emit(P.q[k][0], P.q[k][1], bm, P.h[k], kappa_p, kappa_p, R(1));
         }
       }
       a.pair[pslot] = pr;
@@ -695,7 +826,6 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, kWave);
   if (lane == 0) a.tile_E[tile_id] = E;
 }
-
 
 // ---------------------------------------------------- pairs by master tri
 // pass 0: count pairs per master triangle; pass 1: place (slave triangle,
@@ -1388,6 +1518,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.cap_pairs = c->caps.pairs;
   na.tile_E = b.tile_E;
   na.st = b.status;
+  na.features = c->features;
+  na.m_opp = b.m_opp;
+  na.m_vt_off = b.m_vt_off;
+  na.m_vt = b.m_vt;
   prof_mark(c, ST_NARROW, 0);
   if (c->n_tiles) {
     if (c->mortar)

@@ -57,8 +57,8 @@ __device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
 }
 
 // Eq. (ccd): alpha_k = 0.9 g_k / (-grad g_k . dx) for grad g_k . dx < 0.
-// One wave per work tile (the narrow phase's Morton tiles): lane (j, r) takes
-// record r of the tile's triangle j (a triangle's records are contiguous),
+// One wave per work tile (the narrow phase's Morton tiles): lane (j, r0) takes
+// records r0, r0 + nq, ... of the tile's triangle j (contiguous per triangle),
 // so the triangle's normal and slave displacements are shared loads and the
 // wave belongs to one environment (one atomic per block and environment).
 template <typename R>
@@ -81,11 +81,14 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
   if (ok) {
     const Tile tl = tiles[tile_id];
     e = tl.env;
-    const int j = lane / tl.nq, r = lane - j * tl.nq;
+    const int j = lane / tl.nq, r0 = lane - j * tl.nq;
     if (j < tl.count) {
       const int T = s_order[tl.first + j];
-      if (r < tri_rcnt[T]) {
-        const Rec<R> rc = rec[tri_roff[T] + r];
+      // a triangle's records: nq of them with whole-triangle samples, any
+      // number with clipped mortar samples
+      const int rcnt = tri_rcnt[T], roff = tri_roff[T];
+      for (int r = r0; r < rcnt; r += tl.nq) {
+        const Rec<R> rc = rec[roff + r];
         const R *n = tri_nrm + 3 * (int64_t)T;
         const R bs[3] = {R(1) - rc.s1 - rc.s2, rc.s1, rc.s2};
         const R bm[3] = {rc.b0, rc.b1, rc.b2};
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
             const R *d = dxm + 3 * (int64_t)tm[3 * (int64_t)rc.M + m];
             gd += bm[m] * (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]);
           }
-        if (gd < R(0)) a = to_float_down<R>(R(0.9) * rc.g / (-gd));
+        if (gd < R(0)) a = fminf(a, to_float_down<R>(R(0.9) * rc.g / (-gd)));
       }
     }
   }

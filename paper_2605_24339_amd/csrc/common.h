@@ -19,6 +19,8 @@ namespace gmcp {
 
 constexpr int kWave = 64;
 constexpr int kMaxRule = 4;            // n <= 4  => <= 16 samples per triangle
+constexpr int kRuleDoubles = kMaxRule * 16 * 3 + kMaxRule * 4 * 2;  // 2D rules, then 1D Gauss-Legendre
+constexpr int kGaussOff = kMaxRule * 16 * 3;
 constexpr int kTilePerBlock = 4;       // narrow phase: 4 waves, one tile each
 
 // ---------------------------------------------------------------- status
@@ -33,6 +35,7 @@ struct DevStatus {
 // --------------------------------------------------------- per environment
 struct EnvInfo {
   double kappa, dhat, delta_T, cell;
+  double kappa_e, kappa_p, delta_e;  // edge / point samples (GMCP_FEATURES)
   int32_t rule_n, nq;
   int32_t sv0, sv1, st0, st1;   // slave vertex / triangle ranges
   int32_t mv0, mv1, mt0, mt1;   // master ranges
@@ -75,7 +78,8 @@ struct Buffers {
   Tile *tiles;
   int32_t *s_order, *samp_off, *s_env, *m_env;
   int32_t *s_vt_off, *s_vt, *m_vt_off, *m_vt;   // vt entries: tri*4 + corner
-  double *rule;                                 // [4][16][3] xi, eta, w
+  double *rule;                                 // [4][16][3] xi, eta, w; then [4][4][2] 1D Gauss-Legendre
+  int32_t *m_opp;                               // [Tm][3] triangle across edge k of a master triangle, -1
   void *area;                                   // [Ts] R
   // broad phase
   GridEnv *grid;
@@ -148,7 +152,7 @@ struct Prof {
 struct gmcp_ctx {
   gmcp::Prof prof;
   hipStream_t stream;
-  bool f64, kinematic, mortar;
+  bool f64, kinematic, mortar, features;
   int n_env;
   int64_t Vs, Vm, Ts, Tm, Ns, V, n_tiles, total_cells;
   gmcp_caps caps;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <new>
+#include <map>
 #include <vector>
 
 #include "common.h"
@@ -77,8 +78,10 @@ void gauss_from_recurrence(const Recurrence &r, int n, double *x, double *w) {
 }
 
 // rule[n-1][q][3] = (xi, eta, w) of the n x n Stroud conical product rule
+// and, from kGaussOff, gl[n-1][j][2] = (node, weight) of the n-point
+// Gauss-Legendre rule on [0, 1] (edge samples)
 void build_rules(double *rule) {
-  memset(rule, 0, sizeof(double) * kMaxRule * 16 * 3);
+  memset(rule, 0, sizeof(double) * kRuleDoubles);
   for (int n = 1; n <= kMaxRule; ++n) {
     // Jacobi (alpha=1, beta=0): weight (1-x), mu0 = 2,
     // a_k = -1/((2k+1)(2k+3)), b_k = k(k+1)/(2k+1)^2
@@ -104,6 +107,11 @@ void build_rules(double *rule) {
         r[1] = v * (1.0 - u);
         r[2] = Wu * Wv;
       }
+    for (int j = 0; j < n; ++j) {
+      double *g = rule + kGaussOff + ((n - 1) * 4 + j) * 2;
+      g[0] = 0.5 * (1.0 + xl[j]);
+      g[1] = 0.5 * wl[j];
+    }
   }
 }
 
@@ -123,7 +131,7 @@ struct Plan {
 struct Sizes {
   int n_env;
   int64_t Vs, Vm, Ts, Tm, Ns, V, n_tiles, cells;
-  bool f64, kin;
+  bool f64, kin, feat;
 };
 
 bool layout_sizes(const gmcp_layout *L, Sizes *s) {
@@ -133,6 +141,8 @@ bool layout_sizes(const gmcp_layout *L, Sizes *s) {
   s->n_env = L->n_env;
   s->f64 = (L->flags & GMCP_F64) != 0;
   s->kin = (L->flags & GMCP_KINEMATIC_MASTER) != 0;
+  s->feat = (L->flags & GMCP_FEATURES) != 0;
+  if (s->feat && !(L->flags & GMCP_MORTAR)) return false;  // edge / point samples join clipped face samples
   if (L->slave_v_off[0] != 0 || L->slave_t_off[0] != 0 || L->master_v_off[0] != 0 ||
       L->master_t_off[0] != 0)
     return false;
@@ -175,7 +185,8 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.s_vt = p.take<int32_t>(3 * s.Ts);
   t.m_vt_off = p.take<int32_t>(s.Vm + 1);
   t.m_vt = p.take<int32_t>(3 * s.Tm);
-  t.rule = p.take<double>(kMaxRule * 16 * 3);
+  t.rule = p.take<double>(kRuleDoubles);
+  t.m_opp = p.take<int32_t>(s.feat ? 3 * s.Tm : 0);
   t.area = p.take<char>(rsz * s.Ts);
   t.grid = p.take<GridEnv>(s.n_env);
   t.box = p.take<uint32_t>(6 * s.n_env);
@@ -296,6 +307,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->f64 = s.f64;
   c->kinematic = s.kin;
   c->mortar = (L->flags & GMCP_MORTAR) != 0;
+  c->features = s.feat;
   c->n_env = s.n_env;
   c->Vs = s.Vs;
   c->Vm = s.Vm;
@@ -336,6 +348,9 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
     v.dhat = L->dhat[en];
     v.delta_T = L->delta_T[en];
     v.cell = L->cell ? L->cell[en] : 0.0;
+    v.kappa_e = L->kappa_edge ? L->kappa_edge[en] : 0.0;
+    v.kappa_p = L->kappa_point ? L->kappa_point[en] : 0.0;
+    v.delta_e = L->delta_e ? L->delta_e[en] : 0.0;
     v.rule_n = L->rule_n[en];
     v.nq = v.rule_n * v.rule_n;
     v.sv0 = L->slave_v_off[en];
@@ -397,7 +412,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   std::vector<int32_t> svo, svt, mvo, mvt;
   adjacency(s.Vs, s.Ts, ts, svo, svt);
   adjacency(s.Vm, s.Tm, tm, mvo, mvt);
-  std::vector<double> rule(kMaxRule * 16 * 3);
+  std::vector<double> rule(kRuleDoubles);
   build_rules(rule.data());
 
   auto up = [&](void *dst, const void *src, size_t n) {
@@ -412,6 +427,24 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   up(c->b.m_vt_off, mvo.data(), sizeof(int32_t) * (s.Vm + 1));
   up(c->b.m_vt, mvt.data(), sizeof(int32_t) * 3 * s.Tm);
   up(c->b.rule, rule.data(), sizeof(double) * rule.size());
+  if (s.feat && s.Tm) {
+    // triangle across each master edge (manifold edges; -1 on the boundary)
+    std::vector<int32_t> opp(3 * s.Tm, -1);
+    std::map<std::pair<int32_t, int32_t>, int64_t> edge;
+    for (int64_t t = 0; t < s.Tm; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int32_t a = tm[3 * t + k], b = tm[3 * t + (k + 1) % 3];
+        auto key = std::make_pair(std::min(a, b), std::max(a, b));
+        auto it = edge.find(key);
+        if (it == edge.end()) {
+          edge.emplace(key, 3 * t + k);
+        } else {
+          opp[3 * t + k] = (int32_t)(it->second / 3);
+          opp[it->second] = (int32_t)t;
+        }
+      }
+    up(c->b.m_opp, opp.data(), sizeof(int32_t) * opp.size());
+  }
   DevStatus st{};
   st.index = ~0ull;
   up(c->b.status, &st, sizeof(st));
@@ -446,7 +479,7 @@ int64_t gmcp_num_samples(const gmcp_ctx *c) { return c ? c->Ns : -1; }
 
 int gmcp_rule(int n, double *out) {
   if (n < 1 || n > kMaxRule || !out) return GMCP_E_ARG;
-  std::vector<double> rule(kMaxRule * 16 * 3);
+  std::vector<double> rule(kRuleDoubles);
   build_rules(rule.data());
   memcpy(out, rule.data() + (n - 1) * 16 * 3, sizeof(double) * 3 * n * n);
   return GMCP_OK;

@@ -64,19 +64,24 @@ class Context:
     (eps_max), delta_T (face transition width), cell (broad-phase cell size,
     0 = automatic).  mortar=True uses clipped mortar face samples (every
     opposing pair's projected overlap, fan-triangulated, n x n rule per
-    sub-triangle) instead of one whole-triangle rule per slave triangle.
+    sub-triangle) instead of one whole-triangle rule per slave triangle;
+    features=True adds edge and point samples of the opposing master
+    triangles (stiffnesses kappa_edge, kappa_point, edge transition width
+    delta_e per environment).
     """
 
     def __init__(self, slave_tri, master_tri, slave_v_off, slave_t_off, master_v_off, master_t_off,
                  rule_n, kappa, dhat, delta_T, cell=None, dtype=torch.float32, kinematic=False,
-                 caps: dict | None = None, device="cuda", mortar: bool = False):
+                 caps: dict | None = None, device="cuda", mortar: bool = False, features: bool = False,
+                 kappa_edge=None, kappa_point=None, delta_e=None):
         N.lib()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         self.kinematic = bool(kinematic)
-        self.mortar = bool(mortar)
+        self.mortar = bool(mortar) or bool(features)
+        self.features = bool(features)
         self.ts = torch.as_tensor(slave_tri, dtype=torch.int32).to(self.device).contiguous()
         self.tm = torch.as_tensor(master_tri, dtype=torch.int32).to(self.device).contiguous()
         self.n_env = len(rule_n)
@@ -85,16 +90,20 @@ class Context:
         self._keep = dict(svo=as_i32(slave_v_off), sto=as_i32(slave_t_off), mvo=as_i32(master_v_off),
                           mto=as_i32(master_t_off), rule=as_i32(rule_n), kappa=as_f64(kappa),
                           dhat=as_f64(dhat), dT=as_f64(delta_T),
-                          cell=as_f64(cell if cell is not None else [0.0] * self.n_env))
+                          cell=as_f64(cell if cell is not None else [0.0] * self.n_env),
+                          ke=as_f64(kappa_edge if kappa_edge is not None else [0.0] * self.n_env),
+                          kp=as_f64(kappa_point if kappa_point is not None else [0.0] * self.n_env),
+                          de=as_f64(delta_e if delta_e is not None else [0.0] * self.n_env))
         k = self._keep
         flags = ((N.GMCP_F64 if dtype == torch.float64 else 0) | (N.GMCP_KINEMATIC_MASTER if kinematic else 0)
-                 | (N.GMCP_MORTAR if mortar else 0))
+                 | (N.GMCP_MORTAR if self.mortar else 0) | (N.GMCP_FEATURES if self.features else 0))
         cast = lambda a, t: C.cast(a, C.POINTER(t))
         self.layout = N.Layout(self.n_env, cast(k["svo"], C.c_int32), cast(k["sto"], C.c_int32),
                                cast(k["mvo"], C.c_int32), cast(k["mto"], C.c_int32),
                                cast(k["rule"], C.c_int32), cast(k["kappa"], C.c_double),
                                cast(k["dhat"], C.c_double), cast(k["dT"], C.c_double),
-                               cast(k["cell"], C.c_double), flags)
+                               cast(k["cell"], C.c_double), flags, cast(k["ke"], C.c_double),
+                               cast(k["kp"], C.c_double), cast(k["de"], C.c_double))
         self.Vs, self.Ts = int(slave_v_off[-1]), int(slave_t_off[-1])
         self.Vm, self.Tm = int(master_v_off[-1]), int(master_t_off[-1])
         self.Ns = sum((int(slave_t_off[e + 1]) - int(slave_t_off[e])) * int(rule_n[e]) ** 2
@@ -102,7 +111,8 @@ class Context:
         self.V = self.Vs if kinematic else self.Vs + self.Vm
         c = dict(grid_cells=8 * (self.Ts + self.Tm) + 4096 * self.n_env,
                  grid_items=16 * self.Tm + 4096, candidates=16 * self.Ts + 4096,
-                 active=self.Ns + 64, pairs=self.Ns // 2 + 1024, row_entries=256)
+                 active=(3 * self.Ns if self.mortar else self.Ns) + 64, pairs=self.Ns // 2 + 1024,
+                 row_entries=256)
         if caps:
             c.update(caps)
         self.caps = c
@@ -349,9 +359,11 @@ class Context:
     @classmethod
     def single(cls, slave_tri, master_tri, n_slave_verts: int, n_master_verts: int, rule_n: int = 2,
                kappa: float = 1e5, dhat: float = 1e-3, delta_T: float = 0.0, cell: float = 0.0,
-               dtype=torch.float32, kinematic: bool = False, caps=None, device="cuda", mortar: bool = False):
+               dtype=torch.float32, kinematic: bool = False, caps=None, device="cuda", mortar: bool = False,
+               features: bool = False, kappa_edge: float = 0.0, kappa_point: float = 0.0, delta_e: float = 0.0):
         Ts = int(len(slave_tri))
         Tm = int(len(master_tri))
         return cls(slave_tri, master_tri, [0, n_slave_verts], [0, Ts], [0, n_master_verts], [0, Tm],
                    [rule_n], [kappa], [dhat], [delta_T], [cell], dtype=dtype, kinematic=kinematic, caps=caps,
-                   device=device, mortar=mortar)
+                   device=device, mortar=mortar, features=features, kappa_edge=[kappa_edge],
+                   kappa_point=[kappa_point], delta_e=[delta_e])

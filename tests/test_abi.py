@@ -88,6 +88,12 @@ def test_workspace_size_and_strerror_host_only():
     lay_bad = N.Layout(1, *(cast(k, C.c_int32) for k in keep[:4]), cast(bad, C.c_int32),
                        *(cast(k, C.c_double) for k in keep[5:]), None, 0)
     assert L.gmcp_workspace_size(C.byref(lay_bad), C.byref(caps)) == 0
+    # edge / point samples need the clipped mortar samples
+    lay_feat = N.Layout(1, *(cast(k, C.c_int32) for k in keep[:5]), *(cast(k, C.c_double) for k in keep[5:]),
+                        None, N.GMCP_FEATURES)
+    assert L.gmcp_workspace_size(C.byref(lay_feat), C.byref(caps)) == 0
+    lay_feat.flags = N.GMCP_FEATURES | N.GMCP_MORTAR
+    assert L.gmcp_workspace_size(C.byref(lay_feat), C.byref(caps)) > 0
     assert N.strerror(N.GMCP_E_PENETRATION).startswith("penetration")
     ctx = C.c_void_p()
     assert L.gmcp_create(C.byref(ctx), C.byref(lay_bad), C.byref(caps), None, None, None, 0, None) == N.GMCP_E_ARG

@@ -133,3 +133,78 @@ def test_mortar_hvp_matches_bsr():
         for j in range(rp[r], rp[r + 1]):
             ref[r] += val[j] @ v[col[j]]
     assert rel_fro(ox.cpu().numpy(), ref) <= 1e-12
+
+
+def _feature_ctx(w, dtype, ke, kp, de):
+    from paper_2605_24339_amd import Context
+    return Context.single(w.ts, w.tm, w.xs.shape[0], w.xm.shape[0], rule_n=w.rule_n, kappa=w.kappa, dhat=w.dhat,
+                          delta_T=w.delta_T, dtype=dtype, features=True, kappa_edge=ke, kappa_point=kp, delta_e=de)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_small_indent_face_edge_point_samples_match_oracle(dtype):
+    """Clipped face samples plus the edge and point samples of the opposing
+    master features (Sec. 4.1), with per-type stiffness and the edge
+    transition width (Eq. (gamma))."""
+    need_gpu()
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    w = workloads.small_indent(fp32=fp32)
+    ke, kp, de = w.kappa * 1e-3, w.kappa * 1e-7, 0.1
+    ctx = _feature_ctx(w, tdt, ke, kp, de)
+    xs, xm = to_dev(w.xs, tdt), to_dev(w.xm, tdt)
+    ctx.build_samples(to_dev(w.xs_rest, tdt))
+    ctx.broadphase(xs, xm)
+    A = ctx.assemble(xs, xm)
+    P = workloads.to_problem(w)
+    S = om.samples(P, features=True)
+    O = om.assemble(P, S, kappa_edge=ke, kappa_point=kp, delta_e=de)
+    kinds = {s.kind for s in O.active}
+    assert kinds == {0, 1, 2}
+    assert abs(int(ctx.status().n_active) - len(O.active)) <= 2
+    te, tg = (1e-5, 1e-4) if fp32 else (1e-10, 1e-10)
+    assert abs(float(A.energy.double().sum()) / O.energy - 1) <= te
+    assert rel_fro(A.grad.double().cpu().numpy(), O.grad) <= tg
+    rp, col, val = _oracle_bsr(O.blocks, P.Vs + P.Vm)
+    H = A.hessian
+    assert bsr_rel_error(H.row_ptr.cpu().numpy(), H.col.cpu().numpy(), H.val.double().cpu().numpy().reshape(-1, 9),
+                         rp, col, val) <= tg
+    # the frozen energy reproduces the assembled one (feature weights included)
+    e0 = float(ctx.energy_frozen(xs, xm).double().sum())
+    assert abs(e0 / float(A.energy.double().sum()) - 1) <= te
+
+
+def test_single_master_triangle_features_exact():
+    """One opposing master triangle over a flat pad: the GPU's energy equals
+    the oracle's, whose edge weights sum to the edge lengths exactly."""
+    need_gpu()
+    from paper_2605_24339_amd import Context
+    xs, ts = __import__("gen.meshes", fromlist=["pad"]).pad(6, 1e-2)
+    xm = np.array([[-3.1e-3, -2.7e-3, 3e-4], [3.3e-3, -1.9e-3, 5e-4], [0.4e-3, 3.6e-3, 4e-4]])
+    tm = np.array([[0, 2, 1]])
+    ke, kp = 1e2, 1e-2
+    ctx = Context.single(ts, tm, xs.shape[0], 3, rule_n=2, kappa=1e5, dhat=1e-3, dtype=torch.float64,
+                         features=True, kappa_edge=ke, kappa_point=kp)
+    X, XM = to_dev(xs, torch.float64), to_dev(xm, torch.float64)
+    ctx.build_samples(X)
+    ctx.broadphase(X, XM)
+    A = ctx.assemble(X, XM)
+    P = oracle.Problem(xs, ts, xm, tm, 2, 1e5, 1e-3, 0.0, None, xs)
+    O = om.assemble(P, om.samples(P, features=True), kappa_edge=ke, kappa_point=kp)
+    assert abs(float(A.energy.sum()) / O.energy - 1) <= 1e-12
+    assert rel_fro(A.grad.cpu().numpy(), O.grad) <= 1e-12
+
+
+def test_mortar_capacity_growth_keeps_pairs_valid():
+    """Clipped samples overflowing a small active-sample capacity: the
+    kernel still writes every pair slot it allocated, the binding grows the
+    capacity and the result equals a run that fitted at once."""
+    need_gpu()
+    w = workloads.small_indent(fp32=False)
+    ref_ctx, xs, xm, ref = _run(w, torch.float64)
+    ctx = _ctx(w, torch.float64, caps={"active": 256})
+    ctx.build_samples(to_dev(w.xs_rest, torch.float64))
+    ctx.broadphase(xs, xm)
+    A = ctx.assemble(xs, xm)
+    assert ctx.caps["active"] > 256
+    assert torch.equal(A.energy, ref.energy) and torch.equal(A.grad, ref.grad)
