@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GMCP samples/s (E+grad+Hess) & CCD pairs/s, % HBM peak; Newton iters learned vs plain"
 HBM_PEAK_GBS = 8000.0
 # kernels that one profiled stage brackets exactly (candidates for the roofline)
-KERNEL_STAGES = {"query_count": "k_query<float, 0>", "query_fill": "k_query<float, 1>", "narrow": "k_narrow<float>",
+KERNEL_STAGES = {"query": "k_query<float>", "cand_move": "k_cand_move", "narrow": "k_narrow<float>",
                  "rows_count": "k_rows<float, 0, false>", "rows_fill": "k_rows<float, 1, false>",
                  "rows_count_heavy": "k_rows<float, 0, true>", "rows_fill_heavy": "k_rows<float, 1, true>",
                  "ccd_linear": "k_ccd_linear<float>", "ccd_accd": "k_ccd_accd<float>"}
@@ -55,9 +55,12 @@ def kernel_bytes(stage: str, sz: dict) -> int:
         # records 64 B per active sample, per-triangle normal+sums+counters
         # 64 B, pairs 80 B, tile energies 8 B
         return 12 * Vs + 16 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm + 64 * na + 64 * Ts + 80 * npair + 8 * ntile
-    if stage in ("query_count", "query_fill"):
-        out = 4 * Ts if stage == "query_count" else 4 * nc
-        return 12 * Vs + 12 * Ts + 48 * Tm + 4 * (Ts + 1) + out
+    if stage == "query":
+        # slave positions / triangles, master boxes; out: per-triangle counts
+        # and scratch offsets, sorted scratch lists
+        return 12 * Vs + 12 * Ts + 48 * Tm + 8 * Ts + 4 * nc
+    if stage == "cand_move":
+        return 12 * Ts + 8 * nc
     if stage in ("rows_count", "rows_fill"):
         # light rows: active slave triangles' sums and normals, their pairs,
         # slave adjacency; out: counts, or blocks + row gradients

@@ -294,10 +294,11 @@ int gmcp_profile_read(gmcp_ctx *ctx, double *ms, int64_t *count);
 /*
  * Synchronises and writes host out[4] for the last assembly with a Hessian:
  * BSR rows processed as light rows (at most 256 contributions, small LDS
- * tables), heavy rows, and the blocks written by each class.  For
+ * tables), heavy rows, and the blocks written by each class (counted on the
+ * host from row_ptr, the [V+1] device array of that assembly's BSR).  For
  * per-kernel byte accounting of the profiled stages.
  */
-int gmcp_row_classes(gmcp_ctx *ctx, int64_t *out);
+int gmcp_row_classes(gmcp_ctx *ctx, int64_t *out, const int32_t *row_ptr);
 
 /* Human-readable name of a status code. */
 const char *gmcp_strerror(int code);

@@ -107,7 +107,7 @@ def lib():
         L.gmcp_rule.restype = C.c_int
         L.gmcp_rule.argtypes = [C.c_int, C.POINTER(C.c_double)]
         L.gmcp_row_classes.restype = C.c_int
-        L.gmcp_row_classes.argtypes = [P, C.POINTER(C.c_int64)]
+        L.gmcp_row_classes.argtypes = [P, C.POINTER(C.c_int64), P]
         L.gmcp_profile.restype = C.c_int
         L.gmcp_profile.argtypes = [P, C.c_int]
         L.gmcp_profile_stages.restype = C.c_int

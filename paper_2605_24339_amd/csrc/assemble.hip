@@ -976,15 +976,31 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
         for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = R(0);
     }
   }
+  // list appends: wave ballots, block prefix in LDS, one atomic per block and list
+  __shared__ int wl[kThreads / kWave], wh[kThreads / kWave], bl, bh;
+  const int w = threadIdx.x / kWave;
   const uint64_t ml = __ballot(n_ent > 0 && n_ent <= kLightEnt), mh = __ballot(n_ent > kLightEnt);
-  int bl = 0, bh = 0;
-  if (lane == 0 && ml) bl = atomicAdd(&rcount[0], __popcll(ml));
-  if (lane == 0 && mh) bh = atomicAdd(&rcount[1], __popcll(mh));
-  bl = __shfl(bl, 0, kWave);
-  bh = __shfl(bh, 0, kWave);
+  if (lane == 0) {
+    wl[w] = __popcll(ml);
+    wh[w] = __popcll(mh);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sl = 0, sh = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) {
+      const int a0 = wl[k], b0 = wh[k];
+      wl[k] = sl;
+      wh[k] = sh;
+      sl += a0;
+      sh += b0;
+    }
+    bl = sl ? atomicAdd(&rcount[0], sl) : 0;
+    bh = sh ? atomicAdd(&rcount[1], sh) : 0;
+  }
+  __syncthreads();
   const uint64_t below = (1ull << lane) - 1;
-  if (n_ent > 0 && n_ent <= kLightEnt) rlist[bl + __popcll(ml & below)] = (int32_t)row;
-  if (n_ent > kLightEnt) rlist[a.V + bh + __popcll(mh & below)] = (int32_t)row;
+  if (n_ent > 0 && n_ent <= kLightEnt) rlist[bl + wl[w] + __popcll(ml & below)] = (int32_t)row;
+  if (n_ent > kLightEnt) rlist[a.V + bh + wh[w] + __popcll(mh & below)] = (int32_t)row;
 }
 
 // One wave per listed BSR row (k_row_pre), a fixed grid walking the list.
@@ -1008,7 +1024,7 @@ constexpr int kRowEnt = 512;
 
 template <typename R, int PASS, bool HEAVY>  // HEAVY: the heavy-row list (large LDS tables), same code
 __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots, const int32_t *__restrict__ rlist,
-                                                           int32_t *__restrict__ rcount) {
+                                                           const int32_t *__restrict__ rcount) {
   constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -1110,10 +1126,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       nuniq += __popcll(m);
     }
     if (pass == 0) {
-      if (lane == 0) {
-        a.row_cnt[row] = nuniq;
-        atomicAdd(&rcount[2 + (HEAVY ? 1 : 0)], nuniq);  // blocks per row class
-      }
+      if (lane == 0) a.row_cnt[row] = nuniq;
       return;
     }
     wave_sync();
@@ -1234,10 +1247,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     nuniq += __popcll(m);
   }
   if (pass == 0) {
-    if (lane == 0) {
-      a.row_cnt[row] = nuniq;
-      atomicAdd(&rcount[2 + (HEAVY ? 1 : 0)], nuniq);  // blocks per row class
-    }
+    if (lane == 0) a.row_cnt[row] = nuniq;
     return;
   }
   wave_sync();
@@ -1307,18 +1317,23 @@ __global__ __launch_bounds__(kThreads) void k_grad(RowArgs<R> a, const R *__rest
 }
 
 template <typename R>
-__global__ void k_energy(const double *__restrict__ tile_E, const EnvInfo *__restrict__ env, R *energy) {
-  __shared__ double part[256];
-  int e = blockIdx.x;
+// per-environment sum of the tile energies: a fixed split over 1024
+// threads, wave butterflies, then the 16 wave sums in order (deterministic)
+__global__ __launch_bounds__(1024) void k_energy(const double *__restrict__ tile_E, const EnvInfo *__restrict__ env,
+                                                 R *energy) {
+  __shared__ double part[1024 / kWave];
+  const int e = blockIdx.x, lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int t0 = env[e].tile0, t1 = env[e].tile1;
   double s = 0.0;
-  for (int t = env[e].tile0 + threadIdx.x; t < env[e].tile1; t += blockDim.x) s += tile_E[t];
-  part[threadIdx.x] = s;
+  for (int t = t0 + threadIdx.x; t < t1; t += 1024) s += tile_E[t];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane == 0) part[w] = s;
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < 1024 / kWave; ++k) tot += part[k];
+    energy[e] = (R)tot;
   }
-  if (threadIdx.x == 0) energy[e] = (R)part[0];
 }
 
 __global__ void k_finish_counts(const int32_t *row_ptr, int64_t V, DevStatus *st, int64_t cap_nnzb) {
@@ -1530,7 +1545,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
       hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, kTilePerBlock)), dim3(kThreads), 0, s, na);
   }
   prof_mark(c, ST_NARROW, 1);
-  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(256), 0, s, b.tile_E, b.env, energy);
+  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, s, b.tile_E, b.env, energy);
   // bucket pairs by master triangle (needed for master rows and the HVP)
   const Pair<R> *pr = (const Pair<R> *)b.pair;
   unsigned pb = nblk(c->caps.pairs);
@@ -1554,7 +1569,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     prof_mark(c, ST_MTRI, 1);
   }
   if (grad || H) {
-    e = fill_i32(c, b.rcount, 0, 4);
+    e = fill_i32(c, b.rcount, 0, 2);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_PRE, 0);
     if (c->V)
@@ -1567,7 +1582,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const dim3 rgrid((unsigned)(rneed < kRowBlocks ? (rneed > 0 ? rneed : 1) : kRowBlocks));
   const dim3 hgrid(256);
   const int32_t *light = b.rlist, *heavy = b.rlist + c->V;
-  int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
+  const int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
     prof_mark(c, ST_GRAD, 0);
     hipLaunchKernelGGL((k_rows<R, 2, false>), rgrid, dim3(kWave * nw), 0, s, ra, 64, light, nlight);
@@ -1718,7 +1733,7 @@ hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy
                        c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order, b.env, b.rule, (const R *)b.area,
                        (const Rec<R> *)b.rec, b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, b.status, c->caps.active,
                        b.tile_E);
-  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(256), 0, c->stream, b.tile_E, b.env, energy);
+  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, c->stream, b.tile_E, b.env, energy);
   return hipGetLastError();
 }
 

@@ -382,11 +382,23 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
     }
     if (!active) cand_cnt[t] = 0;
   }
+  // list appends: wave ballots, block prefix in LDS, one atomic per block
+  __shared__ int wq[kThreads / kWave], qb;
+  const int w = threadIdx.x / kWave;
   const uint64_t m = __ballot(active);
-  int qb = 0;
-  if (lane == 0 && m) qb = atomicAdd(qcount, __popcll(m));
-  qb = __shfl(qb, 0, kWave);
-  if (active) qlist[qb + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
+  if (lane == 0) wq[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) {
+      const int c0 = wq[k];
+      wq[k] = sum;
+      sum += c0;
+    }
+    qb = sum ? atomicAdd(qcount, sum) : 0;
+  }
+  __syncthreads();
+  if (active) qlist[qb + wq[w] + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
 }
 
 // One wave per slave triangle.  The support prism (|t| <= eps_max along n_T)
@@ -394,8 +406,12 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
 // cells of all slab boxes, test each master triangle in them (box overlap
 // with the slab box, facing test with slack) and insert it into an LDS hash
 // set, which removes the duplicates of overlapping cells and slabs.
-// pass 0 counts the set; pass 1 writes it sorted ascending.
-template <typename R, int PASS>
+// One pass: the set is compacted, sorted in LDS and written to a scratch
+// list at an offset allocated from the block's share of the scratch (the
+// content of a triangle's list does not depend on the order); k_cand_move
+// then places every list at its CSR offset, so the candidate CSR is the
+// same on every run.
+template <typename R>
 __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, const int32_t *__restrict__ ts,
                                                      const int32_t *__restrict__ s_order,
                                                      const int32_t *__restrict__ s_env,
@@ -404,37 +420,31 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      const int32_t *__restrict__ cell_start,
                                                      const int32_t *__restrict__ items,
                                                      const float4 *__restrict__ mbox, int32_t *__restrict__ cand_cnt,
-                                                     const int32_t *__restrict__ cand_off, int32_t *__restrict__ cand,
-                                                     int64_t cap_cand, int64_t cap_items, int64_t total_cells,
+                                                     int32_t *__restrict__ tmp_off, int32_t *__restrict__ cand_tmp,
+                                                     int64_t cap_cand,
+                                                     int64_t cap_items, int64_t total_cells,
                                                      const int32_t *__restrict__ qlist,
                                                      const int32_t *__restrict__ qcount, DevStatus *st) {
-  constexpr int pass = PASS;
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
+  __shared__ int blk_req;  // candidates requested by this block's triangles (LDS atomics)
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t nlist = *qcount;
   if (cell_start[total_cells] > cap_items) {  // grid incomplete
-    if (pass == 0)
-      for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
-        if (lane == 0) cand_cnt[qlist[li]] = 0;
+    for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
+      if (lane == 0) cand_cnt[qlist[li]] = 0;
     return;
   }
-  if (pass == 1 && cand_off[Ts] > cap_cand) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      atomicMax(&st->need_cand, (unsigned long long)cand_off[Ts]);
-      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
-    }
-    return;
-  }
+  // the scratch is split evenly over the blocks; a block allocates its
+  // triangles' lists from its own share with LDS atomics (no global
+  // contention); a list that does not fit is dropped and the need reported
+  const int64_t share = cap_cand / gridDim.x;
+  if (threadIdx.x == 0) blk_req = 0;
+  __syncthreads();
   // the waves walk the query list (triangles whose prism meets occupied cells)
   for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
     [&](const int64_t t) {
   wave_sync();  // the previous triangle's LDS reads are done
-  int64_t out = 0;
-  if (pass == 1) {
-    out = cand_off[t];
-    if (cand_off[t + 1] == out) return;
-  }
   const int e = s_env[t];
   const GridEnv g = grid[e];
   const float eps = (float)env[e].dhat;
@@ -486,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   for_cells([&](int, int64_t cell) { nitems += cell_start[cell + 1] - cell_start[cell]; });
   for (int o = 32; o > 0; o >>= 1) nitems += __shfl_xor(nitems, o, kWave);
   if (nitems == 0) {
-    if (pass == 0 && lane == 0) cand_cnt[t] = 0;
+    if (lane == 0) cand_cnt[t] = 0;
     return;
   }
   int tsz = 64;
@@ -524,14 +534,8 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
     if (lane == 0) {
       atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
       atomicMin(&st->index, (unsigned long long)t);
-      if (pass == 0) cand_cnt[t] = 0;
+      cand_cnt[t] = 0;
     }
-    return;
-  }
-  int total = fresh;
-  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, kWave);
-  if (pass == 0) {
-    if (lane == 0) cand_cnt[t] = total;
     return;
   }
   wave_sync();
@@ -543,8 +547,18 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
     if (used) dense[w][nu + __popcll(m & ((1ull << lane) - 1))] = set[w][k];
     nu += __popcll(m);
   }
+  int off = 0;
+  if (lane == 0) {
+    off = nu ? atomicAdd(&blk_req, nu) : 0;
+    const bool fits = (int64_t)off + nu <= share;
+    cand_cnt[t] = fits ? nu : 0;
+    tmp_off[t] = (int32_t)(blockIdx.x * share + off);
+    if (!fits) off = -1;
+  }
+  off = __shfl(off, 0, kWave);
   wave_sync();
-  int32_t *l = cand + out;
+  if (off < 0) return;  // dropped (capacity reported below)
+  int32_t *l = cand_tmp + blockIdx.x * share + off;
   for (int k = lane; k < nu; k += kWave) {  // rank sort: ids are unique
     int v = dense[w][k], r = 0;
     for (int m = 0; m < nu; ++m) r += dense[w][m] < v;
@@ -552,8 +566,30 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   }
   wave_sync();  // the set is reused by the wave's next triangle
     }(qlist[li]);
+  __syncthreads();
+  if (threadIdx.x == 0 && (int64_t)blk_req > share) {
+    atomicMax(&st->need_cand, (unsigned long long)blk_req * gridDim.x);
+    atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+  }
 }
 
+// Each listed triangle's sorted list, from its scratch offset to its CSR
+// offset (one wave per list entry of the query list).
+__global__ __launch_bounds__(kThreads) void k_cand_move(const int32_t *__restrict__ qlist,
+                                                         const int32_t *__restrict__ qcount,
+                                                         const int32_t *__restrict__ cand_cnt,
+                                                         const int32_t *__restrict__ tmp_off,
+                                                         const int32_t *__restrict__ cand_off,
+                                                         const int32_t *__restrict__ cand_tmp,
+                                                         int32_t *__restrict__ cand) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t nlist = *qcount;
+  for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves) {
+    const int t = qlist[li];
+    const int n = cand_cnt[t], src = tmp_off[t], dst = cand_off[t];
+    for (int k = lane; k < n; k += kWave) cand[dst + k] = cand_tmp[src + k];
+  }
+}
 
 __global__ void k_cand_total(const int32_t *cand_off, int64_t Ts, DevStatus *st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
@@ -613,11 +649,11 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   prof_mark(c, ST_QUERY_PRE, 1);
   // the wave kernels walk the query list with a fixed grid
   const int64_t qb = (c->Ts + kQueryWaves - 1) / kQueryWaves;
-  const dim3 qgrid((unsigned)(qb < kQueryBlocks ? qb : kQueryBlocks));
+  const dim3 qgrid((unsigned)(qb < kQueryBlocks ? (qb > 0 ? qb : 1) : kQueryBlocks));
   prof_mark(c, ST_QUERY_COUNT, 0);
   if (c->Ts)
-    hipLaunchKernelGGL((k_query<R, 0>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
-                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
+    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
                        c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
   prof_mark(c, ST_QUERY_COUNT, 1);
   e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
@@ -626,9 +662,8 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (e != hipSuccess) return e;
   prof_mark(c, ST_QUERY_FILL, 0);
   if (c->Ts)
-    hipLaunchKernelGGL((k_query<R, 1>), qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
-                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_off, b.cand, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
+    hipLaunchKernelGGL(k_cand_move, qgrid, dim3(kThreads), 0, s, b.qlist, b.qcount, b.cand_cnt, b.cand_tmp_off,
+                       b.cand_off, b.cand_tmp, b.cand);
   prof_mark(c, ST_QUERY_FILL, 1);
   hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
   return hipGetLastError();

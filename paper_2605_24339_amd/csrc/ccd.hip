@@ -213,9 +213,15 @@ __device__ inline int cell_coord(const GridEnv &g, float x, int d) {
   return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-// one wave per work tile, lane = (slave triangle, rule point) as in the
-// narrow phase: Morton-ordered triangles, no idle lanes for small rules,
-// one environment per wave
+// One wave per work tile, lane = (slave triangle j, rule point q) as in the
+// narrow phase.  The lanes of a triangle first gather, from the grid cells
+// its swept box covers, the master triangles whose swept boxes overlap it
+// (each once: the cell holding the lower corner of the overlap), into an
+// LDS slice; then every lane tests its own point's swept box against that
+// list and runs additive CCD on the overlaps.  A triangle whose list
+// overflows its slice walks the cells point by point instead.
+constexpr int kAccdPool = 1024;  // LDS list entries per wave, split over the tile's triangles
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     const R *__restrict__ xs, const R *__restrict__ xm, const R *__restrict__ dxs, const R *__restrict__ dxm,
@@ -223,22 +229,82 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     const int32_t *__restrict__ s_order, const EnvInfo *__restrict__ env, const double *__restrict__ rule,
     const GridEnv *__restrict__ grid, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items,
     const float4 *__restrict__ smbox, int64_t cap_items, int64_t total_cells, uint32_t *bits, DevStatus *st) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int tile_id = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  __shared__ int32_t plist[kThreads / kWave][kAccdPool];
+  __shared__ int32_t pcnt[kThreads / kWave][kWave];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int tile_id = blockIdx.x * (kThreads / kWave) + w;
   float amin = INFINITY;
   int e = -1;
   unsigned long long npairs = 0;
+  auto slack_box = [](float a, float b, float &lo, float &hi) {
+    const float mn = fminf(a, b), mx = fmaxf(a, b);
+    lo = mn - fabsf(mn) * 4e-7f - 1e-30f;
+    hi = mx + fabsf(mx) * 4e-7f + 1e-30f;
+  };
   if (tile_id < n_tiles && cell_start[total_cells] <= cap_items) {
     const Tile tl = tiles[tile_id];
     e = tl.env;
     const int j = lane / tl.nq, q = lane - j * tl.nq;
-    const int64_t T = j < tl.count ? s_order[tl.first + j] : 0;
+    const bool live = j < tl.count;
+    const int64_t T = live ? s_order[tl.first + j] : 0;
     const EnvInfo &ev = env[e];
-    GridEnv g = grid[e];
-    if (j < tl.count && g.valid) {
+    const GridEnv g = grid[e];
+    const int slice = kAccdPool / (tl.count > 0 ? tl.count : 1);
+    const int64_t base = ev.cell0;
+    const float ext[3] = {g.nx * g.h, g.ny * g.h, g.nz * g.h};
+    auto inside_grid = [&](const float lo[3], const float hi[3]) {
+      for (int d = 0; d < 3; ++d)
+        if (hi[d] < g.lo[d] || lo[d] > g.lo[d] + ext[d]) return false;
+      return true;
+    };
+    int64_t v[3] = {0, 0, 0};
+    float tlo[3], thi[3];
+    if (live) {
+      for (int k = 0; k < 3; ++k) v[k] = ts[3 * T + k];
+      for (int d = 0; d < 3; ++d) {  // the triangle's swept box covers every point's
+        float lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < 3; ++k) {
+          float l, h;
+          slack_box((float)xs[3 * v[k] + d], (float)(xs[3 * v[k] + d] + dxs[3 * v[k] + d]), l, h);
+          lo = fminf(lo, l);
+          hi = fmaxf(hi, h);
+        }
+        tlo[d] = lo;
+        thi[d] = hi;
+      }
+    }
+    // ---- gather the triangle's swept candidates into its LDS slice
+    if (live && q == 0) pcnt[w][j] = 0;
+    wave_sync();
+    if (live && g.valid && inside_grid(tlo, thi)) {
+      int c0[3], c1[3];
+      for (int d = 0; d < 3; ++d) {
+        c0[d] = cell_coord(g, tlo[d], d);
+        c1[d] = cell_coord(g, thi[d], d);
+      }
+      for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+          for (int x = c0[0]; x <= c1[0]; ++x) {
+            const int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+            const int i1 = cell_start[cell + 1];
+            for (int i = cell_start[cell] + q; i < i1; i += tl.nq) {
+              const int M = items[i];
+              const float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
+              if (ma.x > thi[0] || mb.x < tlo[0] || ma.y > thi[1] || mb.y < tlo[1] || ma.z > thi[2] ||
+                  mb.z < tlo[2])
+                continue;
+              if (cell_coord(g, fmaxf(ma.x, tlo[0]), 0) != x || cell_coord(g, fmaxf(ma.y, tlo[1]), 1) != y ||
+                  cell_coord(g, fmaxf(ma.z, tlo[2]), 2) != z)
+                continue;
+              const int slot = atomicAdd(&pcnt[w][j], 1);
+              if (slot < slice) plist[w][j * slice + slot] = M;
+            }
+          }
+    }
+    wave_sync();
+    if (live && g.valid) {
       const double *rq = rule + ((ev.rule_n - 1) * 16 + q) * 3;
-      R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
-      int64_t v[3] = {ts[3 * T], ts[3 * T + 1], ts[3 * T + 2]};
+      const R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
       R s0[3], dp[3], off[3];
       for (int d = 0; d < 3; ++d) {
         s0[d] = xs[3 * v[0] + d];
@@ -247,50 +313,45 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
       }
       float lo[3], hi[3];
       for (int d = 0; d < 3; ++d) {
-        R p0 = s0[d] + off[d];
-        float a = (float)p0, b = (float)(p0 + dp[d]);
-        float mn = fminf(a, b), mx = fmaxf(a, b);
-        lo[d] = mn - fabsf(mn) * 4e-7f - 1e-30f;
-        hi[d] = mx + fabsf(mx) * 4e-7f + 1e-30f;
+        const R p0 = s0[d] + off[d];
+        slack_box((float)p0, (float)(p0 + dp[d]), lo[d], hi[d]);
       }
-      int c0[3], c1[3];
-      for (int d = 0; d < 3; ++d) {
-        c0[d] = cell_coord(g, lo[d], d);
-        c1[d] = cell_coord(g, hi[d], d);
-      }
-      float ext[3] = {g.nx * g.h, g.ny * g.h, g.nz * g.h};
-      bool inside = true;
-      for (int d = 0; d < 3; ++d)
-        if (hi[d] < g.lo[d] || lo[d] > g.lo[d] + ext[d]) inside = false;
-      if (inside) {
-        int64_t base = ev.cell0;
+      auto pair = [&](int M) {  // the point against master triangle M
+        const float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
+        if (ma.x > hi[0] || mb.x < lo[0] || ma.y > hi[1] || mb.y < lo[1] || ma.z > hi[2] || mb.z < lo[2]) return;
+        ++npairs;
+        R A[3], B[3], C[3], dA[3], dB[3], dC[3];
+        const int64_t w0 = tm[3 * (int64_t)M], w1 = tm[3 * (int64_t)M + 1], w2 = tm[3 * (int64_t)M + 2];
+        for (int d = 0; d < 3; ++d) {
+          A[d] = (xm[3 * w0 + d] - s0[d]) - off[d];
+          B[d] = (xm[3 * w1 + d] - s0[d]) - off[d];
+          C[d] = (xm[3 * w2 + d] - s0[d]) - off[d];
+          dA[d] = dxm ? dxm[3 * w0 + d] : R(0);
+          dB[d] = dxm ? dxm[3 * w1 + d] : R(0);
+          dC[d] = dxm ? dxm[3 * w2 + d] : R(0);
+        }
+        amin = fminf(amin, to_float_down<R>(accd<R>(dp, A, dA, B, dB, C, dC, R(0.1))));
+      };
+      const int n = pcnt[w][j];
+      if (n <= slice) {
+        for (int i = 0; i < n; ++i) pair(plist[w][j * slice + i]);
+      } else if (inside_grid(lo, hi)) {  // overflow: walk the point's own cells
+        int c0[3], c1[3];
+        for (int d = 0; d < 3; ++d) {
+          c0[d] = cell_coord(g, lo[d], d);
+          c1[d] = cell_coord(g, hi[d], d);
+        }
         for (int z = c0[2]; z <= c1[2]; ++z)
           for (int y = c0[1]; y <= c1[1]; ++y)
             for (int x = c0[0]; x <= c1[0]; ++x) {
-              int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
-              for (int jj = cell_start[cell]; jj < cell_start[cell + 1]; ++jj) {
-                int M = items[jj];
-                float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
-                if (ma.x > hi[0] || mb.x < lo[0] || ma.y > hi[1] || mb.y < lo[1] || ma.z > hi[2] || mb.z < lo[2])
-                  continue;
+              const int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+              for (int i = cell_start[cell]; i < cell_start[cell + 1]; ++i) {
+                const int M = items[i];
+                const float4 ma = smbox[3 * (int64_t)M];
                 if (cell_coord(g, fmaxf(ma.x, lo[0]), 0) != x || cell_coord(g, fmaxf(ma.y, lo[1]), 1) != y ||
                     cell_coord(g, fmaxf(ma.z, lo[2]), 2) != z)
                   continue;
-                ++npairs;
-                R A[3], B[3], C[3], dA[3], dB[3], dC[3];
-                int64_t w0 = tm[3 * (int64_t)M], w1 = tm[3 * (int64_t)M + 1], w2 = tm[3 * (int64_t)M + 2];
-                for (int d = 0; d < 3; ++d) {
-                  R pd = s0[d] + off[d];
-                  A[d] = (xm[3 * w0 + d] - s0[d]) - off[d];
-                  B[d] = (xm[3 * w1 + d] - s0[d]) - off[d];
-                  C[d] = (xm[3 * w2 + d] - s0[d]) - off[d];
-                  (void)pd;
-                  dA[d] = dxm ? dxm[3 * w0 + d] : R(0);
-                  dB[d] = dxm ? dxm[3 * w1 + d] : R(0);
-                  dC[d] = dxm ? dxm[3 * w2 + d] : R(0);
-                }
-                R t = accd<R>(dp, A, dA, B, dB, C, dC, R(0.1));
-                amin = fminf(amin, to_float_down<R>(t));
+                pair(M);
               }
             }
       }

@@ -87,6 +87,7 @@ struct Buffers {
   int32_t *cell_cnt, *cell_start, *items;
   float4 *mbox;                                 // [Tm][3]: lo, hi, unit normal
   int32_t *cand_cnt, *cand_off, *cand;
+  int32_t *cand_tmp, *cand_tmp_off;             // one-pass query: scratch lists and their offsets
   int32_t *qlist, *qcount;                      // [Ts], [1]: slave triangles whose prism meets occupied cells
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
@@ -100,8 +101,7 @@ struct Buffers {
   void *mtri;                                   // [Tm][45] R: per master triangle, sum over its
                                                 // pairs of mm n n^T (6 vertex pairs x 6) and gm n (3 x 3)
   int32_t *row_cnt;                             // [V+1]
-  int32_t *rlist, *rcount;                      // [2V]: BSR rows with contributions (light | heavy);
-                                                // [4]: light rows, heavy rows, light blocks, heavy blocks
+  int32_t *rlist, *rcount;                      // [2V]: BSR rows with contributions (light | heavy); [2] counts
   // step bound
   GridEnv *sgrid;
   uint32_t *sbox;
@@ -120,8 +120,8 @@ struct Buffers {
 // (stages marked "kernel" bracket exactly one kernel launch)
 enum Stage {
   ST_GRID = 0,     // grid build (boxes, counts, scan, placement)
-  ST_QUERY_COUNT,  // kernel k_query, counting pass
-  ST_QUERY_FILL,   // kernel k_query, writing pass
+  ST_QUERY_COUNT,  // kernel k_query (one pass: sets, sorted scratch lists)
+  ST_QUERY_FILL,   // kernel k_cand_move (scratch lists to the CSR)
   ST_NARROW,       // kernel k_narrow: narrow phase + barrier + sums
   ST_BUCKET,       // pairs bucketed by master triangle (count, scan, place, sort)
   ST_GRAD,         // kernel k_grad: gradient rows

@@ -197,6 +197,8 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.cand_cnt = p.take<int32_t>(s.Ts + 1);
   t.cand_off = p.take<int32_t>(s.Ts + 1);
   t.cand = p.take<int32_t>(cp.candidates);
+  t.cand_tmp = p.take<int32_t>(cp.candidates);
+  t.cand_tmp_off = p.take<int32_t>(s.Ts);
   t.qlist = p.take<int32_t>(s.Ts);
   t.qcount = p.take<int32_t>(1);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
@@ -215,7 +217,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.mtri = p.take<char>(s.kin ? 0 : rsz * 45 * s.Tm);
   t.row_cnt = p.take<int32_t>(s.V + 1);
   t.rlist = p.take<int32_t>(2 * s.V);
-  t.rcount = p.take<int32_t>(4);
+  t.rcount = p.take<int32_t>(2);
   t.sgrid = p.take<GridEnv>(s.n_env);
   t.sbox = p.take<uint32_t>(6 * s.n_env);
   t.scell_cnt = p.take<int32_t>(cp.grid_cells + 1);
@@ -649,7 +651,7 @@ int gmcp_status(gmcp_ctx *c, gmcp_status_info *info) {
 }
 
 static const char *kStageNames[gmcp::ST_COUNT] = {
-    "grid_build", "query_count", "query_fill", "narrow",     "pair_bucket", "grad_rows",
+    "grid_build", "query", "cand_move", "narrow",     "pair_bucket", "grad_rows",
     "rows_count", "rows_fill",   "ccd_linear", "ccd_grid",   "ccd_accd",  "master_tri_sums", "rows_copy", "query_pre", "rows_pre", "rows_count_heavy", "rows_fill_heavy"};
 
 int gmcp_profile(gmcp_ctx *c, int enable) {
@@ -684,13 +686,28 @@ int gmcp_profile_read(gmcp_ctx *c, double *ms, int64_t *count) {
   return GMCP_OK;
 }
 
-int gmcp_row_classes(gmcp_ctx *c, int64_t *out) {
-  if (!c || !out || !c->assembled) return GMCP_E_ARG;
-  int32_t h[4];
+int gmcp_row_classes(gmcp_ctx *c, int64_t *out, const int32_t *row_ptr) {
+  if (!c || !out || !row_ptr || !c->assembled) return GMCP_E_ARG;
+  int32_t h[2];
   if (hipMemcpyAsync(h, c->b.rcount, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return GMCP_E_HIP;
-  for (int i = 0; i < 4; ++i) out[i] = h[i];
+  std::vector<int32_t> rl((size_t)h[0] + h[1]), rp(c->V + 1);
+  if ((h[0] && hipMemcpy(rl.data(), c->b.rlist, sizeof(int32_t) * h[0], hipMemcpyDeviceToHost) != hipSuccess) ||
+      (h[1] && hipMemcpy(rl.data() + h[0], c->b.rlist + c->V, sizeof(int32_t) * h[1], hipMemcpyDeviceToHost) !=
+                   hipSuccess) ||
+      hipMemcpy(rp.data(), row_ptr, sizeof(int32_t) * (c->V + 1), hipMemcpyDeviceToHost) != hipSuccess)
+    return GMCP_E_HIP;
+  int64_t nb[2] = {0, 0};
+  for (int64_t i = 0; i < (int64_t)rl.size(); ++i) {
+    const int32_t r = rl[i];
+    if (r < 0 || r >= c->V) return GMCP_E_HIP;
+    nb[i < h[0] ? 0 : 1] += rp[r + 1] - rp[r];
+  }
+  out[0] = h[0];
+  out[1] = h[1];
+  out[2] = nb[0];
+  out[3] = nb[1];
   return GMCP_OK;
 }
 

@@ -57,6 +57,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *__restrict__
     if (j < n) out[j] += add;
 }
 
+// Exclusive scan of up to kScanOne elements in one block of 1024 threads:
+// each thread scans a contiguous run, the run totals are scanned across
+// the block (wave scans + LDS), then the runs are written (one launch).
+constexpr int kOneThreads = 1024;
+constexpr int64_t kScanOne = 1 << 17;
+
+__global__ __launch_bounds__(kOneThreads) void k_scan_one(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                           int64_t n) {
+  __shared__ int wsum[kOneThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int64_t per = (n + kOneThreads - 1) / kOneThreads;
+  const int64_t b = (int64_t)tid * per, e = b + per < n ? b + per : n;
+  int run = 0;
+  for (int64_t j = b; j < e; ++j) run += in[j];
+  const int incl = wave_incl_scan(run, lane);
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int i = 0; i < w; ++i) woff += wsum[i];
+  int ex = woff + incl - run;
+  for (int64_t j = b; j < e; ++j) {
+    const int v = in[j];
+    out[j] = ex;
+    ex += v;
+  }
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -82,6 +109,10 @@ hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t 
   // levels: out <- scan(in); block sums in tmp, scanned recursively in place
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb <= 0) return hipSuccess;
+  if (n <= kScanOne && nb > 1) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kOneThreads), 0, c->stream, in, out, n);
+    return hipGetLastError();
+  }
   if (nb == 1) {
     hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kScanThreads), 0, c->stream, in, out, nullptr, n);
     return hipGetLastError();

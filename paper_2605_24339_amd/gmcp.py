@@ -312,7 +312,7 @@ class Context:
         """Light / heavy BSR rows and their blocks in the last assembly (synchronises)."""
         out = (C.c_int64 * 4)()
         self._bind()
-        _check(N.lib().gmcp_row_classes(self._ctx, out), "gmcp_row_classes")
+        _check(N.lib().gmcp_row_classes(self._ctx, out, _ptr(self.row_ptr)), "gmcp_row_classes")
         return dict(rows_light=out[0], rows_heavy=out[1], nnzb_light=out[2], nnzb_heavy=out[3])
 
     def energy_frozen(self, xs, xm) -> torch.Tensor:

@@ -8,11 +8,13 @@ Scene of trajectory j (seed 5000 + j): 64 x 64 x 8 cubes of 0.3125 mm
 (20 x 20 x 2.5 mm, 196608 tets, 38025 vertices), E = 0.3 MPa, nu = 0.45,
 density 1000 kg/m^3, dt = 1 ms, bottom face prescribed; a rigid sphere
 (icosphere subdivision 3) of radius U[2, 6] mm above the top face (lateral
-offset within 3 mm, initial gap U[0.2, 1] mm).  The relative indentation
-is driven through the prescribed bottom face, which moves toward the
-sphere at U[5, 20] mm/s with a lateral drift of at most 20 mm/s.  The
-tactile surface (slave) is the top face, 2 x 2 samples per triangle,
-dhat = 1 mm, kappa = 1e5.
+offset within 3 mm, initial gap U[0.05, 0.2] mm).  The relative
+indentation is driven through the prescribed bottom face, which moves
+toward the sphere at U[2, 6] mm/s with a lateral drift of at most 4 mm/s
+(at most 0.6 mm of travel in 100 steps on a 2.5 mm block).  The tactile
+surface (slave) is the top face, 2 x 2 samples per triangle, dhat = 1 mm,
+kappa = 2.5e6 (a contact pressure of about 3e4 Pa, 10 % strain of the gel,
+is reached at a gap of dhat / 10).
 
 The network's inputs are standardised and its outputs scaled by the
 targets' RMS (fitted on the training rows).  With the safeguard (default)
@@ -39,6 +41,7 @@ from .mlp import MLP, features, targets
 from .newton import ImplicitSolver
 
 E_Y, NU, RHO, DT = 3e5, 0.45, 1000.0, 1e-3
+KAPPA = 2.5e6
 
 
 class Scene:
@@ -51,13 +54,13 @@ class Scene:
         xm, tm = meshes.icosphere(3, R)
         c = np.array([n * h / 2 + rng.uniform(-3e-3, 3e-3) * n / 64,
                       n * h / 2 + rng.uniform(-3e-3, 3e-3) * n / 64,
-                      nz * h + R + rng.uniform(2e-4, 1e-3)])
+                      nz * h + R + rng.uniform(5e-5, 2e-4)])
         self.xm = xm + c
         self.tm = tm
         v = np.zeros(3)
-        v[2] = rng.uniform(5e-3, 2e-2)
+        v[2] = rng.uniform(2e-3, 6e-3)
         lat = rng.normal(size=2)
-        v[:2] = lat / np.linalg.norm(lat) * rng.uniform(0, 2e-2)
+        v[:2] = lat / np.linalg.norm(lat) * rng.uniform(0, 4e-3)
         self.plate_v = v
         self.center = X.mean(0)
         self.L = float(np.ptp(X, axis=0).max())
@@ -66,7 +69,7 @@ class Scene:
     def make_solver(self, tol=1e-6):
         dev = self.device
         fem = Fem(self.X, self.tets, E_Y, NU, RHO, DT, self.bottom, device=dev)
-        ctx = Context.single(self.top, self.tm, self.X.shape[0], self.xm.shape[0], rule_n=2, kappa=1e5, dhat=1e-3,
+        ctx = Context.single(self.top, self.tm, self.X.shape[0], self.xm.shape[0], rule_n=2, kappa=KAPPA, dhat=1e-3,
                              dtype=torch.float64, kinematic=True, device=dev)
         ctx.build_samples(torch.tensor(self.X, device=dev))
         return ImplicitSolver(fem, ctx, E_Y * self.h * self.h, tol=tol)
