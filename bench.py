@@ -254,6 +254,29 @@ def measure_dualmesh(dev, reps: int = 50) -> dict:
             "update_frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def measure_patch(dev) -> dict:
+    """Contact patch test (two deformable blocks, non-matching interface):
+    Table 1's errors for both face-sample kinds and kappa = 1e4, 1e6, 1e8,
+    with the wall time of each quasi-static GPU solve."""
+    from paper_2605_24339_amd import patchtest
+    patchtest.run(n_top=4, n_bot=6, kappas=(1e6,), device=dev)      # warm-up (library loads, allocator)
+    return patchtest.run(n_top=4, n_bot=6, device=dev)
+
+
+def cpu_patch(kappa: float = 1e6) -> dict:
+    """The oracle's quasi-static patch-test solves on the same scene."""
+    from gen import workloads
+    from oracle import fem as ofem
+    pt = workloads.patch_test(n_top=4, n_bot=6)
+    out = {}
+    for mortar in (False, True):
+        t0 = time.perf_counter()
+        ofem.patch_test(pt, kappa, mortar=mortar)
+        out["clipped mortar" if mortar else "whole triangle"] = time.perf_counter() - t0
+    return {"kappa": kappa, "seconds": out, "what": "FP64 oracle: Newton with direct sparse solves, 4x4x2 on "
+                                                    "6x6x3 cube blocks (one quasi-static solve per sample kind)"}
+
+
 def cpu_baseline(w, budget_s: float) -> dict:
     import oracle
     from gen import workloads
@@ -411,8 +434,11 @@ def main():
         out["mortar"] = {"workload": w.name + " with clipped mortar face samples", "ms_per_step": mo["ms"],
                          "slave_samples_per_s": mo["value"], "clipped_active_samples": mo["sizes"]["n_active"],
                          "pairs": mo["sizes"]["n_pairs"], "stage_ms": mo["stages"]}
+        out["patch_test"] = measure_patch(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if not args.no_extras:
+            out["cpu_baseline"]["patch_test"] = cpu_patch()
     print(json.dumps(out))
 
 

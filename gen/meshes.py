@@ -216,6 +216,18 @@ def tet_block(nx: int, ny: int, nz: int, h: float):
     return x, tets.astype(np.int32), top.astype(np.int32), bottom.astype(np.int32)
 
 
+def tet_block_bottom(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Boundary triangles of the face z = 0 of ``tet_block(nx, ny, nz, h)``,
+    CCW seen from -z (outward), with the same diagonal as the tetrahedra's
+    faces there."""
+    vid = lambda i, j: (i * (ny + 1) + j) * (nz + 1)
+    ti, tj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    ti, tj = ti.ravel(), tj.ravel()
+    v00, v10 = vid(ti, tj), vid(ti + 1, tj)
+    v11, v01 = vid(ti + 1, tj + 1), vid(ti, tj + 1)
+    return np.concatenate([np.stack([v00, v11, v10], 1), np.stack([v00, v01, v11], 1)]).astype(np.int32)
+
+
 def random_rotation(rng) -> np.ndarray:
     """Uniformly distributed rotation matrix (from a normalised quaternion)."""
     q = rng.normal(size=4)

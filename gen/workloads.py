@@ -211,6 +211,55 @@ def flat_punch(n_pad: int = 8, n_punch: int = 5, gap: float = 3e-4, length: floa
     return _finish(w, fp32)
 
 
+@dataclass
+class PatchTest:
+    """Two stacked linear-elastic blocks in contact (the contact patch test)."""
+    X: np.ndarray          # rest positions [V, 3]: the upper block's vertices, then the lower block's
+    tets: np.ndarray       # [n_tet, 4] int32, global vertex ids
+    Vs: int                # vertices of the upper block (the slave body)
+    ts: np.ndarray         # slave triangles: the upper block's bottom face (outward -z), ids < Vs
+    tm: np.ndarray         # master triangles: the lower block's top face (outward +z), ids local to the lower block
+    fixed: np.ndarray      # the lower block's bottom-face vertices (global ids): u = 0
+    roller: np.ndarray     # the upper block's vertices: u_x = u_y = 0
+    f_ext: np.ndarray      # [V, 3] consistent nodal forces of the pressure on the upper block's top face
+    pressure: float
+    young: float
+    poisson: float
+    dhat: float
+    gap: float
+    h_top: float
+    h_bot: float
+
+
+def patch_test(n_top: int = 4, n_bot: int = 6, size: float = 1.0, gap: float = 2e-3, pressure: float = 10.0,
+               young: float = 1e3, poisson: float = 0.0, dhat: float = 1e-3) -> PatchTest:
+    """The contact patch test of Sec. 5 (Table 1) on synthetic meshes: two
+    blocks of size x size x size/2 (cubes of n x n x n/2 cells, six
+    tetrahedra each; n even), the upper one meshed with n_top cells per
+    side and the lower one with n_bot, so the interface meshes do not match
+    when n_top != n_bot.  The upper block starts ``gap`` above the lower
+    one; its top face carries a uniform pressure (nodal forces p A / 3 per
+    adjacent face triangle, -z); the lower block's bottom face is held and
+    the upper block moves only along z (u_x = u_y = 0), as in the paper."""
+    if n_top % 2 or n_bot % 2:
+        raise ValueError("block resolutions must be even (height = half the side)")
+    ht, hb = size / n_top, size / n_bot
+    Xu, Tu, top_u, _ = meshes.tet_block(n_top, n_top, n_top // 2, ht)
+    Xl, Tl, top_l, bot_l = meshes.tet_block(n_bot, n_bot, n_bot // 2, hb)
+    Xu = Xu + np.array([0.0, 0.0, size / 2 + gap])
+    Vs = Xu.shape[0]
+    X = np.concatenate([Xu, Xl])
+    tets = np.concatenate([Tu, Tl + Vs]).astype(np.int32)
+    ts = meshes.tet_block_bottom(n_top, n_top, n_top // 2)
+    f = np.zeros_like(X)
+    p = Xu[top_u]
+    area = 0.5 * np.linalg.norm(np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), axis=1)
+    for j in range(3):
+        np.add.at(f[:, 2], top_u[:, j], -pressure * area / 3.0)
+    return PatchTest(X, tets, Vs, ts, top_l.astype(np.int32), (bot_l + Vs).astype(np.int32),
+                     np.arange(Vs, dtype=np.int32), f, pressure, young, poisson, dhat, gap, ht, hb)
+
+
 def to_problem(w: Workload):
     """Oracle problem built from a workload (for tests and the CPU baseline)."""
     from oracle import Problem

@@ -271,6 +271,23 @@ def assemble(P: "oracle.Problem", smps, kinematic: bool = False, with_hessian: b
     return MortarAssembly(E, grad, blocks, act, np.array(c1s), np.array(c2s))
 
 
+def frozen_energy(P: "oracle.Problem", active, xs_new, xm_new, kappa_edge: float = 0.0,
+                  kappa_point: float = 0.0, delta_e: float = 0.0) -> float:
+    """Energy of the active samples with every sample frozen (Sec. 4.2):
+    normal, slave barycentrics, master vertices and coefficients, weight
+    and feature weight fixed, so g_k = n . (sum_j bm_j x_mj - sum_a bs_a x_sa)
+    is affine in the positions; +inf if a gap is <= 0."""
+    kap = {2: P.kappa, 1: kappa_edge, 0: kappa_point}
+    E = 0.0
+    for s in active:
+        g = float(s.n @ (s.bm @ xm_new[s.mv] - s.bs @ xs_new[P.ts[s.T]]))
+        if g <= 0.0:
+            return float("inf")
+        if g < P.dhat:
+            E += kap[s.kind] * s.w * gamma(P, s, delta_e) * oracle.barrier(g, P.dhat)
+    return E
+
+
 def linear_step(P: "oracle.Problem", active, dxs, dxm=None) -> float:
     """Eq. (ccd) over clipped samples: min over active samples with
     grad g . dx < 0 of 0.9 g / (-grad g . dx) (inf if none), samples frozen."""

@@ -53,7 +53,8 @@ EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_strea
 MLP_EXPORTS = ["gmcp_mlp_param_count", "gmcp_mlp_work_bytes", "gmcp_mlp_forward", "gmcp_mlp_backward",
                "gmcp_mlp_mse", "gmcp_mlp_adam", "gmcp_gemm_bf16"]
 # include/gmcp_fem.h
-FEM_EXPORTS = ["gmcp_fem_workspace_size", "gmcp_fem_create", "gmcp_fem_destroy", "gmcp_fem_set_stream",
+FEM_EXPORTS = ["gmcp_fem_workspace_size", "gmcp_fem_create", "gmcp_fem_destroy", "gmcp_fem_constrain",
+               "gmcp_fem_set_stream",
                "gmcp_fem_nnzb", "gmcp_fem_stiffness", "gmcp_fem_energy", "gmcp_fem_apply", "gmcp_fem_solve"]
 
 # include/gmcp_dualmesh.h

@@ -1011,8 +1011,13 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
 // n_T n_T^T the coef multiplies) are enumerated in a canonical order - the
 // incident triangles in adjacency order, each with its own three vertices
 // and then its pairs' master vertices - and their columns inserted into an
-// LDS hash set; in PASS 1 the contributions are also kept in LDS (rows
-// longer than kRowEnt re-walk their sources), each lane owns one distinct
+// LDS hash set.  The (incident triangle, item) pairs - an item is the
+// triangle's own three vertices or one of its pairs - are spread over the
+// lanes (item offsets of the triangles in LDS, a binary search per item),
+// and every contribution has a fixed slot in the canonical order.  In PASS 1
+// the contributions and the incident triangles' normals are also kept in
+// LDS (rows with more contributions than the stash, or more than kRowSrc
+// incident triangles, re-walk their sources), each lane owns one distinct
 // column and sums its contributions in the canonical order.
 // Master row j: master columns take the per-master-triangle blocks of
 // k_mtri, summed over the incident triangles in adjacency order; slave
@@ -1020,7 +1025,17 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
 // their blocks equal block (a, j) of slave row a (each contribution is a
 // symmetric coef n n^T), so PASS 3 copies them after PASS 1 has written the
 // slave rows.  Columns are ranked and written ascending.
-constexpr int kRowEnt = 512;
+constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows: kLightEnt)
+constexpr int kRowSrc = kWave;   // incident triangles of a slave row kept in LDS
+
+// LDS bytes of one wave of k_rows: hash set and dense list (slots each),
+// the incident-triangle table, and in PASS 1 the contribution stash and the
+// incident triangles' normals
+template <typename R>
+constexpr size_t row_lds_wave(int slots, int pass, bool heavy) {
+  return (size_t)slots * 8 + (size_t)5 * kRowSrc * 4 +
+         (pass == 1 ? (size_t)(heavy ? kRowEnt : kLightEnt) * (8 + sizeof(R)) + (size_t)kRowSrc * 3 * sizeof(R) : 0);
+}
 
 template <typename R, int PASS, bool HEAVY>  // HEAVY: the heavy-row list (large LDS tables), same code
 __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots, const int32_t *__restrict__ rlist,
@@ -1028,12 +1043,19 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const size_t per_wave = (size_t)slots * 8 + (pass == 1 ? (size_t)kRowEnt * (8 + sizeof(R)) : 0);
+  constexpr int ecap = HEAVY ? kRowEnt : kLightEnt;
+  const size_t per_wave = row_lds_wave<R>(slots, pass, HEAVY);
   int32_t *key = reinterpret_cast<int32_t *>(smem + (size_t)w * per_wave);
   int32_t *dense = key + slots;
-  int32_t *ecol = dense + slots;
-  int32_t *etri = ecol + kRowEnt;
-  R *ecoef = reinterpret_cast<R *>(etri + kRowEnt);
+  int32_t *sip = dense + slots;  // incident-triangle table: item prefix, contribution
+  int32_t *seo = sip + kRowSrc;  // offset, triangle, corner, first pair
+  int32_t *stt = seo + kRowSrc;
+  int32_t *sco = stt + kRowSrc;
+  int32_t *spb = sco + kRowSrc;
+  int32_t *ecol = spb + kRowSrc;  // PASS 1 stash: column, table index, coef
+  int32_t *esrc = ecol + ecap;
+  R *ecoef = reinterpret_cast<R *>(esrc + ecap);
+  R *snrm = ecoef + ecap;  // normals of the table's triangles
   if ((pass == 1 || pass == 3) && (int64_t)a.row_ptr[a.V] > a.cap_nnzb) return;
   // the waves walk the list of rows with contributions (k_row_pre)
   const int64_t nlist = *rcount;
@@ -1205,29 +1227,66 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   while (tsz < 2 * n_ent && tsz < slots) tsz <<= 1;
   for (int i = lane; i < tsz; i += kWave) key[i] = -1;
   wave_sync();
-  const bool stash = pass == 1 && n_ent <= kRowEnt;
+  const bool stash = pass == 1 && n_ent <= ecap && se - sb <= kRowSrc;
   bool full = false;
-  int run = 0;
-  for (int s0 = sb; s0 < se; s0 += kWave) {
-    const int src = s0 + lane;
-    const int cnt = src < se ? src_count(src) : 0;
-    int incl = cnt;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int v = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += v;
+  auto put = [&](int32_t col, R cf, int e, int k) {
+    if (row_slot(key, tsz, col, &full) < 0) return;
+    if (stash) {
+      ecol[e] = col;
+      esrc[e] = k;
+      ecoef[e] = cf;
     }
-    int o = run + incl - cnt;
-    if (src < se)
-      visit_src(src, [&](int32_t col, R cf, int t) {
-        if (row_slot(key, tsz, col, &full) < 0) return;
-        if (stash) {
-          ecol[o] = col;
-          etri[o] = t;
-          ecoef[o] = cf;
-        }
-        ++o;
-      });
-    run += __shfl(incl, kWave - 1, kWave);
+  };
+  int run = 0;  // contributions of the earlier chunks of incident triangles
+  for (int s0 = sb; s0 < se; s0 += kRowSrc) {
+    const int src = s0 + lane;
+    int t = 0, corner = 0, np = 0, pb = 0;
+    if (src < se) {
+      const int ent = a.s_vt[src];
+      t = ent >> 2;
+      corner = ent & 3;
+      np = a.tri_npair[t];
+      if (np > 0 && !a.kinematic) pb = a.tri_poff[t];
+    }
+    const int nit = np > 0 ? 1 + (a.kinematic ? 0 : np) : 0;
+    const int nen = np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
+    int iin = nit, ein = nen;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int vi = __shfl_up(iin, d, kWave), ve = __shfl_up(ein, d, kWave);
+      if (lane >= d) {
+        iin += vi;
+        ein += ve;
+      }
+    }
+    const int items = __shfl(iin, kWave - 1, kWave), ents = __shfl(ein, kWave - 1, kWave);
+    wave_sync();  // the previous chunk's table reads are done
+    sip[lane] = iin - nit;
+    seo[lane] = run + ein - nen;
+    stt[lane] = t;
+    sco[lane] = corner;
+    spb[lane] = pb;
+    if (stash && np > 0)
+      for (int d = 0; d < 3; ++d) snrm[3 * lane + d] = a.tri_nrm[3 * (int64_t)t + d];
+    wave_sync();
+    for (int f = lane; f < items; f += kWave) {
+      int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sip[mid] <= f) lo = mid;
+        else hi = mid - 1;
+      }
+      const int j = f - sip[lo], tt = stt[lo], c = sco[lo];
+      if (j == 0) {  // the triangle's own vertices
+        const R *S = a.tri_sum + 9 * (int64_t)tt;
+        for (int b = 0; b < 3; ++b) put(a.ts[3 * (int64_t)tt + b], S[sym3(c, b)], seo[lo] + b, lo);
+      } else {  // pair j - 1 of the triangle: its master vertices
+        const Pair<R> &P = a.pair[spb[lo] + j - 1];
+        const int e0 = seo[lo] + 3 + 3 * (j - 1);
+        for (int m = 0; m < 3; ++m)
+          put((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * c + m], e0 + m, lo);
+      }
+    }
+    run += ents;
   }
   if (__any(full)) {
     if (lane == 0) {
@@ -1256,9 +1315,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     int r = 0;
     for (int m = 0; m < nuniq; ++m) r += dense[m] < c;
     R v[6] = {0, 0, 0, 0, 0, 0};
-    auto add = [&](int32_t col, R cf, int t) {
-      if (col != c) return;
-      const R *nn = a.tri_nrm + 3 * (int64_t)t;
+    auto add_n = [&](R cf, const R *nn) {
       v[0] += cf * nn[0] * nn[0];
       v[1] += cf * nn[0] * nn[1];
       v[2] += cf * nn[0] * nn[2];
@@ -1267,9 +1324,13 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       v[5] += cf * nn[2] * nn[2];
     };
     if (stash) {
-      for (int e = 0; e < n_ent; ++e) add(ecol[e], ecoef[e], etri[e]);
+      for (int e = 0; e < n_ent; ++e)
+        if (ecol[e] == c) add_n(ecoef[e], snrm + 3 * esrc[e]);
     } else {
-      for (int src = sb; src < se; ++src) visit_src(src, add);
+      for (int src = sb; src < se; ++src)
+        visit_src(src, [&](int32_t col, R cf, int t) {
+          if (col == c) add_n(cf, a.tri_nrm + 3 * (int64_t)t);
+        });
     }
     const int64_t dst = (int64_t)a.row_ptr[row] + r;
     a.col[dst] = c;
@@ -1501,7 +1562,13 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
                            R *grad, const gmcp_bsr *H) {
   Buffers &b = c->b;
   hipStream_t s = c->stream;
-  hipError_t e = reset_status(c, 2);
+  StageInit si;
+  si.which = 2;
+  si.zero[0] = b.rcount;  // row-list lengths
+  si.nzero[0] = 2;
+  si.zero[1] = b.row_cnt + c->V;  // the scan's tail
+  si.nzero[1] = 1;
+  hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
   NarrowArgs<R> na;
   na.xs = xs;
@@ -1569,8 +1636,6 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     prof_mark(c, ST_MTRI, 1);
   }
   if (grad || H) {
-    e = fill_i32(c, b.rcount, 0, 2);
-    if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_PRE, 0);
     if (c->V)
       hipLaunchKernelGGL(k_row_pre<R>, dim3(nblk(c->V)), dim3(kThreads), 0, s, ra, b.rlist, b.rcount, H ? 1 : 0);
@@ -1595,24 +1660,20 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     const int lslots = 2 * kLightEnt;
     int hslots = 1024;
     while (hslots < c->caps.row_entries && hslots < 4096) hslots <<= 1;
-    auto lds = [&](int sl, int pass) {
-      return (size_t)nw * ((size_t)sl * 8 + (pass == 1 ? (size_t)kRowEnt * (8 + sizeof(R)) : 0));
-    };
-    e = fill_i32(c, b.row_cnt + c->V, 0, 1);
-    if (e != hipSuccess) return e;
+    auto lds = [&](int sl, int pass, bool heavy) { return (size_t)nw * row_lds_wave<R>(sl, pass, heavy); };
     prof_mark(c, ST_ROWS_COUNT, 0);
-    hipLaunchKernelGGL((k_rows<R, 0, false>), rgrid, dim3(kWave * nw), lds(lslots, 0), s, ra, lslots, light, nlight);
+    hipLaunchKernelGGL((k_rows<R, 0, false>), rgrid, dim3(kWave * nw), lds(lslots, 0, false), s, ra, lslots, light, nlight);
     prof_mark(c, ST_ROWS_COUNT, 1);
     prof_mark(c, ST_ROWS_COUNT_H, 0);
-    hipLaunchKernelGGL((k_rows<R, 0, true>), hgrid, dim3(kWave * nw), lds(hslots, 0), s, ra, hslots, heavy, nheavy);
+    hipLaunchKernelGGL((k_rows<R, 0, true>), hgrid, dim3(kWave * nw), lds(hslots, 0, true), s, ra, hslots, heavy, nheavy);
     prof_mark(c, ST_ROWS_COUNT_H, 1);
     e = scan_exclusive(c, b.row_cnt, H->row_ptr, c->V + 1);
     if (e != hipSuccess) return e;
     prof_mark(c, ST_ROWS_FILL, 0);
-    hipLaunchKernelGGL((k_rows<R, 1, false>), rgrid, dim3(kWave * nw), lds(lslots, 1), s, ra, lslots, light, nlight);
+    hipLaunchKernelGGL((k_rows<R, 1, false>), rgrid, dim3(kWave * nw), lds(lslots, 1, false), s, ra, lslots, light, nlight);
     prof_mark(c, ST_ROWS_FILL, 1);
     prof_mark(c, ST_ROWS_FILL_H, 0);
-    hipLaunchKernelGGL((k_rows<R, 1, true>), hgrid, dim3(kWave * nw), lds(hslots, 1), s, ra, hslots, heavy, nheavy);
+    hipLaunchKernelGGL((k_rows<R, 1, true>), hgrid, dim3(kWave * nw), lds(hslots, 1, true), s, ra, hslots, heavy, nheavy);
     prof_mark(c, ST_ROWS_FILL_H, 1);
     if (c->V > c->Vs) {
       prof_mark(c, ST_ROWS_COPY, 0);

@@ -30,18 +30,12 @@ __device__ inline void load3(const R *x, int64_t v, float o[3]) {
 // outward rounding margin for float boxes of (possibly double) coordinates
 __device__ inline float grow(float v) { return fabsf(v) * 4e-7f + 1e-30f; }
 
-__global__ void k_box_init(uint32_t *box, int n_env) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_env) return;
-  for (int d = 0; d < 3; ++d) {
-    box[6 * e + d] = 0xffffffffu;    // min: largest ordered value
-    box[6 * e + 3 + d] = 0u;         // max: smallest ordered value
-  }
-}
+// slave surface box per environment (swept: union of x and x + dx); large
+// blocks, so that few blocks meet at each environment's six words
+constexpr int kBoxThreads = 1024;
 
-// slave surface box per environment (swept: union of x and x + dx)
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
+__global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
                                                          const int32_t *__restrict__ ts,
                                                          const int32_t *__restrict__ s_env, int64_t Ts,
                                                          uint32_t *box) {
@@ -70,8 +64,8 @@ __global__ __launch_bounds__(kThreads) void k_slave_box(const R *__restrict__ xs
   }
   // environments are contiguous in triangle order: most blocks hold one,
   // which then takes a single set of atomics
-  __shared__ int benv[kThreads / kWave];
-  __shared__ float bbox[kThreads / kWave][6];
+  __shared__ int benv[kBoxThreads / kWave];
+  __shared__ float bbox[kBoxThreads / kWave][6];
   const int w = threadIdx.x / kWave;
   uint64_t vm = __ballot(ok);
   int e0 = vm ? __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave) : -1;
@@ -191,11 +185,16 @@ __device__ inline bool box_hits_grid(const GridEnv &g, const float lo[3], const 
   return true;
 }
 
-// master triangle boxes (and unit normals): static or swept over dx
+// master triangle boxes (and unit normals), static or swept over dx, and
+// the count of the grid cells each box covers (placement: k_grid_insert)
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_master_boxes(const R *__restrict__ xm, const R *__restrict__ dxm,
                                                             const int32_t *__restrict__ tm, int64_t Tm,
-                                                            float4 *__restrict__ mbox) {
+                                                            float4 *__restrict__ mbox,
+                                                            const int32_t *__restrict__ m_env,
+                                                            const EnvInfo *__restrict__ env,
+                                                            const GridEnv *__restrict__ grid,
+                                                            int32_t *__restrict__ cell_cnt) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Tm) return;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -225,9 +224,22 @@ __global__ __launch_bounds__(kThreads) void k_master_boxes(const R *__restrict__
   mbox[3 * t + 0] = make_float4(lo[0], lo[1], lo[2], 0.0f);
   mbox[3 * t + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
   mbox[3 * t + 2] = make_float4((float)(N[0] * inv), (float)(N[1] * inv), (float)(N[2] * inv), 0.0f);
+  const int e = m_env[t];
+  const GridEnv g = grid[e];
+  if (!g.valid || !box_hits_grid(g, lo, hi)) return;
+  int c0[3], c1[3];
+  for (int d = 0; d < 3; ++d) {
+    c0[d] = cell_coord(g, lo[d], d);
+    c1[d] = cell_coord(g, hi[d], d);
+  }
+  const int64_t base = env[e].cell0;
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&cell_cnt[base + ((int64_t)z * g.ny + y) * g.nx + x], 1);
 }
 
-// pass 0: count incidences; pass 1: place ids (counters return to zero)
+// place the master ids in their cells after the count and its scan (the
+// counters return to zero); same cell ranges as the count
 __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restrict__ mbox,
                                                            const int32_t *__restrict__ m_env,
                                                            const EnvInfo *__restrict__ env,
@@ -235,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
                                                            int32_t *__restrict__ cell_cnt,
                                                            const int32_t *__restrict__ cell_start,
                                                            int32_t *__restrict__ items, int64_t cap_items,
-                                                           int64_t total_cells, DevStatus *st, int pass) {
+                                                           int64_t total_cells, DevStatus *st) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Tm) return;
   int e = m_env[t];
@@ -250,25 +262,18 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
     c1[d] = cell_coord(g, hi[d], d);
   }
   int64_t base = env[e].cell0;
-  bool fits = true;
-  if (pass == 1) {
-    int64_t total = cell_start[total_cells];
-    fits = total <= cap_items;
-    if (!fits && t == 0) {
-      atomicMax(&st->need_items, (unsigned long long)total);
-      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
-    }
+  const int64_t total = cell_start[total_cells];
+  const bool fits = total <= cap_items;
+  if (!fits && t == 0) {
+    atomicMax(&st->need_items, (unsigned long long)total);
+    atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
   }
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
         int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
-        if (pass == 0) {
-          atomicAdd(&cell_cnt[cell], 1);
-        } else {
-          int slot = cell_start[cell] + atomicSub(&cell_cnt[cell], 1) - 1;
-          if (fits) items[slot] = (int32_t)t;
-        }
+        int slot = cell_start[cell] + atomicSub(&cell_cnt[cell], 1) - 1;
+        if (fits) items[slot] = (int32_t)t;
       }
 }
 
@@ -427,6 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      const int32_t *__restrict__ qcount, DevStatus *st) {
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
+  __shared__ int32_t ipfx[kQueryWaves][kWave], istart[kQueryWaves][kWave], islab[kQueryWaves][kWave];
   __shared__ int blk_req;  // candidates requested by this block's triangles (LDS atomics)
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t nlist = *qcount;
@@ -503,33 +509,66 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   while (tsz < 2 * nitems && tsz < kQuerySet) tsz <<= 1;
   for (int k = lane; k < tsz; k += kWave) set[w][k] = -1;
   wave_sync();
-  int fresh = 0;
   bool full = false;
-  for_cells([&](int s, int64_t cell) {
-    float lo[3], hi[3];
-    slab_box(tlo, thi, n, -eps + s * dt, -eps + (s + 1) * dt, margin, lo, hi);
-    const int j1 = cell_start[cell + 1];
-    for (int j = cell_start[cell]; j < j1; ++j) {
-      int M = items[j];
-      float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1];
+  // the (slab, cell) items are taken 64 at a time; their master-triangle
+  // incidences are flattened over the lanes (exclusive prefix of the cell
+  // sizes in LDS, binary search per incidence), so a crowded cell does not
+  // serialise on one lane
+  for (int w0 = 0; w0 < work; w0 += kWave) {
+    const int wi = w0 + lane;
+    int s = 0;
+    for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
+    s = min(s, kWave - 1);
+    const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
+    const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
+    const int sstart = __shfl(incl - ncs, s, kWave);
+    int cs = 0, cn = 0;
+    if (wi < work) {
+      const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
+      const int li = wi - sstart;
+      const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+      const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
+      cs = cell_start[cell];
+      cn = cell_start[cell + 1] - cs;
+    }
+    int ci = cn;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int v = __shfl_up(ci, d, kWave);
+      if (lane >= d) ci += v;
+    }
+    const int tot = __shfl(ci, kWave - 1, kWave);
+    wave_sync();
+    ipfx[w][lane] = ci - cn;
+    istart[w][lane] = cs;
+    islab[w][lane] = s;
+    wave_sync();
+    for (int f = lane; f < tot; f += kWave) {
+      int lo_k = 0, hi_k = kWave - 1;  // the last item whose prefix is <= f
+      while (lo_k < hi_k) {
+        const int mid = (lo_k + hi_k + 1) >> 1;
+        if (ipfx[w][mid] <= f) lo_k = mid;
+        else hi_k = mid - 1;
+      }
+      const int j = istart[w][lo_k] + (f - ipfx[w][lo_k]);
+      const int sl = islab[w][lo_k];
+      float lo[3], hi[3];
+      slab_box(tlo, thi, n, -eps + sl * dt, -eps + (sl + 1) * dt, margin, lo, hi);
+      const int M = items[j];
+      const float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1];
       if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
-      float4 nm = mbox[3 * (int64_t)M + 2];
+      const float4 nm = mbox[3 * (int64_t)M + 2];
       // facing test with slack: the narrow phase takes the exact decision
       if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
       uint32_t h = ((uint32_t)M * 2654435761u) & (uint32_t)(tsz - 1);
       int probe = 0;
       for (; probe < tsz; ++probe) {
-        int prev = atomicCAS(&set[w][h], -1, M);
-        if (prev == -1) {
-          ++fresh;
-          break;
-        }
-        if (prev == M) break;
+        const int prev = atomicCAS(&set[w][h], -1, M);
+        if (prev == -1 || prev == M) break;
         h = (h + 1) & (uint32_t)(tsz - 1);
       }
       if (probe == tsz) full = true;
     }
-  });
+  }
   if (__any(full)) {
     if (lane == 0) {
       atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
@@ -581,18 +620,15 @@ __global__ __launch_bounds__(kThreads) void k_cand_move(const int32_t *__restric
                                                          const int32_t *__restrict__ tmp_off,
                                                          const int32_t *__restrict__ cand_off,
                                                          const int32_t *__restrict__ cand_tmp,
-                                                         int32_t *__restrict__ cand) {
+                                                         int32_t *__restrict__ cand, int64_t Ts, DevStatus *st) {
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
   const int64_t nlist = *qcount;
   for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves) {
     const int t = qlist[li];
     const int n = cand_cnt[t], src = tmp_off[t], dst = cand_off[t];
     for (int k = lane; k < n; k += kWave) cand[dst + k] = cand_tmp[src + k];
   }
-}
-
-__global__ void k_cand_total(const int32_t *cand_off, int64_t Ts, DevStatus *st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -609,23 +645,21 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   int32_t *items = swept ? b.sitems : b.items;
   float4 *mbox = swept ? b.smbox : b.mbox;
   hipStream_t s = c->stream;
-  hipLaunchKernelGGL(k_box_init, dim3((c->n_env + 63) / 64), dim3(64), 0, s, box, c->n_env);
+  // the caller's stage_init has emptied the boxes
   if (c->Ts)
-    hipLaunchKernelGGL(k_slave_box<R>, dim3(nblk(c->Ts)), dim3(kThreads), 0, s, xs, swept ? dxs : nullptr, c->ts,
-                       b.s_env, c->Ts, box);
+    hipLaunchKernelGGL(k_slave_box<R>, dim3((unsigned)((c->Ts + kBoxThreads - 1) / kBoxThreads)),
+                       dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, c->ts, b.s_env, c->Ts, box);
   hipLaunchKernelGGL(k_grid_setup, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.env, box, grid, c->n_env,
                      swept ? 1 : 0);
   if (c->Tm) {
     hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr,
-                       c->tm, c->Tm, mbox);
-    hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,
-                       cnt, start, items, c->caps.grid_items, c->total_cells, b.status, 0);
+                       c->tm, c->Tm, mbox, b.m_env, b.env, grid, cnt);
   }
   hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1);
   if (e != hipSuccess) return e;
   if (c->Tm)
     hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,
-                       cnt, start, items, c->caps.grid_items, c->total_cells, b.status, 1);
+                       cnt, start, items, c->caps.grid_items, c->total_cells, b.status);
   return hipGetLastError();
 }
 
@@ -633,13 +667,18 @@ template <typename R>
 hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   Buffers &b = c->b;
   hipStream_t s = c->stream;
-  hipError_t e = reset_status(c, 1);
+  StageInit si;
+  si.which = 1;
+  si.box = b.box;
+  si.zero[0] = b.qcount;
+  si.nzero[0] = 1;
+  si.zero[1] = b.cand_cnt + c->Ts;
+  si.nzero[1] = 1;
+  hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_GRID, 0);
   e = build_grid<R>(c, xs, xm, nullptr, nullptr, false);
   prof_mark(c, ST_GRID, 1);
-  if (e != hipSuccess) return e;
-  e = fill_i32(c, b.qcount, 0, 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_QUERY_PRE, 0);
   if (c->Ts)
@@ -656,16 +695,13 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
                        c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
   prof_mark(c, ST_QUERY_COUNT, 1);
-  e = fill_i32(c, b.cand_cnt + c->Ts, 0, 1);
-  if (e != hipSuccess) return e;
   e = scan_exclusive(c, b.cand_cnt, b.cand_off, c->Ts + 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_QUERY_FILL, 0);
   if (c->Ts)
     hipLaunchKernelGGL(k_cand_move, qgrid, dim3(kThreads), 0, s, b.qlist, b.qcount, b.cand_cnt, b.cand_tmp_off,
-                       b.cand_off, b.cand_tmp, b.cand);
+                       b.cand_off, b.cand_tmp, b.cand, c->Ts, b.status);
   prof_mark(c, ST_QUERY_FILL, 1);
-  hipLaunchKernelGGL(k_cand_total, dim3(1), dim3(64), 0, s, b.cand_off, c->Ts, b.status);
   return hipGetLastError();
 }
 

@@ -15,11 +15,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kAccdMaxIter = 1 << 14;
 
-__global__ void k_alpha_init(uint32_t *bits, int n_env) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n_env) bits[e] = 0x7f800000u;  // +inf
-}
-
 template <typename R> __device__ inline float to_float_down(R v);
 template <> __device__ inline float to_float_down<float>(float v) { return v; }
 template <> __device__ inline float to_float_down<double>(double v) { return __double2float_rd(v); }
@@ -381,9 +376,12 @@ template <typename R>
 hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha) {
   Buffers &b = c->b;
   hipStream_t s = c->stream;
-  hipError_t e = reset_status(c, 4);
+  StageInit si;
+  si.which = 4;
+  si.box = b.sbox;
+  si.alpha = b.alpha_bits;
+  hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_alpha_init, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env);
   const R *dm = dxm;
   prof_mark(c, ST_CCD_LINEAR, 0);
   if (c->n_tiles)

@@ -169,7 +169,17 @@ namespace gmcp {
 // each returns hipSuccess or the launch error
 hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n);
 hipError_t fill_i32(gmcp_ctx *c, int32_t *p, int32_t v, int64_t n);
-hipError_t reset_status(gmcp_ctx *c, int which);
+// one launch for a stage's scalar set-up: the status fields of the stage
+// (which: 1 broad phase, 2 assembly, 4 step bound), empty boxes and +inf
+// step-bound bits per environment, and a few words set to zero
+struct StageInit {
+  int which = 0;
+  uint32_t *box = nullptr;
+  uint32_t *alpha = nullptr;
+  int32_t *zero[3] = {nullptr, nullptr, nullptr};
+  int nzero[3] = {0, 0, 0};  // <= 64 words each
+};
+hipError_t stage_init(gmcp_ctx *c, const StageInit &a);
 // event profiler: prof_mark(c, s, 0) before a stage's launches, (c, s, 1) after
 void prof_mark(gmcp_ctx *c, int stage, int end);
 

@@ -28,7 +28,7 @@ struct FemDev {
   double *k_val;               // [nnzb][9]
   int32_t *c_off, *c_list;     // per K block: contributions tet*16 + a*4 + b
   double *mass;                // [V] lumped mass
-  uint8_t *fixed;              // [V] 1 = Dirichlet vertex
+  uint8_t *fixed;              // [V] Dirichlet components: bit d = component d held
   double *X;                   // [V][3] rest positions
   int32_t *tets;               // [n_tet][4]
   double *Pinv;                // [V][9] block-Jacobi inverse
@@ -44,6 +44,7 @@ struct gmcp_fem {
   int64_t V, n_tet, nnzb, nblk;
   double mu, lambda, rho, dt;
   FemDev d;
+  std::vector<uint8_t> hfixed;  // host copy of the Dirichlet component masks
 };
 
 namespace {
@@ -91,7 +92,15 @@ __global__ void k_kvals(const double *X, const int32_t *tets, const int32_t *c_o
   for (int z = 0; z < 9; ++z) k_val[9 * bk + z] = K[z];
 }
 
-// y = (M/dt^2) x + K x + H x (H optional), 0 on fixed vertices
+// component d of vertex c, 0 when that component is held (Dirichlet
+// columns removed)
+__device__ inline void free_part(const double *x, const uint8_t *fixed, int64_t c, double v[3]) {
+  const int m = fixed[c];
+  for (int d = 0; d < 3; ++d) v[d] = (m >> d) & 1 ? 0.0 : x[3 * c + d];
+}
+
+// y = (M/dt^2) x + K x + H x (H optional) over the free components; 0 in
+// the held ones
 __global__ void k_apply(const int32_t *__restrict__ krp, const int32_t *__restrict__ kcol,
                         const double *__restrict__ kval, const int32_t *__restrict__ hrp,
                         const int32_t *__restrict__ hcol, const double *__restrict__ hval,
@@ -99,28 +108,31 @@ __global__ void k_apply(const int32_t *__restrict__ krp, const int32_t *__restri
                         const double *__restrict__ x, double *__restrict__ y, int64_t V) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V) return;
-  if (fixed[i]) {
+  const int mi = fixed[i];
+  if (mi == 7) {
     y[3 * i] = y[3 * i + 1] = y[3 * i + 2] = 0.0;
     return;
   }
-  double s[3];
-  for (int d = 0; d < 3; ++d) s[d] = mass[i] * inv_dt2 * x[3 * i + d];
+  double s[3], v[3];
+  free_part(x, fixed, i, v);
+  for (int d = 0; d < 3; ++d) s[d] = mass[i] * inv_dt2 * v[d];
   for (int j = krp[i]; j < krp[i + 1]; ++j) {
     int64_t c = kcol[j];
-    if (fixed[c]) continue;
+    if (fixed[c] == 7) continue;
+    free_part(x, fixed, c, v);
     const double *B = kval + 9 * (int64_t)j;
-    for (int r = 0; r < 3; ++r) s[r] += B[3 * r] * x[3 * c] + B[3 * r + 1] * x[3 * c + 1] + B[3 * r + 2] * x[3 * c + 2];
+    for (int r = 0; r < 3; ++r) s[r] += B[3 * r] * v[0] + B[3 * r + 1] * v[1] + B[3 * r + 2] * v[2];
   }
   if (hrp) {
     for (int j = hrp[i]; j < hrp[i + 1]; ++j) {
       int64_t c = hcol[j];
-      if (fixed[c]) continue;
+      if (fixed[c] == 7) continue;
+      free_part(x, fixed, c, v);
       const double *B = hval + 9 * (int64_t)j;
-      for (int r = 0; r < 3; ++r)
-        s[r] += B[3 * r] * x[3 * c] + B[3 * r + 1] * x[3 * c + 1] + B[3 * r + 2] * x[3 * c + 2];
+      for (int r = 0; r < 3; ++r) s[r] += B[3 * r] * v[0] + B[3 * r + 1] * v[1] + B[3 * r + 2] * v[2];
     }
   }
-  for (int d = 0; d < 3; ++d) y[3 * i + d] = s[d];
+  for (int d = 0; d < 3; ++d) y[3 * i + d] = (mi >> d) & 1 ? 0.0 : s[d];
 }
 
 __device__ inline bool inv3(const double *A, double *B) {
@@ -154,9 +166,17 @@ __global__ void k_jacobi(const int32_t *krp, const int32_t *kcol, const double *
     for (int j = hrp[i]; j < hrp[i + 1]; ++j)
       if (hcol[j] == i)
         for (int z = 0; z < 9; ++z) D[z] += hval[9 * (int64_t)j + z];
+  // held components: identity rows/columns for the inverse, zeroed after
+  const int m = fixed[i];
+  for (int d = 0; d < 3; ++d)
+    if ((m >> d) & 1)
+      for (int k = 0; k < 3; ++k) D[3 * d + k] = D[3 * k + d] = (k == d) ? 1.0 : 0.0;
   double P[9];
-  if (fixed[i] || !inv3(D, P))
+  if (m == 7 || !inv3(D, P))
     for (int z = 0; z < 9; ++z) P[z] = 0.0;
+  for (int d = 0; d < 3; ++d)
+    if ((m >> d) & 1)
+      for (int k = 0; k < 3; ++k) P[3 * d + k] = P[3 * k + d] = 0.0;
   for (int z = 0; z < 9; ++z) Pinv[9 * i + z] = P[z];
 }
 
@@ -241,7 +261,7 @@ __global__ void k_cg_roll(double *s) {
 __global__ void k_copy_mask(const double *src, double *dst, const uint8_t *fixed, int64_t V, double scale) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V) return;
-  for (int d = 0; d < 3; ++d) dst[3 * i + d] = fixed[i] ? 0.0 : scale * src[3 * i + d];
+  for (int d = 0; d < 3; ++d) dst[3 * i + d] = (fixed[i] >> d) & 1 ? 0.0 : scale * src[3 * i + d];
 }
 
 __global__ void k_zero(double *p, int64_t n) {
@@ -250,7 +270,7 @@ __global__ void k_zero(double *p, int64_t n) {
 }
 
 // elastic + inertial energy terms per vertex and gradient:
-//   g_i = m_i (x_i - xt_i)/dt^2 + (K (x - X))_i ; 0 on fixed vertices
+//   g_i = m_i (x_i - xt_i)/dt^2 + (K (x - X))_i ; 0 in held components
 //   e_i = 1/2 m_i |x_i - xt_i|^2 / dt^2 + 1/2 u_i . (K u)_i
 __global__ void k_fem_grad(const int32_t *krp, const int32_t *kcol, const double *kval, const double *mass,
                            const uint8_t *fixed, double inv_dt2, const double *X, const double *x,
@@ -269,7 +289,7 @@ __global__ void k_fem_grad(const int32_t *krp, const int32_t *kcol, const double
     double dv = x[3 * i + d] - xt[3 * i + d];
     double ui = x[3 * i + d] - X[3 * i + d];
     ei += 0.5 * mass[i] * inv_dt2 * dv * dv + 0.5 * ui * ku[d];
-    if (g) g[3 * i + d] = fixed[i] ? 0.0 : mass[i] * inv_dt2 * dv + ku[d];
+    if (g) g[3 * i + d] = (fixed[i] >> d) & 1 ? 0.0 : mass[i] * inv_dt2 * dv + ku[d];
   }
   e[i] = ei;
 }
@@ -394,7 +414,7 @@ int gmcp_fem_create(gmcp_fem **out, const int32_t *tets, int64_t n_tet, int64_t 
     for (int k = 0; k < 4; ++k) mass[tets[4 * e + k]] += density * fabs(det) / 24.0;
   }
   std::vector<uint8_t> fx(n_vert, 0);
-  for (int64_t i = 0; i < n_fixed; ++i) fx[fixed[i]] = 1;
+  for (int64_t i = 0; i < n_fixed; ++i) fx[fixed[i]] = 7;
   hipError_t e = hipSuccess;
   auto up = [&](void *dst, const void *src, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
@@ -405,6 +425,7 @@ int gmcp_fem_create(gmcp_fem **out, const int32_t *tets, int64_t n_tet, int64_t 
   up(f->d.c_list, t.clist.data(), sizeof(int32_t) * t.clist.size());
   up(f->d.mass, mass.data(), sizeof(double) * n_vert);
   up(f->d.fixed, fx.data(), n_vert);
+  f->hfixed = fx;
   up(f->d.X, X_rest, sizeof(double) * 3 * n_vert);
   up(f->d.tets, tets, sizeof(int32_t) * 4 * n_tet);
   if (e != hipSuccess) {
@@ -422,6 +443,17 @@ int gmcp_fem_create(gmcp_fem **out, const int32_t *tets, int64_t n_tet, int64_t 
 }
 
 void gmcp_fem_destroy(gmcp_fem *f) { delete f; }
+
+int gmcp_fem_constrain(gmcp_fem *f, const int32_t *verts, int64_t n, int mask) {
+  if (!f || n < 0 || (n > 0 && !verts) || mask < 1 || mask > 7) return GMCP_E_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if (verts[i] < 0 || verts[i] >= f->V) return GMCP_E_ARG;
+  for (int64_t i = 0; i < n; ++i) f->hfixed[verts[i]] |= (uint8_t)mask;
+  if (hipStreamSynchronize(f->stream) != hipSuccess ||
+      hipMemcpy(f->d.fixed, f->hfixed.data(), (size_t)f->V, hipMemcpyHostToDevice) != hipSuccess)
+    return GMCP_E_HIP;
+  return GMCP_OK;
+}
 
 int gmcp_fem_set_stream(gmcp_fem *f, void *stream) {
   if (!f) return GMCP_E_ARG;

@@ -57,31 +57,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *__restrict__
     if (j < n) out[j] += add;
 }
 
-// Exclusive scan of up to kScanOne elements in one block of 1024 threads:
-// each thread scans a contiguous run, the run totals are scanned across
-// the block (wave scans + LDS), then the runs are written (one launch).
-constexpr int kOneThreads = 1024;
-constexpr int64_t kScanOne = 1 << 17;
+// Second launch of the two-launch scan (up to kScanTop blocks): block b
+// adds the sum of the block totals before it (its threads split them, wave
+// butterflies, the wave sums in LDS) to its 1024 elements.
+constexpr int64_t kScanTop = 1024;
 
-__global__ __launch_bounds__(kOneThreads) void k_scan_one(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                           int64_t n) {
-  __shared__ int wsum[kOneThreads / kWave];
+__global__ __launch_bounds__(kScanThreads) void k_scan_add_top(int32_t *__restrict__ out,
+                                                                const int32_t *__restrict__ sums, int64_t n) {
+  __shared__ int wsum[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const int64_t per = (n + kOneThreads - 1) / kOneThreads;
-  const int64_t b = (int64_t)tid * per, e = b + per < n ? b + per : n;
-  int run = 0;
-  for (int64_t j = b; j < e; ++j) run += in[j];
-  const int incl = wave_incl_scan(run, lane);
-  if (lane == kWave - 1) wsum[w] = incl;
+  const int b = blockIdx.x;
+  int s = 0;
+  for (int i = tid; i < b; i += kScanThreads) s += sums[i];
+  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane == 0) wsum[w] = s;
   __syncthreads();
-  int woff = 0;
-  for (int i = 0; i < w; ++i) woff += wsum[i];
-  int ex = woff + incl - run;
-  for (int64_t j = b; j < e; ++j) {
-    const int v = in[j];
-    out[j] = ex;
-    ex += v;
-  }
+  int add = 0;
+  for (int i = 0; i < kScanThreads / kWave; ++i) add += wsum[i];
+  int64_t j = (int64_t)b * kScanBlock + tid;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i, j += kScanThreads)
+    if (j < n) out[j] += add;
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -90,17 +86,28 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_reset_status(DevStatus *st, int which) {
-  if (threadIdx.x != 0) return;
-  if (which & 1) {  // broad phase
-    st->n_cand = 0;
+__global__ void k_stage_init(DevStatus *st, StageInit a, int n_env) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {
+    if (a.which & 1) st->n_cand = 0;  // broad phase
+    if (a.which & 2) {                // assembly
+      st->n_active = 0;
+      st->n_pairs = 0;
+      st->nnzb = 0;
+    }
+    if (a.which & 4) st->n_swept = 0;  // step bound
   }
-  if (which & 2) {  // assembly
-    st->n_active = 0;
-    st->n_pairs = 0;
-    st->nnzb = 0;
+  if (blockIdx.x == 0)
+    for (int k = 0; k < 3; ++k)
+      if (a.zero[k] && (int)threadIdx.x < a.nzero[k]) a.zero[k][threadIdx.x] = 0;
+  if (e < n_env) {
+    if (a.box)
+      for (int d = 0; d < 3; ++d) {
+        a.box[6 * e + d] = 0xffffffffu;  // min: largest ordered value
+        a.box[6 * e + 3 + d] = 0u;       // max: smallest ordered value
+      }
+    if (a.alpha) a.alpha[e] = 0x7f800000u;  // +inf
   }
-  if (which & 4) st->n_swept = 0;
 }
 
 }  // namespace
@@ -109,12 +116,16 @@ hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t 
   // levels: out <- scan(in); block sums in tmp, scanned recursively in place
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb <= 0) return hipSuccess;
-  if (n <= kScanOne && nb > 1) {
-    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kOneThreads), 0, c->stream, in, out, n);
-    return hipGetLastError();
-  }
   if (nb == 1) {
     hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kScanThreads), 0, c->stream, in, out, nullptr, n);
+    return hipGetLastError();
+  }
+  if (nb <= kScanTop) {  // two launches: block scans + totals, then each block's offset
+    if (nb > (int64_t)c->scan_tmp_elems) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, in, out, c->b.scan_tmp,
+                       n);
+    hipLaunchKernelGGL(k_scan_add_top, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, out,
+                       (const int32_t *)c->b.scan_tmp, n);
     return hipGetLastError();
   }
   // the scratch holds every level's block sums back to back
@@ -163,8 +174,11 @@ hipError_t fill_i32(gmcp_ctx *c, int32_t *p, int32_t v, int64_t n) {
   return hipGetLastError();
 }
 
-hipError_t reset_status(gmcp_ctx *c, int which) {
-  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, c->stream, c->b.status, which);
+hipError_t stage_init(gmcp_ctx *c, const StageInit &a) {
+  for (int k = 0; k < 3; ++k)
+    if (a.nzero[k] > 64) return hipErrorInvalidValue;
+  const int blocks = c->n_env > 64 ? (c->n_env + 63) / 64 : 1;
+  hipLaunchKernelGGL(k_stage_init, dim3(blocks), dim3(64), 0, c->stream, c->b.status, a, c->n_env);
   return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ def _lib():
                                       C.c_double, C.c_double, P, C.c_int64, P, C.c_size_t, P]
         L.gmcp_fem_destroy.restype = None
         L.gmcp_fem_destroy.argtypes = [P]
+        L.gmcp_fem_constrain.restype = C.c_int
+        L.gmcp_fem_constrain.argtypes = [P, P, C.c_int64, C.c_int]
         L.gmcp_fem_set_stream.restype = C.c_int
         L.gmcp_fem_set_stream.argtypes = [P, P]
         L.gmcp_fem_nnzb.restype = C.c_int64
@@ -61,7 +63,8 @@ class Fem:
         _check(rc, "gmcp_fem_create")
         self._h = h
         self.X = torch.tensor(X, device=self.device)
-        self.fixed = torch.zeros(self.V, dtype=torch.bool, device=self.device)
+        # held displacement components [V, 3] (whole Dirichlet vertices, rollers)
+        self.fixed = torch.zeros(self.V, 3, dtype=torch.bool, device=self.device)
         self.fixed[torch.tensor(F, dtype=torch.long, device=self.device)] = True
         self._e = torch.zeros(1, dtype=torch.float64, device=self.device)
 
@@ -70,6 +73,16 @@ class Fem:
             _lib().gmcp_fem_destroy(self._h)
         except Exception:
             pass
+
+    def constrain(self, verts, mask: int):
+        """Hold components of vertices: mask bit d (1 = x, 2 = y, 4 = z)."""
+        V = np.ascontiguousarray(verts, dtype=np.int32)
+        self._bind()
+        _check(_lib().gmcp_fem_constrain(self._h, V.ctypes.data, V.shape[0], int(mask)), "gmcp_fem_constrain")
+        idx = torch.tensor(V, dtype=torch.long, device=self.device)
+        for d in range(3):
+            if (mask >> d) & 1:
+                self.fixed[idx, d] = True
 
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -94,7 +107,9 @@ class Fem:
 
     @staticmethod
     def _h_ptrs(H):
-        if H is None:
+        # no contact blocks: H is absent (an empty tensor has no storage, so
+        # its pointer would be null next to a valid row_ptr)
+        if H is None or H.col.numel() == 0:
             return None, None, None
         return _ptr(H.row_ptr), _ptr(H.col), _ptr(H.val)
 

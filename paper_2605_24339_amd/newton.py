@@ -8,8 +8,13 @@ function whose gradient and Hessian the assembly returned.
     E(x) = 1/2 |x - x_tilde|^2_M / dt^2 + 1/2 (x - X)^T K (x - X) + Psi_GMCP(x)
 
 The tactile surface (slave) is a boundary of the body; the indenter
-(master) is prescribed for the step.  Dirichlet vertices move to their
-prescribed positions at the start of the step and stay there.
+(master) is prescribed for the step (kinematic master).  With a contact
+context that is not kinematic, two bodies meet: the positions hold the
+slave body's vertices first, then the master body's, which is the
+contact's own vertex numbering, so its gradient and Hessian act on both
+bodies unchanged.  An optional constant external load f adds -f . x.
+Held components (Dirichlet vertices, rollers) move to their prescribed
+values at the start of the step and stay there.
 
 Every step runs on the GPU library: GMCP broad phase / assembly / step
 bound (gmcp.h), FEM energy / gradient and the PCG solve (gmcp_fem.h); this
@@ -42,9 +47,14 @@ class ImplicitSolver:
     """Newton solver for one body (slave) against a prescribed indenter."""
 
     def __init__(self, fem, contact, f_ref: float, tol: float = 1e-6, max_newton: int = 60,
-                 armijo: float = 1e-4, cg_rtol: float = 1e-3, cg_max: int = 20000):
+                 armijo: float = 1e-4, cg_rtol: float = 1e-3, cg_max: int = 20000, f_ext=None):
         self.fem = fem
-        self.contact = contact      # gmcp Context, float64, kinematic master, slave = body vertices
+        # gmcp Context, float64; kinematic master: slave = body vertices;
+        # otherwise slave body then master body (Vs + Vm = body vertices)
+        self.contact = contact
+        self.two_body = not contact.kinematic
+        self.Vs = contact.Vs
+        self.f_ext = f_ext
         self.f_ref = f_ref
         self.tol = tol
         self.max_newton = max_newton
@@ -53,12 +63,28 @@ class ImplicitSolver:
         self.cg_max = cg_max
 
     # -------------------------------------------------------------- pieces
+    def _sm(self, x, xm):
+        """(slave, master) positions of the contact."""
+        return (x[:self.Vs], x[self.Vs:]) if self.two_body else (x, xm)
+
+    def _ccd(self, x, xm, d) -> float:
+        d = d.contiguous()
+        if self.two_body:
+            a = self.contact.ccd_step(x[:self.Vs], x[self.Vs:], d[:self.Vs], d[self.Vs:])
+        else:
+            a = self.contact.ccd_step(x, xm, d)
+        return float(a.min().item())
+
+    def _ext(self, x) -> float:
+        return 0.0 if self.f_ext is None else -float((self.f_ext * x).sum().item())
+
     def energy(self, x, x_tilde, xm) -> float:
         """Incremental potential with the contact samples re-selected at x."""
         e_fem, _ = self.fem.energy(x, x_tilde, grad=False)
-        self.contact.broadphase(x, xm)
-        A = self.contact.assemble(x, xm, grad=False, hessian=False)
-        return float(e_fem.item() + A.energy.sum().item())
+        s, m = self._sm(x, xm)
+        self.contact.broadphase(s, m)
+        A = self.contact.assemble(s, m, grad=False, hessian=False)
+        return float(e_fem.item() + A.energy.sum().item()) + self._ext(x)
 
     def model_energy(self, x, x_tilde, xm) -> float:
         """Incremental potential with the contact samples of the last
@@ -66,24 +92,28 @@ class ImplicitSolver:
         assembly returned, so the Armijo test and the descent direction
         agree."""
         e_fem, _ = self.fem.energy(x, x_tilde, grad=False)
-        return float(e_fem.item() + self.contact.energy_frozen(x, xm).sum().item())
+        return float(e_fem.item() + self.contact.energy_frozen(*self._sm(x, xm)).sum().item()) + self._ext(x)
 
     def gradient_system(self, x, x_tilde, xm):
         e_fem, g = self.fem.energy(x, x_tilde, grad=True)
-        self.contact.broadphase(x, xm)
-        A = self.contact.assemble(x, xm, grad=True, hessian=True)
+        s, m = self._sm(x, xm)
+        self.contact.broadphase(s, m)
+        A = self.contact.assemble(s, m, grad=True, hessian=True)
         g = g + A.grad
+        if self.f_ext is not None:
+            g = g - self.f_ext
         g[self.fem.fixed] = 0.0
-        E = float(e_fem.item() + A.energy.sum().item())
+        E = float(e_fem.item() + A.energy.sum().item()) + self._ext(x)
         return E, g, A.hessian
 
     def feasible_start(self, x_t, y, xm) -> tuple:
         """x_t + alpha (y - x_t), alpha from the contact step bound (free
-        vertices; Dirichlet vertices are set afterwards)."""
+        components; held ones are set afterwards)."""
         d = (y - x_t).contiguous()
-        self.contact.broadphase(x_t, xm)
-        self.contact.assemble(x_t, xm, grad=False, hessian=False)
-        a = float(self.contact.ccd_step(x_t, xm, d).min().item())
+        s, m = self._sm(x_t, xm)
+        self.contact.broadphase(s, m)
+        self.contact.assemble(s, m, grad=False, hessian=False)
+        a = self._ccd(x_t, xm, d)
         return x_t + a * d, a
 
     # ---------------------------------------------------------------- step
@@ -130,8 +160,7 @@ class ImplicitSolver:
             if not slope < 0.0:      # not a descent direction: fall back to steepest descent
                 d = -g / max(gn, 1e-300)
                 slope = float((g * d).sum().item())
-            a = float(self.contact.ccd_step(x, xm, d.contiguous()).min().item())
-            a = min(1.0, a)
+            a = min(1.0, self._ccd(x, xm, d))
             E0 = self.model_energy(x, x_tilde, xm)
             while True:
                 xn = (x + a * d).contiguous()
