@@ -75,14 +75,50 @@ struct NarrowArgs {
   const int32_t *m_opp, *m_vt_off, *m_vt;          // master edge neighbours, vertex adjacency
 };
 
+// Narrow phase: one wave per work tile, kNarrowWaves tiles per block.  The
+// records and pairs of a block are allocated together (wave counts in LDS,
+// one pair of atomics per block), so every wave of a block passes through
+// that allocation exactly once, whatever its tile holds.
+template <typename R> constexpr int narrow_waves() { return sizeof(R) == 4 ? 8 : 4; }
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
-  __shared__ CandL<R> sc[kTilePerBlock][kWave];
-  __shared__ SampL<R> ss[kTilePerBlock][kWave];
+__global__ __launch_bounds__(kWave * 8) void k_narrow(NarrowArgs<R> a) {
+  constexpr int kNW = narrow_waves<R>();
+  __shared__ CandL<R> sc[kNW][kWave];
+  __shared__ SampL<R> ss[kNW][kWave];
+  __shared__ unsigned int alloc_r[kNW], alloc_p[kNW];
+  __shared__ unsigned long long alloc_rb, alloc_pb;
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * kTilePerBlock + w;
-  if (tile_id >= a.n_tiles) return;  // waves are independent: no block barrier below
-  if (a.cand_off[a.Ts] > a.cap_cand) return;
+  if (a.cand_off[a.Ts] > a.cap_cand) return;  // uniform over the grid: no wave reaches a barrier
+  // the block's allocation: every wave calls it once (two block barriers)
+  auto allocate = [&](int nrec, int npair, unsigned long long &rb, unsigned long long &pb) {
+    if (lane == 0) {
+      alloc_r[w] = (unsigned)nrec;
+      alloc_p[w] = (unsigned)npair;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tr = 0, tp = 0;
+      for (int i = 0; i < kNW; ++i) {
+        const unsigned r0 = alloc_r[i], p0 = alloc_p[i];
+        alloc_r[i] = (unsigned)tr;
+        alloc_p[i] = (unsigned)tp;
+        tr += r0;
+        tp += p0;
+      }
+      alloc_rb = tr ? atomicAdd(&a.st->n_active, tr) : 0;
+      alloc_pb = tp ? atomicAdd(&a.st->n_pairs, tp) : 0;
+    }
+    __syncthreads();
+    rb = alloc_rb + alloc_r[w];
+    pb = alloc_pb + alloc_p[w];
+  };
+  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * kNW + w;
+  if (tile_id >= a.n_tiles) {
+    unsigned long long rb, pb;
+    allocate(0, 0, rb, pb);
+    return;
+  }
   const Tile tl = a.tiles[tile_id];
   const EnvInfo &ev = a.env[tl.env];
   const int nq = tl.nq;
@@ -104,6 +140,8 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
         a.tri_roff[T] = 0;
       }
       if (lane == 0) a.tile_E[tile_id] = 0.0;
+      unsigned long long rb, pb;
+      allocate(0, 0, rb, pb);
       return;
     }
   }
@@ -282,12 +320,31 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
       for (int d = 0; d < 3; ++d) a.tri_nrm[3 * (int64_t)T + d] = n[d];
   }
 
-  // ---- selected-sample records (wave prefix + one atomic per wave)
+  // ---- contact pairs: one per distinct master triangle of a slave triangle
+  bool leader = false;
+  int rank = 0;
+  if (sel) {
+    leader = true;
+    for (int i = 0; i < q; ++i)
+      if (ss[w][j * nq + i].M == bM) {
+        leader = false;
+        break;
+      }
+  }
+  const uint64_t leadmask = __ballot(leader);
+  if (leader) {
+    for (int i = 0; i < nq; ++i) {
+      const SampL<R> &o = ss[w][j * nq + i];
+      if (((leadmask >> (j * nq + i)) & 1) && o.M < bM) ++rank;
+    }
+  }
+  const int npair_w = __popcll(leadmask);
+
+  // ---- records and pairs: wave prefixes, one block allocation
   const int nsel = __popcll(selmask);
   const int rpre = __popcll(selmask & ((one << lane) - 1));
-  unsigned long long rbase = 0;
-  if (lane == 0 && nsel) rbase = atomicAdd(&a.st->n_active, (unsigned long long)nsel);
-  rbase = __shfl(rbase, 0, kWave);
+  unsigned long long rbase, pbase;
+  allocate(nsel, npair_w, rbase, pbase);
   const bool rec_ok = rbase + nsel <= (unsigned long long)a.cap_active;
   if (nsel && !rec_ok && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
   if (sel && rec_ok) {
@@ -311,28 +368,6 @@ __global__ __launch_bounds__(kThreads) void k_narrow(NarrowArgs<R> a) {
     a.rec[rbase + rpre] = r;
   }
 
-  // ---- contact pairs: one per distinct master triangle of a slave triangle
-  bool leader = false;
-  int rank = 0;
-  if (sel) {
-    leader = true;
-    for (int i = 0; i < q; ++i)
-      if (ss[w][j * nq + i].M == bM) {
-        leader = false;
-        break;
-      }
-  }
-  const uint64_t leadmask = __ballot(leader);
-  if (leader) {
-    for (int i = 0; i < nq; ++i) {
-      const SampL<R> &o = ss[w][j * nq + i];
-      if (((leadmask >> (j * nq + i)) & 1) && o.M < bM) ++rank;
-    }
-  }
-  const int npair_w = __popcll(leadmask);
-  unsigned long long pbase = 0;
-  if (lane == 0 && npair_w) pbase = atomicAdd(&a.st->n_pairs, (unsigned long long)npair_w);
-  pbase = __shfl(pbase, 0, kWave);
   const bool pair_ok = pbase + npair_w <= (unsigned long long)a.cap_pairs;
   if (npair_w && !pair_ok && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
   const int tri_pre = valid ? __popcll(leadmask & ((one << (j * nq)) - 1)) : 0;
@@ -1609,7 +1644,8 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     if (c->mortar)
       hipLaunchKernelGGL(k_mortar<R>, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
     else
-      hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, kTilePerBlock)), dim3(kThreads), 0, s, na);
+      hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, narrow_waves<R>())), dim3(kWave * narrow_waves<R>()), 0,
+                         s, na);
   }
   prof_mark(c, ST_NARROW, 1);
   hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, s, b.tile_E, b.env, energy);

@@ -21,10 +21,14 @@ template <> __device__ inline float to_float_down<double>(double v) { return __d
 
 // Per-environment minimum of a >= 0 (uint order of non-negative floats is
 // float order).  Waves reduce by shuffles; a block whose waves all hold one
-// environment issues a single atomic.  Every thread of the block must call.
-__device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
+// environment issues a single atomic.  Optionally the waves' counts (wcount,
+// held by lane 0) are summed into *count with one atomic per block.  Every
+// thread of the block must call.
+__device__ inline void env_min(uint32_t *bits, int env, float a, int lane, unsigned long long wcount = 0,
+                               unsigned long long *count = nullptr) {
   __shared__ int wenv[kThreads / kWave];
   __shared__ float wmin[kThreads / kWave];
+  __shared__ unsigned long long wcnt[kThreads / kWave];
   const int w = threadIdx.x / kWave;
   uint64_t vm = __ballot(env >= 0);
   int e0 = vm ? __shfl(env, __ffsll((unsigned long long)vm) - 1, kWave) : -1;
@@ -35,10 +39,16 @@ __device__ inline void env_min(uint32_t *bits, int env, float a, int lane) {
   if (lane == 0) {
     wenv[w] = uniform ? e0 : -1;
     wmin[w] = m;
+    wcnt[w] = wcount;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
   const int nw = blockDim.x / kWave;
+  if (count) {
+    unsigned long long c = 0;
+    for (int v = 0; v < nw; ++v) c += wcnt[v];
+    if (c) atomicAdd(count, c);
+  }
   for (int v = 0; v < nw; ++v) {
     if (wenv[v] < 0) continue;
     float mm = wmin[v];
@@ -352,11 +362,10 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
       }
     }
   }
-  // pair count: wave sum, one atomic
+  // pair count: wave sums, one atomic per block (with the minimum)
   unsigned long long tot = npairs;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
-  if (lane == 0 && tot) atomicAdd(&st->n_swept, tot);
-  env_min(bits, e, amin, lane);
+  env_min(bits, e, amin, lane, tot, &st->n_swept);
 }
 
 template <typename R>
