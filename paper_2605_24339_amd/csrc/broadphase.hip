@@ -479,34 +479,9 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   }
   const int work = __shfl(incl, kWave - 1, kWave);
   const int64_t base = env[e].cell0;
-  // the lane's share of the (slab, cell) work items: fn(slab, cell)
-  auto for_cells = [&](auto &&fn) {
-    for (int w0 = 0; w0 < work; w0 += kWave) {
-      const int wi = w0 + lane;
-      int s = 0;
-      for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
-      s = min(s, kWave - 1);
-      const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
-      const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
-      const int sstart = __shfl(incl - ncs, s, kWave);
-      if (wi >= work) continue;
-      const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
-      const int li = wi - sstart;
-      const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
-      fn(s, base + ((int64_t)zc * g.ny + y) * g.nx + x);
-    }
-  };
-  // items in the visited cells bound the candidates: skip empty prisms and
-  // size the set to the triangle
-  int nitems = 0;
-  for_cells([&](int, int64_t cell) { nitems += cell_start[cell + 1] - cell_start[cell]; });
-  for (int o = 32; o > 0; o >>= 1) nitems += __shfl_xor(nitems, o, kWave);
-  if (nitems == 0) {
-    if (lane == 0) cand_cnt[t] = 0;
-    return;
-  }
-  int tsz = 64;
-  while (tsz < 2 * nitems && tsz < kQuerySet) tsz <<= 1;
+  // the listed triangles' prisms meet occupied cells (k_query_pre): the set
+  // takes its full size, which saves a counting pass over the cells
+  constexpr int tsz = kQuerySet;
   for (int k = lane; k < tsz; k += kWave) set[w][k] = -1;
   wave_sync();
   bool full = false;
