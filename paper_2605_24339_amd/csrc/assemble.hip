@@ -935,26 +935,25 @@ __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full)
   return -1;
 }
 
-// One wave per master triangle with contact pairs: the sum over its pairs
-// (bucket order: sorted by slave triangle) of the master-master sums times
+// Thread per master triangle with contact pairs: the sum over its pairs in
+// bucket order (sorted by slave triangle) of the master-master sums times
 // n_T n_T^T - six vertex pairs (00 01 02 11 12 22) of six symmetric entries -
-// and of the gradient sums gm_j n_T (three vertices).  Lane partials are
-// combined by a fixed butterfly, so the result is the same on every run.
+// and of the gradient sums gm_j n_T (three vertices); a serial sum in that
+// order, so the result is the same on every run.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ pair,
                                                     const int32_t *__restrict__ mp_off,
                                                     const int32_t *__restrict__ mp_list,
                                                     const R *__restrict__ tri_nrm, int64_t Tm, const DevStatus *st,
                                                     int64_t cap_pairs, R *__restrict__ mtri) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t t = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= Tm || (int64_t)st->n_pairs > cap_pairs) return;
   const int b = mp_off[t], e = mp_off[t + 1];
   if (b == e) return;
   R h[36], g[9];
   for (int z = 0; z < 36; ++z) h[z] = 0;
   for (int z = 0; z < 9; ++z) g[z] = 0;
-  for (int i = b + lane; i < e; i += kWave) {
+  for (int i = b; i < e; ++i) {
     const Pair<R> &P = pair[mp_list[i]];
     const R *nn = tri_nrm + 3 * (int64_t)P.T;
     const R n0 = nn[0], n1 = nn[1], n2 = nn[2];
@@ -967,15 +966,9 @@ __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ p
       g[3 * m + 2] += P.gm[m] * n2;
     }
   }
-  for (int z = 0; z < 36; ++z)
-    for (int o = 32; o > 0; o >>= 1) h[z] += __shfl_xor(h[z], o, kWave);
-  for (int z = 0; z < 9; ++z)
-    for (int o = 32; o > 0; o >>= 1) g[z] += __shfl_xor(g[z], o, kWave);
-  if (lane == 0) {
-    R *out = mtri + 45 * t;
-    for (int z = 0; z < 36; ++z) out[z] = h[z];
-    for (int z = 0; z < 9; ++z) out[36 + z] = g[z];
-  }
+  R *out = mtri + 45 * t;
+  for (int z = 0; z < 36; ++z) out[z] = h[z];
+  for (int z = 0; z < 9; ++z) out[36 + z] = g[z];
 }
 
 // Thread per BSR row: counts the row's contributions (the entries the row
@@ -1064,12 +1057,17 @@ constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows
 constexpr int kRowSrc = kWave;   // incident triangles of a slave row kept in LDS
 
 // LDS bytes of one wave of k_rows: hash set and dense list (slots each),
-// the incident-triangle table, and in PASS 1 the contribution stash and the
-// incident triangles' normals
+// the incident-triangle table, and in PASS 1 the contribution stash - in
+// groups of three (a triangle's own vertices, or one pair's master
+// vertices: three distinct columns, the table index, three coefficients) -
+// and the incident triangles' normals; a multiple of 16 bytes
 template <typename R>
 constexpr size_t row_lds_wave(int slots, int pass, bool heavy) {
-  return (size_t)slots * 8 + (size_t)5 * kRowSrc * 4 +
-         (pass == 1 ? (size_t)(heavy ? kRowEnt : kLightEnt) * (8 + sizeof(R)) + (size_t)kRowSrc * 3 * sizeof(R) : 0);
+  return ((size_t)slots * 8 + (size_t)8 * kRowSrc * 4 +
+          (pass == 1 ? (size_t)((heavy ? kRowEnt : kLightEnt) / 3 + 1) * (16 + 3 * sizeof(R)) +
+                           (size_t)kRowSrc * 3 * sizeof(R)
+                     : 0) +
+          15) / 16 * 16;
 }
 
 template <typename R, int PASS, bool HEAVY>  // HEAVY: the heavy-row list (large LDS tables), same code
@@ -1087,10 +1085,11 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   int32_t *stt = seo + kRowSrc;
   int32_t *sco = stt + kRowSrc;
   int32_t *spb = sco + kRowSrc;
-  int32_t *ecol = spb + kRowSrc;  // PASS 1 stash: column, table index, coef
-  int32_t *esrc = ecol + ecap;
-  R *ecoef = reinterpret_cast<R *>(esrc + ecap);
-  R *snrm = ecoef + ecap;  // normals of the table's triangles
+  int32_t *stv = spb + kRowSrc;  // master rows: the triangle's three vertex ids
+  constexpr int gcap = ecap / 3 + 1;
+  int4 *egrp = reinterpret_cast<int4 *>(stv + 3 * kRowSrc);  // PASS 1 stash: three columns + table index,
+  R *ecoef = reinterpret_cast<R *>(egrp + gcap);          // three coefficients per group
+  R *snrm = ecoef + 3 * gcap;                             // normals of the table's triangles
   if ((pass == 1 || pass == 3) && (int64_t)a.row_ptr[a.V] > a.cap_nnzb) return;
   // the waves walk the list of rows with contributions (k_row_pre)
   const int64_t nlist = *rcount;
@@ -1128,15 +1127,19 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
 
   if (!slave) {
     // ------------------------------------------------------ master row
-    if (pass != 0 && a.grad && lane == 0) {
+    if (pass != 0 && a.grad) {
+      // gradient row: lane partials over the incident triangles, fixed-order butterfly
       R gr[3] = {0, 0, 0};
-      for (int src = sb; src < se; ++src) {
+      for (int src = sb + lane; src < se; src += kWave) {
         const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
         if (a.mp_off[t] == a.mp_off[t + 1]) continue;
         const R *G = a.mtri + 45 * (int64_t)t + 36 + 3 * corner;
         for (int d = 0; d < 3; ++d) gr[d] += G[d];
       }
-      for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = gr[d];
+      for (int d = 0; d < 3; ++d)
+        for (int o = 32; o > 0; o >>= 1) gr[d] += __shfl_xor(gr[d], o, kWave);
+      if (lane == 0)
+        for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = gr[d];
     }
     if (pass == 2) return;
     int n_ent = 0;
@@ -1155,14 +1158,49 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     for (int i = lane; i < tsz; i += kWave) key[i] = -1;
     wave_sync();
     bool full = false;
-    for (int src = sb; src < se; ++src) {
-      const int t = a.m_vt[src] >> 2;
-      const int pb = a.mp_off[t], pe = a.mp_off[t + 1];
-      if (pb == pe) continue;
-      if (lane < 3) row_slot(key, tsz, (int32_t)(a.Vs + a.tm[3 * (int64_t)t + lane]), &full);
-      for (int i = pb + lane; i < pe; i += kWave) {
-        const int64_t T = a.mp_key[i] >> 32;
-        for (int s = 0; s < 3; ++s) row_slot(key, tsz, a.ts[3 * T + s], &full);
+    // (incident triangle, item) pairs over the lanes: item 0 = the triangle's
+    // three master vertices, item 1 + i = the slave vertices of its pair i
+    const bool one_chunk = se - sb <= kRowSrc;
+    for (int s0 = sb; s0 < se; s0 += kRowSrc) {
+      const int src = s0 + lane;
+      int t = 0, corner = 0, np = 0, pb = 0, tv[3] = {0, 0, 0};
+      if (src < se) {
+        const int ent = a.m_vt[src];
+        t = ent >> 2;
+        corner = ent & 3;
+        pb = a.mp_off[t];
+        np = a.mp_off[t + 1] - pb;
+        if (np > 0)
+          for (int m = 0; m < 3; ++m) tv[m] = a.tm[3 * (int64_t)t + m];
+      }
+      const int nit = np > 0 ? 1 + np : 0;
+      int iin = nit;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int vi = __shfl_up(iin, d, kWave);
+        if (lane >= d) iin += vi;
+      }
+      const int items = __shfl(iin, kWave - 1, kWave);
+      wave_sync();  // the previous chunk's table reads are done
+      sip[lane] = iin - nit;
+      stt[lane] = np > 0 ? t : -1;  // -1: no pairs (no contribution)
+      sco[lane] = corner;
+      spb[lane] = pb;
+      for (int m = 0; m < 3; ++m) stv[3 * lane + m] = tv[m];
+      wave_sync();
+      for (int f = lane; f < items; f += kWave) {
+        int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sip[mid] <= f) lo = mid;
+          else hi = mid - 1;
+        }
+        const int j = f - sip[lo];
+        if (j == 0) {
+          for (int m = 0; m < 3; ++m) row_slot(key, tsz, (int32_t)(a.Vs + stv[3 * lo + m]), &full);
+        } else {
+          const int64_t T = a.mp_key[spb[lo] + j - 1] >> 32;
+          for (int q = 0; q < 3; ++q) row_slot(key, tsz, a.ts[3 * T + q], &full);
+        }
       }
     }
     if (__any(full)) {
@@ -1195,13 +1233,25 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       a.col[dst] = c;
       if (c < a.Vs) continue;  // slave column: PASS 3
       R v[6] = {0, 0, 0, 0, 0, 0};
-      for (int src = sb; src < se; ++src) {
-        const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
-        if (a.mp_off[t] == a.mp_off[t + 1]) continue;
-        for (int m = 0; m < 3; ++m) {
-          if ((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]) != c) continue;
-          const R *B = a.mtri + 45 * (int64_t)t + 6 * sym3(corner, m);
-          for (int z = 0; z < 6; ++z) v[z] += B[z];
+      if (one_chunk) {  // the incident triangles are in the table, in adjacency order
+        for (int k = 0; k < se - sb; ++k) {
+          const int t = stt[k];
+          if (t < 0) continue;
+          for (int m = 0; m < 3; ++m) {
+            if ((int32_t)(a.Vs + stv[3 * k + m]) != c) continue;
+            const R *B = a.mtri + 45 * (int64_t)t + 6 * sym3(sco[k], m);
+            for (int z = 0; z < 6; ++z) v[z] += B[z];
+          }
+        }
+      } else {
+        for (int src = sb; src < se; ++src) {
+          const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
+          if (a.mp_off[t] == a.mp_off[t + 1]) continue;
+          for (int m = 0; m < 3; ++m) {
+            if ((int32_t)(a.Vs + a.tm[3 * (int64_t)t + m]) != c) continue;
+            const R *B = a.mtri + 45 * (int64_t)t + 6 * sym3(corner, m);
+            for (int z = 0; z < 6; ++z) v[z] += B[z];
+          }
         }
       }
       R *ov = a.val + 9 * dst;
@@ -1264,12 +1314,13 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   wave_sync();
   const bool stash = pass == 1 && n_ent <= ecap && se - sb <= kRowSrc;
   bool full = false;
-  auto put = [&](int32_t col, R cf, int e, int k) {
-    if (row_slot(key, tsz, col, &full) < 0) return;
+  // one group of three contributions starting at canonical offset e0 (a multiple of 3)
+  auto put3 = [&](const int32_t col[3], const R cf[3], int e0, int k) {
+    for (int b = 0; b < 3; ++b) row_slot(key, tsz, col[b], &full);
     if (stash) {
-      ecol[e] = col;
-      esrc[e] = k;
-      ecoef[e] = cf;
+      const int gi = e0 / 3;
+      egrp[gi] = make_int4(col[0], col[1], col[2], k);
+      for (int b = 0; b < 3; ++b) ecoef[3 * gi + b] = cf[b];
     }
   };
   int run = 0;  // contributions of the earlier chunks of incident triangles
@@ -1311,14 +1362,22 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
         else hi = mid - 1;
       }
       const int j = f - sip[lo], tt = stt[lo], c = sco[lo];
+      int32_t col[3];
+      R cf[3];
       if (j == 0) {  // the triangle's own vertices
         const R *S = a.tri_sum + 9 * (int64_t)tt;
-        for (int b = 0; b < 3; ++b) put(a.ts[3 * (int64_t)tt + b], S[sym3(c, b)], seo[lo] + b, lo);
+        for (int b = 0; b < 3; ++b) {
+          col[b] = a.ts[3 * (int64_t)tt + b];
+          cf[b] = S[sym3(c, b)];
+        }
+        put3(col, cf, seo[lo], lo);
       } else {  // pair j - 1 of the triangle: its master vertices
         const Pair<R> &P = a.pair[spb[lo] + j - 1];
-        const int e0 = seo[lo] + 3 + 3 * (j - 1);
-        for (int m = 0; m < 3; ++m)
-          put((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * c + m], e0 + m, lo);
+        for (int m = 0; m < 3; ++m) {
+          col[m] = (int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]);
+          cf[m] = P.sm[3 * c + m];
+        }
+        put3(col, cf, seo[lo] + 3 + 3 * (j - 1), lo);
       }
     }
     run += ents;
@@ -1358,9 +1417,12 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       v[4] += cf * nn[1] * nn[2];
       v[5] += cf * nn[2] * nn[2];
     };
-    if (stash) {
-      for (int e = 0; e < n_ent; ++e)
-        if (ecol[e] == c) add_n(ecoef[e], snrm + 3 * esrc[e]);
+    if (stash) {  // the three columns of a group are distinct: at most one matches
+      for (int gi = 0; gi < n_ent / 3; ++gi) {
+        const int4 cg = egrp[gi];
+        const int b = cg.x == c ? 0 : (cg.y == c ? 1 : (cg.z == c ? 2 : -1));
+        if (b >= 0) add_n(ecoef[3 * gi + b], snrm + 3 * cg.w);
+      }
     } else {
       for (int src = sb; src < se; ++src)
         visit_src(src, [&](int32_t col, R cf, int t) {
@@ -1667,7 +1729,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const int nw = kRowWaves;
   if (!c->kinematic && (grad || H) && c->Tm) {
     prof_mark(c, ST_MTRI, 0);
-    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads / kWave)), dim3(kThreads), 0, s, pr, b.mp_off,
+    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads)), dim3(kThreads), 0, s, pr, b.mp_off,
                        b.mp_list, (const R *)b.tri_nrm, c->Tm, b.status, c->caps.pairs, (R *)b.mtri);
     prof_mark(c, ST_MTRI, 1);
   }
