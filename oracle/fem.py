@@ -208,7 +208,8 @@ def newton_step(body: Body, P_of, x_t, v_t, fixed_pos, kappa, dhat, rule_n, xm, 
             Efn, _ = body.fem_energy_grad(xn, x_tilde)
             En = Efn - float(np.sum(f_ext * xn)) + frozen(P, nr, A, xn)
             stats["energy_evals"] += 1
-            if En <= E0 + armijo * alpha * slope or alpha < 1e-14:
+            # Armijo, or a change below the energy's double-precision resolution
+            if En <= E0 + armijo * alpha * slope or abs(En - E0) <= 64 * 2.2e-16 * abs(E0) or alpha < 1e-14:
                 break
             alpha *= 0.5
         x = xn

@@ -166,7 +166,10 @@ class ImplicitSolver:
                 xn = (x + a * d).contiguous()
                 En = self.model_energy(xn, x_tilde, xm)
                 st.energy_evals += 1
-                if En <= E0 + self.armijo * a * slope or a < 1e-14:
+                # Armijo, or a change below the energy's double-precision
+                # resolution (near convergence the decrease is smaller than
+                # the rounding of E, and the test cannot be decided)
+                if En <= E0 + self.armijo * a * slope or abs(En - E0) <= 64 * 2.2e-16 * abs(E0) or a < 1e-14:
                     break
                 a *= 0.5
             st.alphas.append(a)

@@ -28,9 +28,10 @@ def test_matching_meshes_carry_the_uniform_stress():
     assert all(s["residual"] <= 1e-10 for s in st)
     zz, spur = stress_errors(pt, x)
     assert zz <= 1e-8 and spur <= 1e-8 * pt.pressure
-    # the gap is uniform and balances the pressure
+    # the gap is uniform (to the solve's resolution: |grad E| <= 1e-10 E h^2
+    # fixes positions to about that over the stiffness E h) and balances the pressure
     gaps = x[:pt.Vs][pt.ts][:, :, 2].ravel().min(), x[:pt.Vs][pt.ts][:, :, 2].ravel().max()
-    assert gaps[1] - gaps[0] <= 1e-12
+    assert gaps[1] - gaps[0] <= 1e-10
     g = x[:pt.Vs][pt.ts][:, :, 2].min() - x[pt.Vs:][pt.tm][:, :, 2].max()
     eps = pt.dhat
     B = lambda t: -(t - eps) ** 2 * math.log(t / eps)
