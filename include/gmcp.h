@@ -236,6 +236,27 @@ int gmcp_ccd_step(gmcp_ctx *ctx, const void *x_slave, const void *x_master, cons
                   const void *dx_master, void *alpha);
 
 /*
+ * The same step bound in two calls, so that its part that does not depend
+ * on the assembly can run on another stream while the broad phase and the
+ * assembly run (Eqs. (ccd), (global_ccd)):
+ *   gmcp_ccd_swept   swept grid and additive CCD over every swept pair
+ *                    (needs only gmcp_build_samples); starts a new bound;
+ *   gmcp_ccd_finish  Eq. (ccd) over the active samples of the last assembly,
+ *                    then alpha [n_env] exactly as gmcp_ccd_step writes it.
+ * Same arguments as gmcp_ccd_step (dx_master NULL = static master).  The
+ * caller orders the two on the device: gmcp_ccd_finish's stream must wait
+ * for the work gmcp_ccd_swept enqueued (an event, or the same stream), and
+ * for the assembly.  gmcp_ccd_swept uses its own scan scratch and grid, so
+ * it may overlap gmcp_broadphase and gmcp_assemble of the same context on a
+ * second stream; it must not overlap another step-bound call.
+ * gmcp_ccd_finish returns GMCP_E_ARG unless gmcp_ccd_swept was called since
+ * the last bound (host order) and an assembly exists.
+ */
+int gmcp_ccd_swept(gmcp_ctx *ctx, const void *x_slave, const void *x_master, const void *dx_slave,
+                   const void *dx_master);
+int gmcp_ccd_finish(gmcp_ctx *ctx, const void *dx_slave, const void *dx_master, void *alpha);
+
+/*
  * Joint Hessian-vector product of E(x, delta) with the samples of the last
  * assembly frozen:  [out_x; out_d] = sum_k c2_k (grad g_k . v_x + v_d[k]) [grad g_k; e_k].
  * v_x, out_x [V][3]; v_d, out_d [Ns] nullable.  Deterministic.

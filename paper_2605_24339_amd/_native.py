@@ -46,7 +46,7 @@ class Bsr(C.Structure):
 
 EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_stream",
            "gmcp_build_samples", "gmcp_num_samples", "gmcp_broadphase", "gmcp_assemble",
-           "gmcp_ccd_step", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
+           "gmcp_ccd_step", "gmcp_ccd_swept", "gmcp_ccd_finish", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
            "gmcp_strerror", "gmcp_profile", "gmcp_profile_stages", "gmcp_profile_stage_name",
            "gmcp_profile_read", "gmcp_rule", "gmcp_row_classes"]
 # include/gmcp_mlp.h
@@ -93,6 +93,10 @@ def lib():
         L.gmcp_assemble.argtypes = [P, P, P, P, P, P, P, C.POINTER(Bsr)]
         L.gmcp_ccd_step.restype = C.c_int
         L.gmcp_ccd_step.argtypes = [P, P, P, P, P, P]
+        L.gmcp_ccd_swept.restype = C.c_int
+        L.gmcp_ccd_swept.argtypes = [P, P, P, P, P]
+        L.gmcp_ccd_finish.restype = C.c_int
+        L.gmcp_ccd_finish.argtypes = [P, P, P, P]
         L.gmcp_hvp.restype = C.c_int
         L.gmcp_hvp.argtypes = [P, P, P, P, P]
         L.gmcp_energy_frozen.restype = C.c_int

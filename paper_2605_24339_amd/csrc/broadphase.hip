@@ -630,7 +630,7 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
     hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr,
                        c->tm, c->Tm, mbox, b.m_env, b.env, grid, cnt);
   }
-  hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1);
+  hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1, swept);
   if (e != hipSuccess) return e;
   if (c->Tm)
     hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,

@@ -382,7 +382,7 @@ __global__ void k_alpha_final(const uint32_t *bits, int n_env, R *alpha) {
 }  // namespace
 
 template <typename R>
-hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha) {
+hipError_t launch_ccd_swept(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm) {
   Buffers &b = c->b;
   hipStream_t s = c->stream;
   StageInit si;
@@ -391,33 +391,51 @@ hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   si.alpha = b.alpha_bits;
   hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
-  const R *dm = dxm;
-  prof_mark(c, ST_CCD_LINEAR, 0);
-  if (c->n_tiles)
-    hipLaunchKernelGGL(k_ccd_linear<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
-                       dim3(kThreads), 0, s,
-                       (const Rec<R> *)b.rec, b.status, c->caps.active, b.tiles, (int)c->n_tiles, b.s_order,
-                       b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, c->ts, c->tm, b.env, b.rule, dxs, dm,
-                       b.alpha_bits);
-  prof_mark(c, ST_CCD_LINEAR, 1);
   prof_mark(c, ST_CCD_GRID, 0);
-  e = build_grid<R>(c, xs, xm, dxs, dm, true);
+  e = build_grid<R>(c, xs, xm, dxs, dxm, true);
   prof_mark(c, ST_CCD_GRID, 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_CCD_ACCD, 0);
   if (c->n_tiles)
     hipLaunchKernelGGL(k_ccd_accd<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
-                       dim3(kThreads), 0, s, xs, xm, dxs, dm, c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order,
+                       dim3(kThreads), 0, s, xs, xm, dxs, dxm, c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order,
                        b.env, b.rule, b.sgrid, b.scell_start, b.sitems, b.smbox, c->caps.grid_items, c->total_cells,
                        b.alpha_bits, b.status);
   prof_mark(c, ST_CCD_ACCD, 1);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_ccd_finish(gmcp_ctx *c, const R *dxs, const R *dxm, R *alpha) {
+  Buffers &b = c->b;
+  hipStream_t s = c->stream;
+  prof_mark(c, ST_CCD_LINEAR, 0);
+  if (c->n_tiles)
+    hipLaunchKernelGGL(k_ccd_linear<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
+                       dim3(kThreads), 0, s,
+                       (const Rec<R> *)b.rec, b.status, c->caps.active, b.tiles, (int)c->n_tiles, b.s_order,
+                       b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, c->ts, c->tm, b.env, b.rule, dxs, dxm,
+                       b.alpha_bits);
+  prof_mark(c, ST_CCD_LINEAR, 1);
   hipLaunchKernelGGL(k_alpha_final<R>, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.alpha_bits, c->n_env, alpha);
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha) {
+  hipError_t e = launch_ccd_swept<R>(c, xs, xm, dxs, dxm);
+  if (e != hipSuccess) return e;
+  return launch_ccd_finish<R>(c, dxs, dxm, alpha);
 }
 
 template hipError_t launch_ccd<float>(gmcp_ctx *, const float *, const float *, const float *, const float *,
                                       float *);
 template hipError_t launch_ccd<double>(gmcp_ctx *, const double *, const double *, const double *, const double *,
                                        double *);
+template hipError_t launch_ccd_swept<float>(gmcp_ctx *, const float *, const float *, const float *, const float *);
+template hipError_t launch_ccd_swept<double>(gmcp_ctx *, const double *, const double *, const double *,
+                                             const double *);
+template hipError_t launch_ccd_finish<float>(gmcp_ctx *, const float *, const float *, float *);
+template hipError_t launch_ccd_finish<double>(gmcp_ctx *, const double *, const double *, double *);
 
 }  // namespace gmcp

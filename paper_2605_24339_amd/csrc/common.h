@@ -113,6 +113,7 @@ struct Buffers {
   void *hv_pair;                                // [pairs][3] R
   // scan scratch
   int32_t *scan_tmp;
+  int32_t *scan_tmp2;                           // the swept grid's scans (second stream)
   DevStatus *status;
 };
 
@@ -159,6 +160,7 @@ struct gmcp_ctx {
   const int32_t *ts, *tm;
   std::vector<gmcp::EnvInfo> henv;
   bool samples_built, broadphase_done, assembled;
+  bool swept_ready;  // gmcp_ccd_swept enqueued, gmcp_ccd_finish not yet
   gmcp::Buffers b;
   size_t scan_tmp_elems;
 };
@@ -167,7 +169,9 @@ namespace gmcp {
 
 // ------------------------------------------------------------ launchers
 // each returns hipSuccess or the launch error
-hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n);
+// side = true uses the second scratch (the swept grid's scans may run on
+// another stream, concurrently with the broad phase and assembly)
+hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side = false);
 hipError_t fill_i32(gmcp_ctx *c, int32_t *p, int32_t v, int64_t n);
 // one launch for a stage's scalar set-up: the status fields of the stage
 // (which: 1 broad phase, 2 assembly, 4 step bound), empty boxes and +inf
@@ -194,6 +198,12 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
                            R *energy, R *grad, const gmcp_bsr *H);
 template <typename R>
 hipError_t launch_ccd(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm, R *alpha);
+// the step bound in two parts: swept grid + additive CCD (needs only the
+// samples), then Eq. (ccd) over the assembled samples + the final bound
+template <typename R>
+hipError_t launch_ccd_swept(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const R *dxm);
+template <typename R>
+hipError_t launch_ccd_finish(gmcp_ctx *c, const R *dxs, const R *dxm, R *alpha);
 template <typename R>
 hipError_t launch_hvp(gmcp_ctx *c, const R *vx, const R *vd, R *ox, R *od);
 template <typename R>

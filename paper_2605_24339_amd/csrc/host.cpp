@@ -230,6 +230,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   int64_t nmax = std::max<int64_t>({s.Ts + 1, s.Tm + 1, s.V + 1, cp.grid_cells + 1, 1});
   size_t se = (size_t)(2 * (nmax / 1024 + 2) + 2 * 1024 + 64);
   t.scan_tmp = p.take<int32_t>((int64_t)se);
+  t.scan_tmp2 = p.take<int32_t>((int64_t)se);
   if (scan_elems) *scan_elems = se;
   if (b) *b = t;
   return p.off + 256;
@@ -324,6 +325,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->samples_built = false;
   c->broadphase_done = false;
   c->assembled = false;
+  c->swept_ready = false;
   plan_workspace(s, *caps, (char *)workspace, &c->b, &c->scan_tmp_elems);
 
   // ---- topology back to the host
@@ -582,6 +584,24 @@ int gmcp_ccd_step(gmcp_ctx *c, const void *xs, const void *xm, const void *dxs, 
                                              (const double *)dxm, (double *)alpha)
                         : launch_ccd<float>(c, (const float *)xs, (const float *)xm, (const float *)dxs,
                                             (const float *)dxm, (float *)alpha);
+  return fail(c, e);
+}
+
+int gmcp_ccd_swept(gmcp_ctx *c, const void *xs, const void *xm, const void *dxs, const void *dxm) {
+  if (!c || !xs || (c->Tm > 0 && !xm) || !dxs || !c->samples_built) return GMCP_E_ARG;
+  hipError_t e = c->f64 ? launch_ccd_swept<double>(c, (const double *)xs, (const double *)xm, (const double *)dxs,
+                                                   (const double *)dxm)
+                        : launch_ccd_swept<float>(c, (const float *)xs, (const float *)xm, (const float *)dxs,
+                                                  (const float *)dxm);
+  c->swept_ready = e == hipSuccess;
+  return fail(c, e);
+}
+
+int gmcp_ccd_finish(gmcp_ctx *c, const void *dxs, const void *dxm, void *alpha) {
+  if (!c || !dxs || !alpha || !c->assembled || !c->swept_ready) return GMCP_E_ARG;
+  c->swept_ready = false;
+  hipError_t e = c->f64 ? launch_ccd_finish<double>(c, (const double *)dxs, (const double *)dxm, (double *)alpha)
+                        : launch_ccd_finish<float>(c, (const float *)dxs, (const float *)dxm, (float *)alpha);
   return fail(c, e);
 }
 

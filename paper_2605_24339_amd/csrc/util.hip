@@ -112,7 +112,8 @@ __global__ void k_stage_init(DevStatus *st, StageInit a, int n_env) {
 
 }  // namespace
 
-hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n) {
+hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side) {
+  int32_t *const scratch = side ? c->b.scan_tmp2 : c->b.scan_tmp;
   // levels: out <- scan(in); block sums in tmp, scanned recursively in place
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb <= 0) return hipSuccess;
@@ -122,17 +123,16 @@ hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t 
   }
   if (nb <= kScanTop) {  // two launches: block scans + totals, then each block's offset
     if (nb > (int64_t)c->scan_tmp_elems) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, in, out, c->b.scan_tmp,
-                       n);
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, in, out, scratch, n);
     hipLaunchKernelGGL(k_scan_add_top, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, out,
-                       (const int32_t *)c->b.scan_tmp, n);
+                       (const int32_t *)scratch, n);
     return hipGetLastError();
   }
   // the scratch holds every level's block sums back to back
   int32_t *lvl_in[8], *lvl_out[8];
   int64_t lvl_n[8];
   int depth = 0;
-  int32_t *tmp = c->b.scan_tmp;
+  int32_t *tmp = scratch;
   int64_t used = 0;
   int64_t cur = n;
   const int32_t *src = in;

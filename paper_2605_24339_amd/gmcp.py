@@ -80,6 +80,8 @@ class Context:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         self.kinematic = bool(kinematic)
+        self._side = None          # second stream of the overlapped step (created on first use)
+        self._profiling = False
         self.mortar = bool(mortar) or bool(features)
         self.features = bool(features)
         self.ts = torch.as_tensor(slave_tri, dtype=torch.int32).to(self.device).contiguous()
@@ -272,12 +274,46 @@ class Context:
             self.assemble(xs, xm, grad=False, hessian=False)
         raise GMCPError(N.GMCP_E_CAPACITY, -1, "gmcp_ccd_step: capacities did not settle")
 
+    def ccd_swept(self, xs, xm, dxs, dxm=None):
+        """First part of the step bound (swept grid + additive CCD) on the
+        current stream; no capacity check (see ``step``)."""
+        xs = self._x(xs, self.Vs, "x_slave")
+        xm = self._x(xm, self.Vm, "x_master")
+        dxs = self._x(dxs, self.Vs, "dx_slave")
+        dxm = self._x(dxm, self.Vm, "dx_master")
+        self._bind()
+        _check(N.lib().gmcp_ccd_swept(self._ctx, _ptr(xs), _ptr(xm), _ptr(dxs), _ptr(dxm)), "gmcp_ccd_swept")
+
+    def ccd_finish(self, dxs, dxm=None) -> torch.Tensor:
+        """Second part of the step bound (Eq. (ccd) over the assembled samples)."""
+        dxs = self._x(dxs, self.Vs, "dx_slave")
+        dxm = self._x(dxm, self.Vm, "dx_master")
+        self._bind()
+        _check(N.lib().gmcp_ccd_finish(self._ctx, _ptr(dxs), _ptr(dxm), _ptr(self.alpha)), "gmcp_ccd_finish")
+        return self.alpha
+
     def step(self, xs, xm, dxs, dxm=None, check: bool = False):
         """One pass of the whole hot path: broad phase, assembly (energy,
-        gradient, BSR Hessian), step bound."""
-        self.broadphase(xs, xm, check=check)
-        A = self.assemble(xs, xm, check=check)
-        alpha = self.ccd_step(xs, xm, dxs, dxm, check=check)
+        gradient, BSR Hessian), step bound.  Unchecked and not profiled, the
+        step bound's swept part (grid + additive CCD, independent of the
+        assembly) runs on a second stream, forked from and joined back into
+        the current one, so it overlaps the broad phase and the assembly (also
+        inside a captured graph)."""
+        if check or self._profiling:
+            self.broadphase(xs, xm, check=check)
+            A = self.assemble(xs, xm, check=check)
+            alpha = self.ccd_step(xs, xm, dxs, dxm, check=check)
+            return A, alpha
+        main = torch.cuda.current_stream(self.device)
+        if self._side is None:
+            self._side = torch.cuda.Stream(self.device)  # default priority
+        self._side.wait_stream(main)
+        with torch.cuda.stream(self._side):
+            self.ccd_swept(xs, xm, dxs, dxm)
+        self.broadphase(xs, xm, check=False)
+        A = self.assemble(xs, xm, check=False)
+        main.wait_stream(self._side)
+        alpha = self.ccd_finish(dxs, dxm)
         return A, alpha
 
     def capture(self, xs, xm, dxs, dxm=None) -> "torch.cuda.CUDAGraph":
@@ -344,8 +380,10 @@ class Context:
         return off, cand[:n]
 
     def profile(self, enable: bool = True):
-        """Start (clears) or stop per-stage HIP-event timing on this context's stream."""
+        """Start (clears) or stop per-stage HIP-event timing on this context's
+        stream (steps then run their stages in order on one stream)."""
         _check(N.lib().gmcp_profile(self._ctx, int(enable)), "gmcp_profile")
+        self._profiling = bool(enable)
 
     def profile_read(self) -> dict:
         """{stage: (total_ms, occurrences)} since the last profile(True); synchronises."""

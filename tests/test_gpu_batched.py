@@ -3,6 +3,9 @@
 * A captured step replayed several times, with eager library work and
   synchronisations between replays, equals the eager step bit for bit on
   every replay, also after the inputs change in place.
+* The step bound split in two calls (swept part on a second stream,
+  overlapping the broad phase and assembly) equals the one-call step bound
+  bit for bit; the second call without the first is rejected.
 * The 256-environment batch (uneven pads, rules, indenters) runs in one
   launch sequence; sampled environments match the FP64 oracle (energy,
   gradient, step bound, selection outside the ambiguity band).
@@ -66,6 +69,32 @@ def test_graph_replay_matches_eager():
     rep = _snapshot(ctx, nn2)
     ctx.step(xs, xm, dxs, dxm, check=True)
     assert _same(_snapshot(ctx, nn2), rep)
+
+
+def test_overlapped_step_bound_matches_sequential():
+    need_gpu()
+    from paper_2605_24339_amd import GMCPError, _native
+    from gpu_helpers import make_ctx
+    w = workloads.large_indent()
+    ctx = make_ctx(w, torch.float32)
+    xs, xm = to_dev(w.xs, torch.float32), to_dev(w.xm, torch.float32)
+    dxs, dxm = to_dev(w.dxs, torch.float32), to_dev(w.dxm, torch.float32)
+    ctx.build_samples(xs)
+    ctx.step(xs, xm, dxs, dxm, check=True)          # sequential, one-call step bound
+    torch.cuda.synchronize()
+    nnzb = int(ctx.status().nnzb)
+    seq = _snapshot(ctx, nnzb)
+    n_swept = int(ctx.status().n_swept)
+    for _ in range(3):
+        ctx.alpha.fill_(-1.0)
+        ctx.step(xs, xm, dxs, dxm)                  # overlapped: swept part on the side stream
+        torch.cuda.synchronize()
+        st = ctx.status()
+        assert st.code == 0 and int(st.nnzb) == nnzb and int(st.n_swept) == n_swept
+        assert _same(_snapshot(ctx, nnzb), seq)
+    with pytest.raises(GMCPError) as e:             # finish without a swept part
+        ctx.ccd_finish(dxs, dxm)
+    assert e.value.code == _native.GMCP_E_ARG
 
 
 def test_batch_256_envs_sampled_parity():
