@@ -1727,12 +1727,29 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   RowArgs<R> ra = row_args<R>(c, H);
   ra.grad = grad;
   const int nw = kRowWaves;
-  if (!c->kinematic && (grad || H) && c->Tm) {
+  // light and heavy rows (and the master-triangle sums) are independent:
+  // the heavy ones run on the library's second stream, forked after the row
+  // lists and joined before what reads both (not while profiling)
+  const bool par = c->side != nullptr && !c->prof.on;
+  const hipStream_t hs = par ? c->side : s;
+  auto fork = [&]() {
+    if (!par) return hipSuccess;
+    hipError_t r = hipEventRecord(c->ev_fork, s);
+    return r != hipSuccess ? r : hipStreamWaitEvent(c->side, c->ev_fork, 0);
+  };
+  auto join = [&]() {
+    if (!par) return hipSuccess;
+    hipError_t r = hipEventRecord(c->ev_join, c->side);
+    return r != hipSuccess ? r : hipStreamWaitEvent(s, c->ev_join, 0);
+  };
+  const bool sums = !c->kinematic && (grad || H) && c->Tm;
+  auto mtri = [&](hipStream_t st) {
     prof_mark(c, ST_MTRI, 0);
-    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads)), dim3(kThreads), 0, s, pr, b.mp_off,
+    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads)), dim3(kThreads), 0, st, pr, b.mp_off,
                        b.mp_list, (const R *)b.tri_nrm, c->Tm, b.status, c->caps.pairs, (R *)b.mtri);
     prof_mark(c, ST_MTRI, 1);
-  }
+  };
+  if (sums && !H) mtri(s);  // the gradient rows read the sums
   if (grad || H) {
     prof_mark(c, ST_ROWS_PRE, 0);
     if (c->V)
@@ -1748,8 +1765,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
     prof_mark(c, ST_GRAD, 0);
+    if ((e = fork()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_rows<R, 2, true>), hgrid, dim3(kWave * nw), 0, hs, ra, 64, heavy, nheavy);
     hipLaunchKernelGGL((k_rows<R, 2, false>), rgrid, dim3(kWave * nw), 0, s, ra, 64, light, nlight);
-    hipLaunchKernelGGL((k_rows<R, 2, true>), hgrid, dim3(kWave * nw), 0, s, ra, 64, heavy, nheavy);
+    if ((e = join()) != hipSuccess) return e;
     prof_mark(c, ST_GRAD, 1);
   }
   if (H) {
@@ -1759,24 +1778,35 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     int hslots = 1024;
     while (hslots < c->caps.row_entries && hslots < 4096) hslots <<= 1;
     auto lds = [&](int sl, int pass, bool heavy) { return (size_t)nw * row_lds_wave<R>(sl, pass, heavy); };
-    prof_mark(c, ST_ROWS_COUNT, 0);
-    hipLaunchKernelGGL((k_rows<R, 0, false>), rgrid, dim3(kWave * nw), lds(lslots, 0, false), s, ra, lslots, light, nlight);
-    prof_mark(c, ST_ROWS_COUNT, 1);
+    if ((e = fork()) != hipSuccess) return e;
+    if (sums) mtri(hs);  // read by the writing pass
     prof_mark(c, ST_ROWS_COUNT_H, 0);
-    hipLaunchKernelGGL((k_rows<R, 0, true>), hgrid, dim3(kWave * nw), lds(hslots, 0, true), s, ra, hslots, heavy, nheavy);
+    hipLaunchKernelGGL((k_rows<R, 0, true>), hgrid, dim3(kWave * nw), lds(hslots, 0, true), hs, ra, hslots, heavy,
+                       nheavy);
     prof_mark(c, ST_ROWS_COUNT_H, 1);
+    prof_mark(c, ST_ROWS_COUNT, 0);
+    hipLaunchKernelGGL((k_rows<R, 0, false>), rgrid, dim3(kWave * nw), lds(lslots, 0, false), s, ra, lslots, light,
+                       nlight);
+    prof_mark(c, ST_ROWS_COUNT, 1);
+    if ((e = join()) != hipSuccess) return e;
     e = scan_exclusive(c, b.row_cnt, H->row_ptr, c->V + 1);
     if (e != hipSuccess) return e;
-    prof_mark(c, ST_ROWS_FILL, 0);
-    hipLaunchKernelGGL((k_rows<R, 1, false>), rgrid, dim3(kWave * nw), lds(lslots, 1, false), s, ra, lslots, light, nlight);
-    prof_mark(c, ST_ROWS_FILL, 1);
+    if ((e = fork()) != hipSuccess) return e;
     prof_mark(c, ST_ROWS_FILL_H, 0);
-    hipLaunchKernelGGL((k_rows<R, 1, true>), hgrid, dim3(kWave * nw), lds(hslots, 1, true), s, ra, hslots, heavy, nheavy);
+    hipLaunchKernelGGL((k_rows<R, 1, true>), hgrid, dim3(kWave * nw), lds(hslots, 1, true), hs, ra, hslots, heavy,
+                       nheavy);
     prof_mark(c, ST_ROWS_FILL_H, 1);
+    prof_mark(c, ST_ROWS_FILL, 0);
+    hipLaunchKernelGGL((k_rows<R, 1, false>), rgrid, dim3(kWave * nw), lds(lslots, 1, false), s, ra, lslots, light,
+                       nlight);
+    prof_mark(c, ST_ROWS_FILL, 1);
+    if ((e = join()) != hipSuccess) return e;
     if (c->V > c->Vs) {
       prof_mark(c, ST_ROWS_COPY, 0);
+      if ((e = fork()) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_rows<R, 3, true>), hgrid, dim3(kWave * nw), 0, hs, ra, hslots, heavy, nheavy);
       hipLaunchKernelGGL((k_rows<R, 3, false>), rgrid, dim3(kWave * nw), 0, s, ra, lslots, light, nlight);
-      hipLaunchKernelGGL((k_rows<R, 3, true>), hgrid, dim3(kWave * nw), 0, s, ra, hslots, heavy, nheavy);
+      if ((e = join()) != hipSuccess) return e;
       prof_mark(c, ST_ROWS_COPY, 1);
     }
     hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, s, H->row_ptr, c->V, b.status, H->cap_nnzb);

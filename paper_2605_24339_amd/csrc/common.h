@@ -153,6 +153,12 @@ struct Prof {
 struct gmcp_ctx {
   gmcp::Prof prof;
   hipStream_t stream;
+  // the library's second stream (default priority) and its fork / join
+  // events: independent launches of one call overlap (forked from and
+  // joined back into `stream`, so the caller sees one stream, also under
+  // graph capture); null if creation failed (then everything runs in order)
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
   bool f64, kinematic, mortar, features;
   int n_env;
   int64_t Vs, Vm, Ts, Tm, Ns, V, n_tiles, total_cells;

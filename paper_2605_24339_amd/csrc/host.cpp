@@ -463,6 +463,19 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
     delete c;
     return GMCP_E_HIP;
   }
+  c->side = nullptr;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess) {
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(c->side);
+      c->side = nullptr;
+    } else if (hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(c->ev_fork);
+      (void)hipStreamDestroy(c->side);
+      c->side = nullptr;
+    }
+  } else {
+    c->side = nullptr;
+  }
   *out = c;
   return GMCP_OK;
 }
@@ -470,6 +483,12 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
 void gmcp_destroy(gmcp_ctx *c) {
   if (!c) return;
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipEventDestroy(c->ev_fork);
+    (void)hipEventDestroy(c->ev_join);
+    (void)hipStreamDestroy(c->side);
+  }
   delete c;
 }
 
