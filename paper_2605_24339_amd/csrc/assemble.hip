@@ -82,7 +82,7 @@ struct NarrowArgs {
 template <typename R> constexpr int narrow_waves() { return sizeof(R) == 4 ? 8 : 4; }
 
 template <typename R>
-__global__ __launch_bounds__(kWave * 8) void k_narrow(NarrowArgs<R> a) {
+__device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   constexpr int kNW = narrow_waves<R>();
   __shared__ CandL<R> sc[kNW][kWave];
   __shared__ SampL<R> ss[kNW][kWave];
@@ -403,6 +403,13 @@ __global__ __launch_bounds__(kWave * 8) void k_narrow(NarrowArgs<R> a) {
     a.pair[pbase + tri_pre + rank] = p;
   }
 }
+
+// float: six waves per SIMD (80 registers), three blocks of 8 waves per CU
+__global__ __launch_bounds__(kWave * 8) __attribute__((amdgpu_waves_per_eu(6))) void k_narrow_f32(
+    NarrowArgs<float> a) {
+  narrow_body<float>(a);
+}
+__global__ __launch_bounds__(kWave * 4) void k_narrow_f64(NarrowArgs<double> a) { narrow_body<double>(a); }
 
 // ----------------------------------------------------------- mortar samples
 // Clipped mortar face samples (Sec. 4.1, face samples): for a slave
@@ -1706,8 +1713,12 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     if (c->mortar)
       hipLaunchKernelGGL(k_mortar<R>, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
     else
-      hipLaunchKernelGGL(k_narrow<R>, dim3(nblk(c->n_tiles, narrow_waves<R>())), dim3(kWave * narrow_waves<R>()), 0,
-                         s, na);
+      if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL(k_narrow_f32, dim3(nblk(c->n_tiles, narrow_waves<R>())), dim3(kWave * narrow_waves<R>()),
+                           0, s, na);
+      else
+        hipLaunchKernelGGL(k_narrow_f64, dim3(nblk(c->n_tiles, narrow_waves<R>())), dim3(kWave * narrow_waves<R>()),
+                           0, s, na);
   }
   prof_mark(c, ST_NARROW, 1);
   hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, s, b.tile_E, b.env, energy);
