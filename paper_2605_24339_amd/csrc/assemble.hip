@@ -32,6 +32,7 @@ template <typename R> struct CandL {
 template <typename R> struct SampL {
   int32_t M;
   R c1, c2, b0, b1, b2;
+  R s1, s2;  // the rule point (slave barycentrics 1 - s1 - s2, s1, s2)
 };
 
 __device__ inline int sym3(int a, int b) {  // 00 01 02 11 12 22
@@ -60,7 +61,7 @@ struct NarrowArgs {
   const EnvInfo *env;
   const double *rule;
   const R *area;
-  const int32_t *cand_off, *cand;
+  const int32_t *cand_cnt, *cand_pos, *cand;  // per slave triangle: list length and offset in cand
   int64_t Ts, cap_cand;
   const R *g_ref, *dgap;
   Rec<R> *rec;
@@ -89,7 +90,6 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   __shared__ unsigned int alloc_r[kNW], alloc_p[kNW];
   __shared__ unsigned long long alloc_rb, alloc_pb;
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  if (a.cand_off[a.Ts] > a.cap_cand) return;  // uniform over the grid: no wave reaches a barrier
   // the block's allocation: every wave calls it once (two block barriers)
   auto allocate = [&](int nrec, int npair, unsigned long long &rb, unsigned long long &pb) {
     if (lane == 0) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   // ---- a tile without candidates selects nothing: empty bookkeeping only
   // (the broad phase has already checked its triangles' frames)
   {
-    int cn = valid ? a.cand_off[T + 1] - a.cand_off[T] : 0;
+    int cn = valid ? a.cand_cnt[T] : 0;
     for (int o = 32; o > 0; o >>= 1) cn = max(cn, __shfl_xor(cn, o, kWave));
     if (cn == 0) {
       if (valid && q == 0) {
@@ -177,8 +177,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   R eps = dhat;
   if (valid && a.g_ref) eps = fmin(R(0.9) * a.g_ref[k], dhat);
 
-  const int cbeg = (valid && !degen) ? a.cand_off[T] : 0;
-  const int ccnt = (valid && !degen) ? a.cand_off[T + 1] - cbeg : 0;
+  const int ccnt = (valid && !degen) ? a.cand_cnt[T] : 0;
+  const int cbeg = ccnt > 0 ? a.cand_pos[T] : 0;
   int maxc = ccnt;
   for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, kWave));
 
@@ -287,6 +287,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   me.b0 = bb0;
   me.b1 = bb1;
   me.b2 = bb2;
+  me.s1 = xi;
+  me.s2 = eta;
   ss[w][lane] = me;
   wave_sync();
 
@@ -310,8 +312,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
       for (int i = 0; i < nq; ++i) {
         const SampL<R> &o = ss[w][j * nq + i];
         if (o.M < 0) continue;
-        const double *ri = a.rule + ((ev.rule_n - 1) * 16 + i) * 3;
-        R bs[3] = {R(1) - (R)ri[0] - (R)ri[1], (R)ri[0], (R)ri[1]};
+        R bs[3] = {R(1) - o.s1 - o.s2, o.s1, o.s2};
         acc += ib >= 0 ? o.c2 * bs[ia] * bs[ib] : o.c1 * bs[ia];
       }
       a.tri_sum[9 * (int64_t)T + v] = acc;
@@ -387,8 +388,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
     for (int i = 0; i < nq; ++i) {
       const SampL<R> &o = ss[w][j * nq + i];
       if (o.M != bM) continue;
-      const double *ri = a.rule + ((ev.rule_n - 1) * 16 + i) * 3;
-      R bs[3] = {R(1) - (R)ri[0] - (R)ri[1], (R)ri[0], (R)ri[1]};
+      R bs[3] = {R(1) - o.s1 - o.s2, o.s1, o.s2};
       R bm[3] = {o.b0, o.b1, o.b2};
       p.mm[0] += o.c2 * bm[0] * bm[0];
       p.mm[1] += o.c2 * bm[0] * bm[1];
@@ -570,7 +570,6 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   const int lane = threadIdx.x;
   const int tile_id = xcd_block(blockIdx.x, gridDim.x);
   if (tile_id >= a.n_tiles) return;
-  if (a.cand_off[a.Ts] > a.cap_cand) return;
   const Tile tl = a.tiles[tile_id];
   const EnvInfo &ev = a.env[tl.env];
   const R eps = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
@@ -584,7 +583,7 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   const uint64_t below = (1ull << lane) - 1;
   for (int j = 0; j < tl.count; ++j) {
     const int T = a.s_order[tl.first + j];
-    const int cb = a.cand_off[T], cn = a.cand_off[T + 1] - cb;
+    const int cn = a.cand_cnt[T], cb = cn > 0 ? a.cand_pos[T] : 0;
     // slave frame
     R s0[3], e1[3], e2[3], n[3];
     {
@@ -719,9 +718,11 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
     if (__any(pen) && lane == 0) set_error(a.st, GMCP_E_PENETRATION, (unsigned long long)T);
     if (nchunk > kMortarChunks && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
     unsigned long long rbase = 0, pbase = 0;
-    if (lane == 0) {
-      if (nrec) rbase = atomicAdd(&a.st->n_active, (unsigned long long)nrec);
-      if (npair) pbase = atomicAdd(&a.st->n_pairs, (unsigned long long)npair);
+    if (lane == 0 && (nrec || npair)) {  // records and pairs in one atomic (k_mortar_counts unpacks the totals)
+      const unsigned long long old =
+          atomicAdd(&a.st->mortar_alloc, ((unsigned long long)npair << 32) | (unsigned long long)nrec);
+      rbase = old & 0xffffffffull;
+      pbase = old >> 32;
     }
     rbase = __shfl(rbase, 0, kWave);
     pbase = __shfl(pbase, 0, kWave);
@@ -872,6 +873,15 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
 // ---------------------------------------------------- pairs by master tri
 // pass 0: count pairs per master triangle; pass 1: place (slave triangle,
 // pair) keys into the buckets in arrival order (counters return to zero)
+// the totals of the clipped-sample allocation into the status counters
+__global__ void k_mortar_counts(DevStatus *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const unsigned long long v = st->mortar_alloc;
+    st->n_active = v & 0xffffffffull;
+    st->n_pairs = v >> 32;
+  }
+}
+
 template <typename R>
 __global__ void k_pair_bucket(const Pair<R> *__restrict__ pair, const DevStatus *st, int64_t cap_pairs,
                               int32_t *__restrict__ mp_cnt, const int32_t *__restrict__ mp_off,
@@ -1686,8 +1696,9 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.env = b.env;
   na.rule = b.rule;
   na.area = (const R *)b.area;
-  na.cand_off = b.cand_off;
-  na.cand = b.cand;
+  na.cand_cnt = b.cand_cnt;
+  na.cand_pos = b.cand_tmp_off;
+  na.cand = b.cand_tmp;
   na.Ts = c->Ts;
   na.cap_cand = c->caps.candidates;
   na.g_ref = g_ref;
@@ -1710,9 +1721,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.m_vt = b.m_vt;
   prof_mark(c, ST_NARROW, 0);
   if (c->n_tiles) {
-    if (c->mortar)
+    if (c->mortar) {
       hipLaunchKernelGGL(k_mortar<R>, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
-    else
+      hipLaunchKernelGGL(k_mortar_counts, dim3(1), dim3(64), 0, s, b.status);
+    } else
       if constexpr (sizeof(R) == 4)
         hipLaunchKernelGGL(k_narrow_f32, dim3(nblk(c->n_tiles, narrow_waves<R>())), dim3(kWave * narrow_waves<R>()),
                            0, s, na);

@@ -94,26 +94,26 @@ __global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
   const int nw = blockDim.x / kWave;
   bool same = true;
   for (int v = 0; v < nw; ++v)
     if (benv[v] != -1 && benv[v] != benv[0]) same = false;
+  if (same) {  // one environment (the common case): six threads, one component each
+    const int d = threadIdx.x;
+    if (d >= 6 || benv[0] < 0) return;
+    float a = bbox[0][d];
+    for (int v = 1; v < nw; ++v)
+      if (benv[v] >= 0) a = d < 3 ? fminf(a, bbox[v][d]) : fmaxf(a, bbox[v][d]);
+    if (d < 3) atomicMin(&box[6 * benv[0] + d], float_to_ordered(a));
+    else atomicMax(&box[6 * benv[0] + d], float_to_ordered(a));
+    return;
+  }
+  if (threadIdx.x != 0) return;  // several environments: each uniform wave's box on its own
   for (int v = 0; v < nw; ++v) {
     if (benv[v] < 0) continue;
-    if (same && v > 0) continue;
-    float a[6];
-    for (int d = 0; d < 6; ++d) a[d] = bbox[v][d];
-    if (same)
-      for (int u = 1; u < nw; ++u)
-        if (benv[u] >= 0)
-          for (int d = 0; d < 3; ++d) {
-            a[d] = fminf(a[d], bbox[u][d]);
-            a[3 + d] = fmaxf(a[3 + d], bbox[u][3 + d]);
-          }
     for (int d = 0; d < 3; ++d) {
-      atomicMin(&box[6 * benv[v] + d], float_to_ordered(a[d]));
-      atomicMax(&box[6 * benv[v] + 3 + d], float_to_ordered(a[3 + d]));
+      atomicMin(&box[6 * benv[v] + d], float_to_ordered(bbox[v][d]));
+      atomicMax(&box[6 * benv[v] + 3 + d], float_to_ordered(bbox[v][3 + d]));
     }
   }
 }
@@ -280,7 +280,6 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
 constexpr int kQueryWaves = kThreads / kWave;
 constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS set)
 constexpr int kMaxSlabs = 64;
-constexpr int kQueryBlocks = 2048;  // fixed grid of the list-walking query (8 blocks of 4 waves per CU)
 
 // vertex box and unit normal of slave triangle t (float, grown outward)
 template <typename R>
@@ -376,11 +375,24 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
             active = true;  // too many cells to count here: let the wave kernel decide
           } else {
             const int64_t base = env[e].cell0;
-            for (int z = c0[2]; z <= c1[2] && !active; ++z)
-              for (int y = c0[1]; y <= c1[1] && !active; ++y) {
-                const int64_t row = base + ((int64_t)z * g.ny + y) * g.nx;
-                active = cell_start[row + c1[0] + 1] > cell_start[row + c0[0]];  // x-run of cells is contiguous
+            // the (y, z) rows of the box, 8 at a time so that their loads are
+            // in flight together; a row's x-run of cells is contiguous
+            const int ny = c1[1] - c0[1] + 1, nrow = ny * (c1[2] - c0[2] + 1);
+            for (int r0 = 0; r0 < nrow && !active; r0 += 8) {
+              int32_t hi_s[8], lo_s[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const int r = r0 + k;
+                hi_s[k] = lo_s[k] = 0;
+                if (r < nrow) {
+                  const int64_t row = base + ((int64_t)(c0[2] + r / ny) * g.ny + c0[1] + r % ny) * g.nx;
+                  hi_s[k] = cell_start[row + c1[0] + 1];
+                  lo_s[k] = cell_start[row + c0[0]];
+                }
               }
+#pragma unroll
+              for (int k = 0; k < 8; ++k) active = active || hi_s[k] > lo_s[k];
+            }
           }
         }
       }
@@ -417,7 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
 // then places every list at its CSR offset, so the candidate CSR is the
 // same on every run.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, const int32_t *__restrict__ ts,
+__device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32_t *__restrict__ ts,
                                                      const int32_t *__restrict__ s_order,
                                                      const int32_t *__restrict__ s_env,
                                                      const EnvInfo *__restrict__ env,
@@ -429,7 +441,8 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
                                                      int64_t cap_cand,
                                                      int64_t cap_items, int64_t total_cells,
                                                      const int32_t *__restrict__ qlist,
-                                                     const int32_t *__restrict__ qcount, DevStatus *st) {
+                                                     const int32_t *__restrict__ qcount,
+                                                     int32_t *__restrict__ cand_blk, DevStatus *st) {
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
   __shared__ int32_t ipfx[kQueryWaves][kWave], istart[kQueryWaves][kWave], islab[kQueryWaves][kWave];
@@ -439,6 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   if (cell_start[total_cells] > cap_items) {  // grid incomplete
     for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
       if (lane == 0) cand_cnt[qlist[li]] = 0;
+    if (threadIdx.x == 0) cand_blk[blockIdx.x] = 0;
     return;
   }
   // the scratch is split evenly over the blocks; a block allocates its
@@ -581,10 +595,35 @@ __global__ __launch_bounds__(kThreads) void k_query(const R *__restrict__ xs, co
   wave_sync();  // the set is reused by the wave's next triangle
     }(qlist[li]);
   __syncthreads();
-  if (threadIdx.x == 0 && (int64_t)blk_req > share) {
-    atomicMax(&st->need_cand, (unsigned long long)blk_req * gridDim.x);
-    atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+  if (threadIdx.x == 0) {
+    cand_blk[blockIdx.x] = blk_req;  // summed by gmcp_status
+    if ((int64_t)blk_req > share) {
+      atomicMax(&st->need_cand, (unsigned long long)blk_req * gridDim.x);
+      atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+    }
   }
+}
+
+// float: seven waves per SIMD (72 registers); double as compiled
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_query_f32(
+    const float *__restrict__ xs, const int32_t *__restrict__ ts, const int32_t *__restrict__ s_order,
+    const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const GridEnv *__restrict__ grid, int64_t Ts,
+    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items, const float4 *__restrict__ mbox,
+    int32_t *__restrict__ cand_cnt, int32_t *__restrict__ tmp_off, int32_t *__restrict__ cand_tmp, int64_t cap_cand,
+    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount,
+    int32_t *__restrict__ cand_blk, DevStatus *st) {
+  query_body<float>(xs, ts, s_order, s_env, env, grid, Ts, cell_start, items, mbox, cand_cnt, tmp_off, cand_tmp,
+                    cap_cand, cap_items, total_cells, qlist, qcount, cand_blk, st);
+}
+__global__ __launch_bounds__(kThreads) void k_query_f64(
+    const double *__restrict__ xs, const int32_t *__restrict__ ts, const int32_t *__restrict__ s_order,
+    const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const GridEnv *__restrict__ grid, int64_t Ts,
+    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items, const float4 *__restrict__ mbox,
+    int32_t *__restrict__ cand_cnt, int32_t *__restrict__ tmp_off, int32_t *__restrict__ cand_tmp, int64_t cap_cand,
+    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount,
+    int32_t *__restrict__ cand_blk, DevStatus *st) {
+  query_body<double>(xs, ts, s_order, s_env, env, grid, Ts, cell_start, items, mbox, cand_cnt, tmp_off, cand_tmp,
+                    cap_cand, cap_items, total_cells, qlist, qcount, cand_blk, st);
 }
 
 // Each listed triangle's sorted list, from its scratch offset to its CSR
@@ -595,9 +634,8 @@ __global__ __launch_bounds__(kThreads) void k_cand_move(const int32_t *__restric
                                                          const int32_t *__restrict__ tmp_off,
                                                          const int32_t *__restrict__ cand_off,
                                                          const int32_t *__restrict__ cand_tmp,
-                                                         int32_t *__restrict__ cand, int64_t Ts, DevStatus *st) {
+                                                         int32_t *__restrict__ cand) {
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_cand = (unsigned long long)cand_off[Ts];
   const int64_t nlist = *qcount;
   for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves) {
     const int t = qlist[li];
@@ -665,18 +703,33 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   const int64_t qb = (c->Ts + kQueryWaves - 1) / kQueryWaves;
   const dim3 qgrid((unsigned)(qb < kQueryBlocks ? (qb > 0 ? qb : 1) : kQueryBlocks));
   prof_mark(c, ST_QUERY_COUNT, 0);
+  c->query_blocks = c->Ts ? (int)qgrid.x : 0;
   if (c->Ts)
-    hipLaunchKernelGGL(k_query<R>, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+  {
+    if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL(k_query_f32, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.status);
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.cand_blk, b.status);
+    else
+      hipLaunchKernelGGL(k_query_f64, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
+                       b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.cand_blk, b.status);
+  }
   prof_mark(c, ST_QUERY_COUNT, 1);
-  e = scan_exclusive(c, b.cand_cnt, b.cand_off, c->Ts + 1);
+  // the narrow phase reads every list where the query wrote it (count and
+  // scratch offset per triangle); the candidate CSR is built only for export
+  return hipGetLastError();
+}
+
+hipError_t build_candidate_csr(gmcp_ctx *c) {
+  Buffers &b = c->b;
+  hipError_t e = scan_exclusive(c, b.cand_cnt, b.cand_off, c->Ts + 1);
   if (e != hipSuccess) return e;
-  prof_mark(c, ST_QUERY_FILL, 0);
+  const int64_t qb = (c->Ts + kQueryWaves - 1) / kQueryWaves;
+  const dim3 qgrid((unsigned)(qb < kQueryBlocks ? (qb > 0 ? qb : 1) : kQueryBlocks));
   if (c->Ts)
-    hipLaunchKernelGGL(k_cand_move, qgrid, dim3(kThreads), 0, s, b.qlist, b.qcount, b.cand_cnt, b.cand_tmp_off,
-                       b.cand_off, b.cand_tmp, b.cand, c->Ts, b.status);
-  prof_mark(c, ST_QUERY_FILL, 1);
+    hipLaunchKernelGGL(k_cand_move, qgrid, dim3(kThreads), 0, c->stream, b.qlist, b.qcount, b.cand_cnt,
+                       b.cand_tmp_off, b.cand_off, b.cand_tmp, b.cand);
   return hipGetLastError();
 }
 

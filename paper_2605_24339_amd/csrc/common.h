@@ -21,6 +21,7 @@ constexpr int kWave = 64;
 constexpr int kMaxRule = 4;            // n <= 4  => <= 16 samples per triangle
 constexpr int kRuleDoubles = kMaxRule * 16 * 3 + kMaxRule * 4 * 2;  // 2D rules, then 1D Gauss-Legendre
 constexpr int kGaussOff = kMaxRule * 16 * 3;
+constexpr int kQueryBlocks = 2048;  // fixed grid of the list-walking query (8 blocks of 4 waves per CU)
 constexpr int kTilePerBlock = 4;       // narrow phase: 4 waves, one tile each
 
 // ---------------------------------------------------------------- status
@@ -30,6 +31,7 @@ struct DevStatus {
   unsigned long long index;  // min offending id (atomicMin), ~0ull if none
   unsigned long long n_active, n_pairs, nnzb, n_cand, n_swept;
   unsigned long long need_items, need_cand, need_active, need_pairs, need_row;
+  unsigned long long mortar_alloc;  // clipped samples: pairs << 32 | records, one atomic per triangle
 };
 
 // --------------------------------------------------------- per environment
@@ -88,6 +90,7 @@ struct Buffers {
   float4 *mbox;                                 // [Tm][3]: lo, hi, unit normal
   int32_t *cand_cnt, *cand_off, *cand;
   int32_t *cand_tmp, *cand_tmp_off;             // one-pass query: scratch lists and their offsets
+  int32_t *cand_blk;                            // [kQueryBlocks] candidates found by each query block
   int32_t *qlist, *qcount;                      // [Ts], [1]: slave triangles whose prism meets occupied cells
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
@@ -167,6 +170,7 @@ struct gmcp_ctx {
   std::vector<gmcp::EnvInfo> henv;
   bool samples_built, broadphase_done, assembled;
   bool swept_ready;  // gmcp_ccd_swept enqueued, gmcp_ccd_finish not yet
+  int query_blocks;  // grid of the last query (its entries of b.cand_blk are valid)
   gmcp::Buffers b;
   size_t scan_tmp_elems;
 };
@@ -195,6 +199,8 @@ void prof_mark(gmcp_ctx *c, int stage, int end);
 
 template <typename R> hipError_t launch_rest_area(gmcp_ctx *c, const R *x_rest, R *weights);
 template <typename R> hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm);
+// the candidate lists of the last broad phase as a CSR (cand_off, cand), for export
+hipError_t build_candidate_csr(gmcp_ctx *c);
 // grid over master triangles per environment; swept != 0 uses the boxes of
 // the motion x -> x + dx (domain: slave swept box) instead of the prism region
 template <typename R>

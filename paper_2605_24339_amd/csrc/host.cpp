@@ -199,6 +199,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.cand = p.take<int32_t>(cp.candidates);
   t.cand_tmp = p.take<int32_t>(cp.candidates);
   t.cand_tmp_off = p.take<int32_t>(s.Ts);
+  t.cand_blk = p.take<int32_t>(kQueryBlocks);
   t.qlist = p.take<int32_t>(s.Ts);
   t.qcount = p.take<int32_t>(1);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
@@ -326,6 +327,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->broadphase_done = false;
   c->assembled = false;
   c->swept_ready = false;
+  c->query_blocks = 0;
   plan_workspace(s, *caps, (char *)workspace, &c->b, &c->scan_tmp_elems);
 
   // ---- topology back to the host
@@ -650,8 +652,9 @@ int gmcp_sample_results(gmcp_ctx *c, int32_t *M, void *g, void *bm, void *c1, vo
 
 int gmcp_candidates(gmcp_ctx *c, int32_t *cand_off, int32_t *cand, int64_t cap) {
   if (!c || !cand_off || !c->broadphase_done) return GMCP_E_ARG;
-  hipError_t e = hipMemcpyAsync(cand_off, c->b.cand_off, sizeof(int32_t) * (c->Ts + 1), hipMemcpyDeviceToDevice,
-                                c->stream);
+  hipError_t e = build_candidate_csr(c);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cand_off, c->b.cand_off, sizeof(int32_t) * (c->Ts + 1), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && cand && cap > 0) {
     int64_t n = std::min<int64_t>(cap, c->caps.candidates);
     e = hipMemcpyAsync(cand, c->b.cand, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream);
@@ -671,12 +674,22 @@ int gmcp_status(gmcp_ctx *c, gmcp_status_info *info) {
   info->n_active = (int64_t)st.n_active;
   info->n_pairs = (int64_t)st.n_pairs;
   info->nnzb = (int64_t)st.nnzb;
-  info->n_candidates = (int64_t)st.n_cand;
+  // candidates: the query blocks' totals (no single-address atomics in the query)
+  int64_t ncand = 0;
+  if (c->query_blocks > 0) {
+    std::vector<int32_t> blk(c->query_blocks);
+    if (hipMemcpyAsync(blk.data(), c->b.cand_blk, sizeof(int32_t) * blk.size(), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return GMCP_E_HIP;
+    for (int32_t v : blk) ncand += v;
+  }
+  info->n_candidates = ncand;
   info->n_swept = (int64_t)st.n_swept;
   info->need.grid_cells = c->caps.grid_cells;
   // the counters are complete totals even when a buffer overflowed
   info->need.grid_items = std::max<int64_t>((int64_t)st.need_items, 0);
-  info->need.candidates = std::max<int64_t>((int64_t)st.need_cand, (int64_t)st.n_cand);
+  info->need.candidates = std::max<int64_t>((int64_t)st.need_cand, ncand);
   info->need.active = (int64_t)st.n_active;
   info->need.pairs = (int64_t)st.n_pairs;
   info->need.row_entries = (int64_t)st.need_row;

@@ -94,6 +94,7 @@ __global__ void k_stage_init(DevStatus *st, StageInit a, int n_env) {
       st->n_active = 0;
       st->n_pairs = 0;
       st->nnzb = 0;
+      st->mortar_alloc = 0;
     }
     if (a.which & 4) st->n_swept = 0;  // step bound
   }
