@@ -1495,9 +1495,15 @@ template <typename R>
 // per-environment sum of the tile energies: a fixed split over 1024
 // threads, wave butterflies, then the 16 wave sums in order (deterministic)
 __global__ __launch_bounds__(1024) void k_energy(const double *__restrict__ tile_E, const EnvInfo *__restrict__ env,
-                                                 R *energy) {
+                                                 R *energy, const int32_t *__restrict__ row_ptr, int64_t V,
+                                                 DevStatus *st, int64_t cap_nnzb) {
   __shared__ double part[1024 / kWave];
   const int e = blockIdx.x, lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (row_ptr && e == 0 && threadIdx.x == 0) {  // the BSR's block count (after the row kernels)
+    const long long nnzb = row_ptr[V];
+    st->nnzb = (unsigned long long)nnzb;
+    if (nnzb > cap_nnzb) atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+  }
   const int t0 = env[e].tile0, t1 = env[e].tile1;
   double s = 0.0;
   for (int t = t0 + threadIdx.x; t < t1; t += 1024) s += tile_E[t];
@@ -1511,12 +1517,6 @@ __global__ __launch_bounds__(1024) void k_energy(const double *__restrict__ tile
   }
 }
 
-__global__ void k_finish_counts(const int32_t *row_ptr, int64_t V, DevStatus *st, int64_t cap_nnzb) {
-  if (threadIdx.x || blockIdx.x) return;
-  long long nnzb = row_ptr[V];
-  st->nnzb = (unsigned long long)nnzb;
-  if (nnzb > cap_nnzb) atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
-}
 
 template <typename R>
 __global__ void k_rest_area(const R *__restrict__ x, const int32_t *__restrict__ ts, int64_t Ts, R *area,
@@ -1733,7 +1733,6 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
                            0, s, na);
   }
   prof_mark(c, ST_NARROW, 1);
-  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, s, b.tile_E, b.env, energy);
   // bucket pairs by master triangle (needed for master rows and the HVP)
   const Pair<R> *pr = (const Pair<R> *)b.pair;
   unsigned pb = nblk(c->caps.pairs);
@@ -1832,8 +1831,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
       if ((e = join()) != hipSuccess) return e;
       prof_mark(c, ST_ROWS_COPY, 1);
     }
-    hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(64), 0, s, H->row_ptr, c->V, b.status, H->cap_nnzb);
   }
+  // per-environment energy (and the BSR's block count when written)
+  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, s, b.tile_E, b.env, energy,
+                     H ? (const int32_t *)H->row_ptr : nullptr, c->V, b.status, H ? H->cap_nnzb : (int64_t)0);
   return hipGetLastError();
 }
 
@@ -1945,7 +1946,8 @@ hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy
                        c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order, b.env, b.rule, (const R *)b.area,
                        (const Rec<R> *)b.rec, b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, b.status, c->caps.active,
                        b.tile_E);
-  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, c->stream, b.tile_E, b.env, energy);
+  hipLaunchKernelGGL(k_energy<R>, dim3(c->n_env), dim3(1024), 0, c->stream, b.tile_E, b.env, energy, nullptr,
+                     (int64_t)0, b.status, (int64_t)0);
   return hipGetLastError();
 }
 

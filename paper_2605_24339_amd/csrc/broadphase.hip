@@ -38,8 +38,12 @@ template <typename R>
 __global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
                                                          const int32_t *__restrict__ ts,
                                                          const int32_t *__restrict__ s_env, int64_t Ts,
-                                                         uint32_t *box) {
+                                                         uint32_t *box, int32_t *zero_a, int32_t *zero_b) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {  // counters of the kernels that follow (nullable)
+    if (zero_a) *zero_a = 0;
+    if (zero_b) *zero_b = 0;
+  }
   int lane = threadIdx.x & (kWave - 1);
   bool ok = t < Ts;
   int env = ok ? s_env[t] : -1;
@@ -118,14 +122,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__
   }
 }
 
-// grid geometry per environment: domain = box grown by `pad`, cell size
+// grid geometry of environment e: domain = box grown by `pad`, cell size
 // from the caller (cell > 0) or max(eps_max / 4, cbrt(volume / budget)),
 // enlarged until the cell count fits the environment's budget
-__global__ void k_grid_setup(const EnvInfo *__restrict__ env, const uint32_t *__restrict__ box, GridEnv *grid,
-                             int n_env, int swept) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_env) return;
-  const EnvInfo &v = env[e];
+__device__ inline GridEnv grid_of(const EnvInfo &v, const uint32_t *__restrict__ box, int e, int swept) {
   GridEnv g;
   float lo[3], hi[3];
   bool empty = false;
@@ -143,8 +143,7 @@ __global__ void k_grid_setup(const EnvInfo *__restrict__ env, const uint32_t *__
     g.h = 1.0f;
     g.inv_h = 1.0f;
     for (int d = 0; d < 3; ++d) g.lo[d] = 0.0f;
-    grid[e] = g;
-    return;
+    return g;
   }
   double ext[3] = {hi[0] - (double)lo[0], hi[1] - (double)lo[1], hi[2] - (double)lo[2]};
   double span = fmax(ext[0], fmax(ext[1], ext[2]));
@@ -168,7 +167,7 @@ __global__ void k_grid_setup(const EnvInfo *__restrict__ env, const uint32_t *__
   g.ny = (int)n[1];
   g.nz = (int)n[2];
   for (int d = 0; d < 3; ++d) g.lo[d] = lo[d];
-  grid[e] = g;
+  return g;
 }
 
 __device__ inline int cell_coord(const GridEnv &g, float x, int d) {
@@ -185,17 +184,22 @@ __device__ inline bool box_hits_grid(const GridEnv &g, const float lo[3], const 
   return true;
 }
 
-// master triangle boxes (and unit normals), static or swept over dx, and
-// the count of the grid cells each box covers (placement: k_grid_insert)
+// Thread per master triangle (and per environment): the environments'
+// grids from their slave boxes (thread e writes grid[e]; every triangle's
+// thread derives its own environment's grid, so no separate launch is
+// needed), master triangle boxes (and unit normals), static or swept over
+// dx, and the count of the grid cells each box covers (placement:
+// k_grid_insert)
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_master_boxes(const R *__restrict__ xm, const R *__restrict__ dxm,
                                                             const int32_t *__restrict__ tm, int64_t Tm,
                                                             float4 *__restrict__ mbox,
                                                             const int32_t *__restrict__ m_env,
                                                             const EnvInfo *__restrict__ env,
-                                                            const GridEnv *__restrict__ grid,
-                                                            int32_t *__restrict__ cell_cnt) {
+                                                            const uint32_t *__restrict__ box, GridEnv *grid,
+                                                            int n_env, int swept, int32_t *__restrict__ cell_cnt) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_env) grid[t] = grid_of(env[t], box, (int)t, swept);
   if (t >= Tm) return;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   R p[3][3];
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_master_boxes(const R *__restrict__
   mbox[3 * t + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
   mbox[3 * t + 2] = make_float4((float)(N[0] * inv), (float)(N[1] * inv), (float)(N[2] * inv), 0.0f);
   const int e = m_env[t];
-  const GridEnv g = grid[e];
+  const GridEnv g = grid_of(env[e], box, e, swept);
   if (!g.valid || !box_hits_grid(g, lo, hi)) return;
   int c0[3], c1[3];
   for (int d = 0; d < 3; ++d) {
@@ -334,9 +338,14 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
                                                          const int32_t *__restrict__ cell_start, int64_t cap_items,
                                                          int64_t total_cells, int32_t *__restrict__ cand_cnt,
                                                          int32_t *__restrict__ qlist, int32_t *__restrict__ qcount,
-                                                         DevStatus *st) {
+                                                         uint32_t *__restrict__ box, int n_env, DevStatus *st) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
+  if (i < n_env)  // the slave boxes were read by the grid kernels: empty them for the next call
+    for (int d = 0; d < 3; ++d) {
+      box[6 * i + d] = 0xffffffffu;  // min: largest ordered value
+      box[6 * i + 3 + d] = 0u;       // max: smallest ordered value
+    }
   bool active = false;
   int64_t t = -1;
   if (i < Ts) {
@@ -658,16 +667,17 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   int32_t *items = swept ? b.sitems : b.items;
   float4 *mbox = swept ? b.smbox : b.mbox;
   hipStream_t s = c->stream;
-  // the caller's stage_init has emptied the boxes
+  // the boxes are empty here: the swept ones from the caller's stage_init,
+  // the static ones from the previous query prepass (or creation); the
+  // slave-box kernel also zeroes the broad phase's two list counters
   if (c->Ts)
     hipLaunchKernelGGL(k_slave_box<R>, dim3((unsigned)((c->Ts + kBoxThreads - 1) / kBoxThreads)),
-                       dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, c->ts, b.s_env, c->Ts, box);
-  hipLaunchKernelGGL(k_grid_setup, dim3((c->n_env + 63) / 64), dim3(64), 0, s, b.env, box, grid, c->n_env,
-                     swept ? 1 : 0);
-  if (c->Tm) {
-    hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr,
-                       c->tm, c->Tm, mbox, b.m_env, b.env, grid, cnt);
-  }
+                       dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, c->ts, b.s_env, c->Ts, box,
+                       swept ? nullptr : b.qcount, swept ? nullptr : b.cand_cnt + c->Ts);
+  const int64_t nmb = std::max<int64_t>(c->Tm, c->n_env);
+  if (nmb)
+    hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(nmb)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr, c->tm,
+                       c->Tm, mbox, b.m_env, b.env, box, grid, c->n_env, swept ? 1 : 0, cnt);
   hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1, swept);
   if (e != hipSuccess) return e;
   if (c->Tm)
@@ -680,24 +690,26 @@ template <typename R>
 hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   Buffers &b = c->b;
   hipStream_t s = c->stream;
-  StageInit si;
-  si.which = 1;
-  si.box = b.box;
-  si.zero[0] = b.qcount;
-  si.nzero[0] = 1;
-  si.zero[1] = b.cand_cnt + c->Ts;
-  si.nzero[1] = 1;
-  hipError_t e = stage_init(c, si);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!c->Ts) {  // no slave triangle: nothing below resets these
+    StageInit si;
+    si.which = 1;
+    si.box = b.box;
+    si.zero[0] = b.qcount;
+    si.nzero[0] = 1;
+    si.zero[1] = b.cand_cnt + c->Ts;
+    si.nzero[1] = 1;
+    if ((e = stage_init(c, si)) != hipSuccess) return e;
+  }
   prof_mark(c, ST_GRID, 0);
   e = build_grid<R>(c, xs, xm, nullptr, nullptr, false);
   prof_mark(c, ST_GRID, 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_QUERY_PRE, 0);
   if (c->Ts)
-    hipLaunchKernelGGL(k_query_pre<R>, dim3(nblk(c->Ts)), dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env,
-                       b.grid, c->Ts, b.cell_start, c->caps.grid_items, c->total_cells, b.cand_cnt, b.qlist, b.qcount,
-                       b.status);
+    hipLaunchKernelGGL(k_query_pre<R>, dim3(nblk(std::max<int64_t>(c->Ts, c->n_env))), dim3(kThreads), 0, s, xs, c->ts,
+                       b.s_order, b.s_env, b.env, b.grid, c->Ts, b.cell_start, c->caps.grid_items, c->total_cells,
+                       b.cand_cnt, b.qlist, b.qcount, b.box, c->n_env, b.status);
   prof_mark(c, ST_QUERY_PRE, 1);
   // the wave kernels walk the query list with a fixed grid
   const int64_t qb = (c->Ts + kQueryWaves - 1) / kQueryWaves;

@@ -465,6 +465,14 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
     delete c;
     return GMCP_E_HIP;
   }
+  {  // the static slave boxes start empty (each broad phase empties them for the next)
+    gmcp::StageInit si;
+    si.box = c->b.box;
+    if (gmcp::stage_init(c, si) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+      delete c;
+      return GMCP_E_HIP;
+    }
+  }
   c->side = nullptr;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess) {
     if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
