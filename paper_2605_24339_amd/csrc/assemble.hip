@@ -70,6 +70,7 @@ struct NarrowArgs {
   int32_t *tri_npair, *tri_poff, *tri_roff, *tri_rcnt;
   Pair<R> *pair;
   int64_t cap_pairs;
+  int32_t *mp_cnt;  // pairs per master triangle (counted where the pairs are written)
   double *tile_E;
   DevStatus *st;
   bool features;                                   // clipped samples: edge and point samples too
@@ -401,6 +402,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
       for (int m = 0; m < 3; ++m) p.gm[m] += o.c1 * bm[m];
     }
     a.pair[pbase + tri_pre + rank] = p;
+    atomicAdd(&a.mp_cnt[bM], 1);
   }
 }
 
@@ -858,6 +860,7 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
         }
       }
       a.pair[pslot] = pr;
+      atomicAdd(&a.mp_cnt[M], 1);
     }
     for (int z = 0; z < 9; ++z)
       for (int o = 32; o > 0; o >>= 1) ts_[z] += __shfl_xor(ts_[z], o, kWave);
@@ -882,20 +885,24 @@ __global__ void k_mortar_counts(DevStatus *st) {
   }
 }
 
+// pairs into their master triangle's bucket (counts from the narrow phase,
+// offsets from their scan); the counters return to zero.  When the pairs
+// overflowed, the written ones were counted but are not placed: the
+// counters are cleared instead.
 template <typename R>
 __global__ void k_pair_bucket(const Pair<R> *__restrict__ pair, const DevStatus *st, int64_t cap_pairs,
                               int32_t *__restrict__ mp_cnt, const int32_t *__restrict__ mp_off,
-                              long long *__restrict__ mp_key, int pass) {
+                              long long *__restrict__ mp_key, int64_t Tm) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t np = (int64_t)st->n_pairs;
-  if (np > cap_pairs || p >= np) return;
-  int M = pair[p].M;
-  if (pass == 0) {
-    atomicAdd(&mp_cnt[M], 1);
-  } else {
-    int slot = mp_off[M] + atomicSub(&mp_cnt[M], 1) - 1;
-    mp_key[slot] = ((long long)pair[p].T << 32) | (long long)p;
+  if (np > cap_pairs) {
+    for (int64_t i = p; i <= Tm; i += (int64_t)gridDim.x * blockDim.x) mp_cnt[i] = 0;
+    return;
   }
+  if (p >= np) return;
+  int M = pair[p].M;
+  int slot = mp_off[M] + atomicSub(&mp_cnt[M], 1) - 1;
+  mp_key[slot] = ((long long)pair[p].T << 32) | (long long)p;
 }
 
 // deterministic order inside each bucket: every key is ranked among its
@@ -952,37 +959,64 @@ __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full)
   return -1;
 }
 
-// Thread per master triangle with contact pairs: the sum over its pairs in
-// bucket order (sorted by slave triangle) of the master-master sums times
+// Four lanes per master triangle with contact pairs: the sum over its pairs
+// (bucket order: sorted by slave triangle) of the master-master sums times
 // n_T n_T^T - six vertex pairs (00 01 02 11 12 22) of six symmetric entries -
-// and of the gradient sums gm_j n_T (three vertices); a serial sum in that
-// order, so the result is the same on every run.
+// and of the gradient sums gm_j n_T (three vertices).  Lane s of the group
+// sums the pairs s, s + 4, ... in order (their loads issued four at a time),
+// and the four partials are combined by a fixed butterfly, so the result is
+// the same on every run.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ pair,
                                                     const int32_t *__restrict__ mp_off,
                                                     const int32_t *__restrict__ mp_list,
                                                     const R *__restrict__ tri_nrm, int64_t Tm, const DevStatus *st,
                                                     int64_t cap_pairs, R *__restrict__ mtri) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= Tm || (int64_t)st->n_pairs > cap_pairs) return;
-  const int b = mp_off[t], e = mp_off[t + 1];
-  if (b == e) return;
+  const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t t = gt >> 2;
+  const int sub = (int)(gt & 3);
+  const bool live = t < Tm && (int64_t)st->n_pairs <= cap_pairs;
+  const int b = live ? mp_off[t] : 0, e = live ? mp_off[t + 1] : 0;
+  if (__all(b == e)) return;  // wave-uniform: the groups below shuffle
   R h[36], g[9];
   for (int z = 0; z < 36; ++z) h[z] = 0;
   for (int z = 0; z < 9; ++z) g[z] = 0;
-  for (int i = b; i < e; ++i) {
-    const Pair<R> &P = pair[mp_list[i]];
-    const R *nn = tri_nrm + 3 * (int64_t)P.T;
-    const R n0 = nn[0], n1 = nn[1], n2 = nn[2];
-    const R o[6] = {n0 * n0, n0 * n1, n0 * n2, n1 * n1, n1 * n2, n2 * n2};
-    for (int v = 0; v < 6; ++v)
-      for (int c = 0; c < 6; ++c) h[6 * v + c] += P.mm[v] * o[c];
-    for (int m = 0; m < 3; ++m) {
-      g[3 * m + 0] += P.gm[m] * n0;
-      g[3 * m + 1] += P.gm[m] * n1;
-      g[3 * m + 2] += P.gm[m] * n2;
+  for (int i0 = b + sub; i0 < e; i0 += 16) {
+    R mm[4][6], gm[4][3], nn[4][3];
+    int T[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T[k] = i0 + 4 * k < e ? pair[mp_list[i0 + 4 * k]].T : -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (T[k] < 0) continue;
+      const Pair<R> &P = pair[mp_list[i0 + 4 * k]];
+      for (int v = 0; v < 6; ++v) mm[k][v] = P.mm[v];
+      for (int m = 0; m < 3; ++m) gm[k][m] = P.gm[m];
+      for (int d = 0; d < 3; ++d) nn[k][d] = tri_nrm[3 * (int64_t)T[k] + d];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (T[k] < 0) continue;
+      const R n0 = nn[k][0], n1 = nn[k][1], n2 = nn[k][2];
+      const R o[6] = {n0 * n0, n0 * n1, n0 * n2, n1 * n1, n1 * n2, n2 * n2};
+      for (int v = 0; v < 6; ++v)
+        for (int c = 0; c < 6; ++c) h[6 * v + c] += mm[k][v] * o[c];
+      for (int m = 0; m < 3; ++m) {
+        g[3 * m + 0] += gm[k][m] * n0;
+        g[3 * m + 1] += gm[k][m] * n1;
+        g[3 * m + 2] += gm[k][m] * n2;
+      }
     }
   }
+  for (int z = 0; z < 36; ++z) {
+    h[z] += __shfl_xor(h[z], 1, kWave);
+    h[z] += __shfl_xor(h[z], 2, kWave);
+  }
+  for (int z = 0; z < 9; ++z) {
+    g[z] += __shfl_xor(g[z], 1, kWave);
+    g[z] += __shfl_xor(g[z], 2, kWave);
+  }
+  if (b == e || sub != 0) return;
   R *out = mtri + 45 * t;
   for (int z = 0; z < 36; ++z) out[z] = h[z];
   for (int z = 0; z < 9; ++z) out[36 + z] = g[z];
@@ -1713,6 +1747,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.tri_rcnt = b.tri_rcnt;
   na.pair = (Pair<R> *)b.pair;
   na.cap_pairs = c->caps.pairs;
+  na.mp_cnt = b.mp_cnt;
   na.tile_E = b.tile_E;
   na.st = b.status;
   na.features = c->features;
@@ -1737,12 +1772,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const Pair<R> *pr = (const Pair<R> *)b.pair;
   unsigned pb = nblk(c->caps.pairs);
   prof_mark(c, ST_BUCKET, 0);
-  hipLaunchKernelGGL(k_pair_bucket<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.status, c->caps.pairs, b.mp_cnt,
-                     b.mp_off, b.mp_key, 0);
-  e = scan_exclusive(c, b.mp_cnt, b.mp_off, c->Tm + 1);
+  e = scan_exclusive(c, b.mp_cnt, b.mp_off, c->Tm + 1);  // counts written by the narrow phase
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pair_bucket<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.status, c->caps.pairs, b.mp_cnt,
-                     b.mp_off, b.mp_key, 1);
+                     b.mp_off, b.mp_key, c->Tm);
   hipLaunchKernelGGL(k_bucket_rank<R>, dim3(pb), dim3(kThreads), 0, s, pr, b.mp_off, b.mp_key, b.mp_list, b.status,
                      c->caps.pairs);
   prof_mark(c, ST_BUCKET, 1);
@@ -1767,7 +1800,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const bool sums = !c->kinematic && (grad || H) && c->Tm;
   auto mtri = [&](hipStream_t st) {
     prof_mark(c, ST_MTRI, 0);
-    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(c->Tm, kThreads)), dim3(kThreads), 0, st, pr, b.mp_off,
+    hipLaunchKernelGGL(k_mtri<R>, dim3(nblk(4 * c->Tm, kThreads)), dim3(kThreads), 0, st, pr, b.mp_off,
                        b.mp_list, (const R *)b.tri_nrm, c->Tm, b.status, c->caps.pairs, (R *)b.mtri);
     prof_mark(c, ST_MTRI, 1);
   };
