@@ -223,8 +223,9 @@ __device__ inline int cell_coord(const GridEnv &g, float x, int d) {
 // its swept box covers, the master triangles whose swept boxes overlap it
 // (each once: the cell holding the lower corner of the overlap), into an
 // LDS slice; then every lane tests its own point's swept box against that
-// list and runs additive CCD on the overlaps.  A triangle whose list
-// overflows its slice walks the cells point by point instead.
+// list, and the overlaps go through a per-wave queue that runs additive CCD
+// on 64 pairs at a time.  A triangle whose list overflows its slice walks
+// the cells point by point instead.
 constexpr int kAccdPool = 1024;  // LDS list entries per wave, split over the tile's triangles
 
 template <typename R>
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     const float4 *__restrict__ smbox, int64_t cap_items, int64_t total_cells, uint32_t *bits, DevStatus *st) {
   __shared__ int32_t plist[kThreads / kWave][kAccdPool];
   __shared__ int32_t pcnt[kThreads / kWave][kWave];
+  __shared__ int32_t qpt[kThreads / kWave][2 * kWave], qm[kThreads / kWave][2 * kWave];  // pair queue
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int tile_id = blockIdx.x * (kThreads / kWave) + w;
   float amin = INFINITY;
@@ -307,59 +309,110 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
           }
     }
     wave_sync();
-    if (live && g.valid) {
+    // the point's start (relative frame) and displacement, and its swept box
+    const bool pt_ok = live && g.valid;
+    R s0[3] = {0, 0, 0}, dp[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    if (pt_ok) {
       const double *rq = rule + ((ev.rule_n - 1) * 16 + q) * 3;
       const R bs[3] = {R(1) - (R)rq[0] - (R)rq[1], (R)rq[0], (R)rq[1]};
-      R s0[3], dp[3], off[3];
       for (int d = 0; d < 3; ++d) {
         s0[d] = xs[3 * v[0] + d];
         off[d] = bs[1] * (xs[3 * v[1] + d] - s0[d]) + bs[2] * (xs[3 * v[2] + d] - s0[d]);
         dp[d] = bs[0] * dxs[3 * v[0] + d] + bs[1] * dxs[3 * v[1] + d] + bs[2] * dxs[3 * v[2] + d];
       }
-      float lo[3], hi[3];
       for (int d = 0; d < 3; ++d) {
         const R p0 = s0[d] + off[d];
         slack_box((float)p0, (float)(p0 + dp[d]), lo[d], hi[d]);
       }
-      auto pair = [&](int M) {  // the point against master triangle M
-        const float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
-        if (ma.x > hi[0] || mb.x < lo[0] || ma.y > hi[1] || mb.y < lo[1] || ma.z > hi[2] || mb.z < lo[2]) return;
-        ++npairs;
-        R A[3], B[3], C[3], dA[3], dB[3], dC[3];
-        const int64_t w0 = tm[3 * (int64_t)M], w1 = tm[3 * (int64_t)M + 1], w2 = tm[3 * (int64_t)M + 2];
-        for (int d = 0; d < 3; ++d) {
-          A[d] = (xm[3 * w0 + d] - s0[d]) - off[d];
-          B[d] = (xm[3 * w1 + d] - s0[d]) - off[d];
-          C[d] = (xm[3 * w2 + d] - s0[d]) - off[d];
-          dA[d] = dxm ? dxm[3 * w0 + d] : R(0);
-          dB[d] = dxm ? dxm[3 * w1 + d] : R(0);
-          dC[d] = dxm ? dxm[3 * w2 + d] : R(0);
-        }
-        amin = fminf(amin, to_float_down<R>(accd<R>(dp, A, dA, B, dB, C, dC, R(0.1))));
-      };
-      const int n = pcnt[w][j];
-      if (n <= slice) {
-        for (int i = 0; i < n; ++i) pair(plist[w][j * slice + i]);
-      } else if (inside_grid(lo, hi)) {  // overflow: walk the point's own cells
-        int c0[3], c1[3];
-        for (int d = 0; d < 3; ++d) {
-          c0[d] = cell_coord(g, lo[d], d);
-          c1[d] = cell_coord(g, hi[d], d);
-        }
-        for (int z = c0[2]; z <= c1[2]; ++z)
-          for (int y = c0[1]; y <= c1[1]; ++y)
-            for (int x = c0[0]; x <= c1[0]; ++x) {
-              const int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
-              for (int i = cell_start[cell]; i < cell_start[cell + 1]; ++i) {
-                const int M = items[i];
-                const float4 ma = smbox[3 * (int64_t)M];
-                if (cell_coord(g, fmaxf(ma.x, lo[0]), 0) != x || cell_coord(g, fmaxf(ma.y, lo[1]), 1) != y ||
-                    cell_coord(g, fmaxf(ma.z, lo[2]), 2) != z)
-                  continue;
-                pair(M);
-              }
-            }
+    }
+    auto boxes_meet = [&](int M) {
+      const float4 ma = smbox[3 * (int64_t)M], mb = smbox[3 * (int64_t)M + 1];
+      return !(ma.x > hi[0] || mb.x < lo[0] || ma.y > hi[1] || mb.y < lo[1] || ma.z > hi[2] || mb.z < lo[2]);
+    };
+    // additive CCD of a point (given by its frame) against master triangle M
+    auto run = [&](int M, const R ps0[3], const R poff[3], const R pdp[3]) {
+      R A[3], B[3], C[3], dA[3], dB[3], dC[3];
+      const int64_t w0 = tm[3 * (int64_t)M], w1 = tm[3 * (int64_t)M + 1], w2 = tm[3 * (int64_t)M + 2];
+      for (int d = 0; d < 3; ++d) {
+        A[d] = (xm[3 * w0 + d] - ps0[d]) - poff[d];
+        B[d] = (xm[3 * w1 + d] - ps0[d]) - poff[d];
+        C[d] = (xm[3 * w2 + d] - ps0[d]) - poff[d];
+        dA[d] = dxm ? dxm[3 * w0 + d] : R(0);
+        dB[d] = dxm ? dxm[3 * w1 + d] : R(0);
+        dC[d] = dxm ? dxm[3 * w2 + d] : R(0);
       }
+      amin = fminf(amin, to_float_down<R>(accd<R>(pdp, A, dA, B, dB, C, dC, R(0.1))));
+    };
+    // The wave's (point, master triangle) overlaps from the LDS lists are
+    // queued in LDS and run 64 at a time, one pair per lane, so a point with
+    // many overlaps does not hold the rest of the wave; each lane fetches the
+    // queued point's frame from the point's lane by shuffles.  The minimum
+    // does not depend on which lane runs a pair.
+    const int n = pt_ok ? pcnt[w][j] : 0;
+    const bool walk = n > slice;  // list overflowed: this point walks its own cells below
+    const int nl = walk ? 0 : n;
+    int maxn = nl;
+    for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o, kWave));
+    auto drain = [&](int first, int count) {  // every lane calls (the shuffles)
+      const bool act = lane < count;
+      const int p = act ? qpt[w][first + lane] : lane;
+      const int M = act ? qm[w][first + lane] : 0;
+      R ps0[3], poff[3], pdp[3];
+      for (int d = 0; d < 3; ++d) {
+        ps0[d] = __shfl(s0[d], p, kWave);
+        poff[d] = __shfl(off[d], p, kWave);
+        pdp[d] = __shfl(dp[d], p, kWave);
+      }
+      if (act) run(M, ps0, poff, pdp);
+    };
+    const uint64_t one = 1;
+    int qn = 0;  // queued pairs (wave-uniform), < kWave between rounds
+    for (int r = 0; r < maxn; ++r) {
+      int M = 0;
+      bool hit = false;
+      if (r < nl) {
+        M = plist[w][j * slice + r];
+        hit = boxes_meet(M);
+      }
+      const uint64_t hm = __ballot(hit);
+      if (hit) {
+        const int pos = qn + __popcll(hm & ((one << lane) - 1));
+        qpt[w][pos] = lane;
+        qm[w][pos] = M;
+        ++npairs;
+      }
+      qn += __popcll(hm);
+      if (qn >= kWave) {
+        wave_sync();
+        qn -= kWave;
+        drain(qn, kWave);
+        wave_sync();  // the drained entries are read before the next round overwrites them
+      }
+    }
+    wave_sync();
+    if (qn > 0) drain(0, qn);
+    if (walk && inside_grid(lo, hi)) {  // overflow: walk the point's own cells
+      int c0[3], c1[3];
+      for (int d = 0; d < 3; ++d) {
+        c0[d] = cell_coord(g, lo[d], d);
+        c1[d] = cell_coord(g, hi[d], d);
+      }
+      for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+          for (int x = c0[0]; x <= c1[0]; ++x) {
+            const int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
+            for (int i = cell_start[cell]; i < cell_start[cell + 1]; ++i) {
+              const int M = items[i];
+              const float4 ma = smbox[3 * (int64_t)M];
+              if (cell_coord(g, fmaxf(ma.x, lo[0]), 0) != x || cell_coord(g, fmaxf(ma.y, lo[1]), 1) != y ||
+                  cell_coord(g, fmaxf(ma.z, lo[2]), 2) != z)
+                continue;
+              if (!boxes_meet(M)) continue;
+              ++npairs;
+              run(M, s0, off, dp);
+            }
+          }
     }
   }
   // pair count: wave sums, one atomic per block (with the minimum)
