@@ -424,11 +424,13 @@ __global__ __launch_bounds__(kWave * 4) void k_narrow_f64(NarrowArgs<double> a) 
 // in the projected master triangle, gap g = sum_j beta^m_j h_j with h_j the
 // master vertices' heights above T's plane (= n_T . (x_m - x_s), Eq. (gap)),
 // weight w = 2 A_sub W_q with A_sub the sub-triangle's share of T's rest
-// area.  One wave per work tile, the tile's triangles in turn, lane = one
-// candidate pair (chunks of 64): a counting pass sizes the triangle's
-// records and pairs (one allocation each, so they stay contiguous and in
-// candidate order), a writing pass recomputes and writes them.  Per
-// triangle and per pair sums, energy: lane order and fixed butterflies.
+// area.  One wave per work tile, the tile's triangles in turn, candidate
+// pairs in chunks of 64: a lane projects and clips one pair, then the
+// chunk's (pair, sub-triangle, rule point) items are spread over the lanes.
+// A counting pass sizes the triangle's records and pairs (one allocation,
+// so they stay contiguous and in candidate order), a writing pass
+// recomputes and writes them.  Per triangle and per pair sums, energy:
+// fixed lane orders, segmented scans and butterflies.
 constexpr int kMortarChunks = 8;  // candidates per slave triangle <= 512 (the broad phase's set)
 
 template <typename R>
@@ -564,11 +566,16 @@ __device__ inline bool clip_seg(const R qa[2], const R qb[2], R &t0, R &t1) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
-  __shared__ R poly[2][6][2][kWave];
+__device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
+  __shared__ R poly[2][6][2][kWave];                   // clip buffers (lane-minor); see fr below
   __shared__ uint64_t maskbuf[kMortarChunks][kWave];   // accepted face samples of each lane's pair
   __shared__ uint32_t fmaskbuf[kMortarChunks][kWave];  // accepted edge (bit 4k + j) / point (bit 12 + k) samples
   __shared__ uint8_t oflag[kMortarChunks * kWave];     // candidate i of the triangle is opposing
+  __shared__ uint64_t accw[kWave];                     // accepted face items of a chunk, 64 per word
+  __shared__ int32_t istart[kWave + 1];                // first face item of each candidate lane of a chunk
+  __shared__ int32_t rstart[kWave];                    // first record of each candidate lane (from the triangle's)
+  __shared__ int32_t candM[kWave];                     // master triangle of each candidate lane
+  __shared__ R pacc[18][kWave];                        // each candidate lane's pair sums (mm 6, sm 9, gm 3)
   const int lane = threadIdx.x;
   const int tile_id = xcd_block(blockIdx.x, gridDim.x);
   if (tile_id >= a.n_tiles) return;
@@ -581,6 +588,9 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   const double *gl = a.rule + kGaussOff + (ev.rule_n - 1) * 4 * 2;
   const bool features = a.features;
   R(*buf)[6][2][kWave] = poly;
+  // once a lane's clip is done its column of buffer 1 is free: it holds the
+  // pair's frame there, fr[z][lane] = q0 (2), qi (4), h (3)
+  R(*fr)[kWave] = reinterpret_cast<R(*)[kWave]>(&poly[1][0][0][0]);
   double E = 0.0;
   const uint64_t below = (1ull << lane) - 1;
   for (int j = 0; j < tl.count; ++j) {
@@ -678,44 +688,123 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
       return fm;
     };
 
+    // The face samples of a chunk (up to 64 candidate pairs) are spread
+    // over the lanes: each candidate lane clips its pair (polygon in buffer
+    // 0, frame in fr) and owns (m - 2) nq items (sub-triangle s, rule point
+    // q; item index (s - 1) nq + q within the pair, the bit of its mask);
+    // the items of all pairs, in candidate order, are taken 64 at a time,
+    // the candidate of an item found by binary search in istart.  Returns
+    // the chunk's item count.  Every lane calls.
+    auto chunk_items = [&](const MortarPair<R> &P, bool clip) -> int {
+      int m = 0;
+      if (clip) {
+        m = mortar_clip(P, buf, lane);
+        fr[0][lane] = P.q[0][0];
+        fr[1][lane] = P.q[0][1];
+        fr[2][lane] = P.qi[0][0];
+        fr[3][lane] = P.qi[0][1];
+        fr[4][lane] = P.qi[1][0];
+        fr[5][lane] = P.qi[1][1];
+        fr[6][lane] = P.h[0];
+        fr[7][lane] = P.h[1];
+        fr[8][lane] = P.h[2];
+      }
+      const int ni = m >= 3 ? (m - 2) * nq : 0;
+      int incl = ni;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int v = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += v;
+      }
+      istart[lane] = incl - ni;
+      if (lane == kWave - 1) istart[kWave] = incl;
+      wave_sync();
+      return __shfl(incl, kWave - 1, kWave);
+    };
+    auto item_of = [&](int f, int &cl, int &s, int &qq) -> int {  // f < the chunk's item count
+      int lo = 0, hi = kWave - 1;  // the last lane whose items start at or before f
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (istart[mid] <= f) lo = mid;
+        else hi = mid - 1;
+      }
+      cl = lo;
+      const int local = f - istart[lo];
+      s = local / nq + 1;
+      qq = local - (s - 1) * nq;
+      return local;
+    };
+    // sub-triangle s of candidate lane cl's polygon at rule point qq: slave
+    // point (u, v), master barycentrics b1, b2, gap, twice the sub-triangle's
+    // (u, v) area; false if the sub-triangle is degenerate
+    auto face = [&](int cl, int s, int qq, R &u, R &v, R &b1, R &b2, R &g, R &a2) -> bool {
+      const int s1i = s < 5 ? s : 4, s2i = s + 1 < 6 ? s + 1 : 5;  // in-range LDS reads
+      const R Au = buf[0][0][0][cl], Av = buf[0][0][1][cl];
+      const R Bu = buf[0][s1i][0][cl] - Au, Bv = buf[0][s1i][1][cl] - Av;
+      const R Cu = buf[0][s2i][0][cl] - Au, Cv = buf[0][s2i][1][cl] - Av;
+      const R cr = Bu * Cv - Bv * Cu;
+      if (cr == R(0)) return false;
+      const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1];
+      u = Au + xi * Bu + eta * Cu;
+      v = Av + xi * Bv + eta * Cv;
+      const R yu = u - fr[0][cl], yv = v - fr[1][cl];
+      b1 = fr[2][cl] * yu + fr[3][cl] * yv;
+      b2 = fr[4][cl] * yu + fr[5][cl] * yv;
+      g = (R(1) - b1 - b2) * fr[6][cl] + b1 * fr[7][cl] + b2 * fr[8][cl];
+      a2 = fabs(cr);
+      return true;
+    };
+
     // ---- counting pass: accepted samples per candidate pair (bit masks)
     int nrec = 0, npair = 0;
     bool pen = false;
     for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
       const int ci = ch * kWave + lane;
-      uint64_t mask = 0;
+      MortarPair<R> P;
+      P.ok = false;
+      P.opposing = false;
+      int M = -1;
       uint32_t fmask = 0;
       if (ci < cn) {
-        const int M = a.cand[cb + ci];
-        const MortarPair<R> P = pair_of(M);
-        if (P.ok) {
-          const int m = mortar_clip(P, buf, lane);
-          for (int s = 1; s + 1 < m; ++s) {
-            const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
-            const R Bu = buf[0][s][0][lane] - Au, Bv = buf[0][s][1][lane] - Av;
-            const R Cu = buf[0][s + 1][0][lane] - Au, Cv = buf[0][s + 1][1][lane] - Av;
-            if (Bu * Cv - Bv * Cu == R(0)) continue;
-            for (int qq = 0; qq < nq; ++qq) {
-              const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1];
-              const R u = Au + xi * Bu + eta * Cu, v = Av + xi * Bv + eta * Cv;
-              const R yu = u - P.q[0][0], yv = v - P.q[0][1];
-              const R b1 = P.qi[0][0] * yu + P.qi[0][1] * yv, b2 = P.qi[1][0] * yu + P.qi[1][1] * yv;
-              const R g = (R(1) - b1 - b2) * P.h[0] + b1 * P.h[1] + b2 * P.h[2];
-              if (g > R(0) && g < eps) mask |= 1ull << ((s - 1) * nq + qq);
-              else if (g > -eps && g <= R(0)) pen = true;
-            }
+        M = a.cand[cb + ci];
+        P = pair_of(M);
+        if (features && P.opposing) fmask = feature_mask(P, M, pen);
+      }
+      const int tot = chunk_items(P, P.ok);
+      for (int f0 = 0; f0 < tot; f0 += kWave) {
+        const int f = f0 + lane;
+        bool acc = false;
+        if (f < tot) {
+          int cl, s, qq;
+          item_of(f, cl, s, qq);
+          R u, v, b1, b2, g, a2;
+          if (face(cl, s, qq, u, v, b1, b2, g, a2)) {
+            if (g > R(0) && g < eps) acc = true;
+            else if (g > -eps && g <= R(0)) pen = true;
           }
         }
-        if (features && P.opposing) fmask = feature_mask(P, M, pen);
+        const uint64_t am = __ballot(acc);
+        if (lane == 0) accw[f0 / kWave] = am;
+      }
+      wave_sync();
+      uint64_t mask = 0;  // this lane's pair: bits [istart, istart + ni) of the chunk's words
+      {
+        const int i0 = istart[lane], ni = istart[lane + 1] - i0;
+        if (ni > 0) {
+          const int w0 = i0 >> 6, sh = i0 & 63;
+          mask = accw[w0] >> sh;
+          if (sh > 0 && sh + ni > 64) mask |= accw[w0 + 1] << (64 - sh);
+          if (ni < 64) mask &= (1ull << ni) - 1;
+        }
       }
       maskbuf[ch][lane] = mask;
       fmaskbuf[ch][lane] = fmask;
       const int cntl = __popcll(mask) + __popc(fmask);
       const uint64_t pm = __ballot(cntl > 0);
       npair += __popcll(pm);
-      int tot = cntl;
-      for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
-      nrec += tot;
+      int tot_r = cntl;
+      for (int o = 32; o > 0; o >>= 1) tot_r += __shfl_xor(tot_r, o, kWave);
+      nrec += tot_r;
+      wave_sync();  // the chunk's polygons, frames and words are reused by the next
     }
     if (__any(pen) && lane == 0) set_error(a.st, GMCP_E_PENETRATION, (unsigned long long)T);
     if (nchunk > kMortarChunks && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
@@ -743,63 +832,40 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
     if (nrec == 0 || !pair_ok) continue;
 
     // ---- writing pass: exactly the samples of the masks, so the records
-    // written always fill the allocated range
+    // written always fill the allocated range.  A pair's records are its
+    // face samples in item order, then its edge / point samples.
     R ts_[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // c2 bs_a bs_b (00 01 02 11 12 22), c1 bs_a
-    unsigned long long roff = rbase, poff = pbase;
-    for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
-      const int ci = ch * kWave + lane;
-      const uint64_t mask = maskbuf[ch][lane];
-      const uint32_t fmask = fmaskbuf[ch][lane];
-      const int cntl = __popcll(mask) + __popc(fmask);
-      int incl = cntl;
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int v = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += v;
-      }
-      const uint64_t pm = __ballot(cntl > 0);
-      unsigned long long r = roff + (unsigned long long)(incl - cntl);
-      const unsigned long long pslot = poff + __popcll(pm & below);
-      roff += __shfl(incl, kWave - 1, kWave);
-      poff += __popcll(pm);
-      if (cntl == 0) continue;
-      const int M = a.cand[cb + ci];
-      const MortarPair<R> P = pair_of(M);
-      Pair<R> pr;
-      pr.T = T;
-      pr.M = M;
-      for (int z = 0; z < 6; ++z) pr.mm[z] = 0;
-      for (int z = 0; z < 9; ++z) pr.sm[z] = 0;
-      for (int z = 0; z < 3; ++z) pr.gm[z] = 0;
-      // one active sample: slave point (u, v), master coefficients on M's
-      // vertices, gap, kappa_q w gamma
-      auto emit = [&](R u, R v, const R bm[3], R graw, R kw, R kap, R gam) {
-        // the counting pass accepted 0 < g < eps; a recomputation that rounds
-        // differently is clamped into the band
-        const R g = fmin(fmax(graw, eps * R(1e-6)), eps);
-        const R dd = g - eps;
-        const R L = log1p_r<R>(dd / eps);
-        const R B = -dd * dd * L;
-        const R B1 = -R(2) * dd * L - dd * dd / g;
-        const R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
-        const R c1 = kw * B1, c2 = fmax(kw * B2, R(0));
-        E += (double)(kw * B);
-        const R bs[3] = {R(1) - u - v, u, v};
-        ts_[0] += c2 * bs[0] * bs[0];
-        ts_[1] += c2 * bs[0] * bs[1];
-        ts_[2] += c2 * bs[0] * bs[2];
-        ts_[3] += c2 * bs[1] * bs[1];
-        ts_[4] += c2 * bs[1] * bs[2];
-        ts_[5] += c2 * bs[2] * bs[2];
-        for (int z = 0; z < 3; ++z) ts_[6 + z] += c1 * bs[z];
-        pr.mm[0] += c2 * bm[0] * bm[0];
-        pr.mm[1] += c2 * bm[0] * bm[1];
-        pr.mm[2] += c2 * bm[0] * bm[2];
-        pr.mm[3] += c2 * bm[1] * bm[1];
-        pr.mm[4] += c2 * bm[1] * bm[2];
-        pr.mm[5] += c2 * bm[2] * bm[2];
-        for (int s2 = 0; s2 < 3; ++s2)
-          for (int m2 = 0; m2 < 3; ++m2) pr.sm[3 * s2 + m2] -= c2 * bs[s2] * bm[m2];
-        for (int m2 = 0; m2 < 3; ++m2) pr.gm[m2] += c1 * bm[m2];
+    // one active sample: the record at r, the triangle sums and energy, and
+    // the pair sums' terms pt (mm 6, sm 9, gm 3)
+    auto term = [&](unsigned long long r, int M, R u, R v, const R bm[3], R graw, R kw, R kap, R gam, R pt[18]) {
+      // the counting pass accepted 0 < g < eps; a recomputation that rounds
+      // differently is clamped into the band
+      const R g = fmin(fmax(graw, eps * R(1e-6)), eps);
+      const R dd = g - eps;
+      const R L = log1p_r<R>(dd / eps);
+      const R B = -dd * dd * L;
+      const R B1 = -R(2) * dd * L - dd * dd / g;
+      const R B2 = -R(2) * L - R(4) * dd / g + dd * dd / (g * g);
+      const R c1 = kw * B1, c2 = fmax(kw * B2, R(0));
+      E += (double)(kw * B);
+      const R bs[3] = {R(1) - u - v, u, v};
+      ts_[0] += c2 * bs[0] * bs[0];
+      ts_[1] += c2 * bs[0] * bs[1];
+      ts_[2] += c2 * bs[0] * bs[2];
+      ts_[3] += c2 * bs[1] * bs[1];
+      ts_[4] += c2 * bs[1] * bs[2];
+      ts_[5] += c2 * bs[2] * bs[2];
+      for (int z = 0; z < 3; ++z) ts_[6 + z] += c1 * bs[z];
+      pt[0] = c2 * bm[0] * bm[0];
+      pt[1] = c2 * bm[0] * bm[1];
+      pt[2] = c2 * bm[0] * bm[2];
+      pt[3] = c2 * bm[1] * bm[1];
+      pt[4] = c2 * bm[1] * bm[2];
+      pt[5] = c2 * bm[2] * bm[2];
+      for (int s2 = 0; s2 < 3; ++s2)
+        for (int m2 = 0; m2 < 3; ++m2) pt[6 + 3 * s2 + m2] = -(c2 * bs[s2] * bm[m2]);
+      for (int m2 = 0; m2 < 3; ++m2) pt[15 + m2] = c1 * bm[m2];
+      if (write_rec) {
         Rec<R> rc;
         rc.k = -1;
         rc.M = M;
@@ -817,50 +883,115 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
         rc.s2 = v;
         rc.kwg = kw;
         rc.pad = 0;
-        if (write_rec) a.rec[r++] = rc;
-      };
-      if (mask) {
-        mortar_clip(P, buf, lane);
-        for (uint64_t bits = mask; bits; bits &= bits - 1) {
-          const int idx = __ffsll((unsigned long long)bits) - 1;
-          const int s = idx / nq + 1, qq = idx - (s - 1) * nq;
-          const int s1i = s < 5 ? s : 4, s2i = s + 1 < 6 ? s + 1 : 5;  // in-range LDS reads
-          const R Au = buf[0][0][0][lane], Av = buf[0][0][1][lane];
-          const R Bu = buf[0][s1i][0][lane] - Au, Bv = buf[0][s1i][1][lane] - Av;
-          const R Cu = buf[0][s2i][0][lane] - Au, Cv = buf[0][s2i][1][lane] - Av;
-          const R a2 = fabs(Bu * Cv - Bv * Cu);  // twice the (u, v) area
-          const R xi = (R)rule[3 * qq], eta = (R)rule[3 * qq + 1], wq = (R)rule[3 * qq + 2];
-          const R u = Au + xi * Bu + eta * Cu, v = Av + xi * Bv + eta * Cv;
-          const R yu = u - P.q[0][0], yv = v - P.q[0][1];
-          const R b1 = P.qi[0][0] * yu + P.qi[0][1] * yv, b2 = P.qi[1][0] * yu + P.qi[1][1] * yv;
-          const R bm[3] = {R(1) - b1 - b2, b1, b2};
-          const R gam = deltaT > R(0) ? hermite(fmin(bm[0], fmin(bm[1], bm[2])), deltaT) : R(1);
-          emit(u, v, bm, bm[0] * P.h[0] + bm[1] * P.h[1] + bm[2] * P.h[2], kappa * R(2) * (a2 * area) * wq * gam,
-               kappa, gam);
+        a.rec[r] = rc;
+      }
+    };
+    unsigned long long roff = rbase, poff = pbase;
+    for (int ch = 0; ch < nchunk && ch < kMortarChunks; ++ch) {
+      const int ci = ch * kWave + lane;
+      const uint64_t mask = maskbuf[ch][lane];
+      const uint32_t fmask = fmaskbuf[ch][lane];
+      const int cntl = __popcll(mask) + __popc(fmask);
+      int incl = cntl;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int v = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += v;
+      }
+      const uint64_t pm = __ballot(cntl > 0);
+      const unsigned long long r0 = roff + (unsigned long long)(incl - cntl);  // this pair's first record
+      const unsigned long long pslot = poff + __popcll(pm & below);
+      roff += __shfl(incl, kWave - 1, kWave);
+      poff += __popcll(pm);
+      int M = -1;
+      MortarPair<R> P;
+      P.ok = false;
+      P.opposing = false;
+      if (cntl > 0) {
+        M = a.cand[cb + ci];
+        if (mask) P = pair_of(M);
+      }
+      candM[lane] = M;
+      rstart[lane] = (int32_t)(r0 - rbase);
+      const int tot = chunk_items(P, mask != 0);  // pairs with face samples only
+      // face samples over the lanes; each pair's sums are segmented scans
+      // over the lanes of its items (items of a pair are contiguous), taken
+      // by the pair's own lane from the last of them: fixed order
+      for (int z = 0; z < 18; ++z) pacc[z][lane] = R(0);
+      for (int f0 = 0; f0 < tot; f0 += kWave) {
+        const int f = f0 + lane;
+        int seg = kWave + lane;  // idle lanes: segments of their own
+        R pt[18];
+        for (int z = 0; z < 18; ++z) pt[z] = R(0);
+        if (f < tot) {
+          int cl, s, qq;
+          const int local = item_of(f, cl, s, qq);
+          seg = cl;
+          const uint64_t cm = maskbuf[ch][cl];
+          if ((cm >> local) & 1ull) {
+            R u, v, b1, b2, g, a2;
+            face(cl, s, qq, u, v, b1, b2, g, a2);  // accepted: not degenerate
+            const R bm[3] = {R(1) - b1 - b2, b1, b2};
+            const R gam = deltaT > R(0) ? hermite(fmin(bm[0], fmin(bm[1], bm[2])), deltaT) : R(1);
+            const R wq = (R)rule[3 * qq + 2];
+            const unsigned long long r = rbase + (unsigned long long)rstart[cl] + __popcll(cm & ((1ull << local) - 1));
+            term(r, candM[cl], u, v, bm, bm[0] * fr[6][cl] + bm[1] * fr[7][cl] + bm[2] * fr[8][cl],
+                 kappa * R(2) * (a2 * area) * wq * gam, kappa, gam, pt);
+          }
+        }
+        for (int d = 1; d < kWave; d <<= 1) {
+          const int su = __shfl_up(seg, d, kWave);
+          const bool take = lane >= d && su == seg;
+          for (int z = 0; z < 18; ++z) {
+            const R t = __shfl_up(pt[z], d, kWave);
+            if (take) pt[z] += t;
+          }
+        }
+        const int i0 = istart[lane], i1 = istart[lane + 1];
+        const bool mine = i1 > i0 && i1 > f0 && i0 < f0 + kWave;
+        const int src = mine ? min(i1, f0 + kWave) - 1 - f0 : lane;
+        for (int z = 0; z < 18; ++z) {
+          const R t = __shfl(pt[z], src, kWave);
+          if (mine) pacc[z][lane] += t;
         }
       }
-      for (uint32_t bits = fmask; bits; bits &= bits - 1) {
-        const int idx = __ffs(bits) - 1;
-        R bm[3] = {0, 0, 0};
-        if (idx < 12) {  // edge k, Gauss point jj
-          const int k = idx >> 2, jj = idx & 3, k1 = k == 2 ? 0 : k + 1;
-          R t0, t1;
-          clip_seg(P.q[k], P.q[k1], t0, t1);
-          const R eta = t0 + (t1 - t0) * (R)gl[2 * jj];
-          bm[k] = R(1) - eta;
-          bm[k1] = eta;
-          const R u = P.q[k][0] + eta * (P.q[k1][0] - P.q[k][0]), v = P.q[k][1] + eta * (P.q[k1][1] - P.q[k][1]);
-          const R gam = delta_e > R(0) ? hermite(eta, delta_e) * hermite(R(1) - eta, delta_e) : R(1);
-          const R w = P.len[k] * (t1 - t0) * (R)gl[2 * jj + 1];
-          emit(u, v, bm, (R(1) - eta) * P.h[k] + eta * P.h[k1], kappa_e * w * gam, kappa_e, gam);
-        } else {  // vertex k: one point sample, weight 1
-          const int k = idx - 12;
-          bm[k] = R(1);
-          emit(P.q[k][0], P.q[k][1], bm, P.h[k], kappa_p, kappa_p, R(1));
+      if (cntl > 0) {
+        Pair<R> pr;
+        pr.T = T;
+        pr.M = M;
+        for (int z = 0; z < 6; ++z) pr.mm[z] = pacc[z][lane];
+        for (int z = 0; z < 9; ++z) pr.sm[z] = pacc[6 + z][lane];
+        for (int z = 0; z < 3; ++z) pr.gm[z] = pacc[15 + z][lane];
+        if (fmask) {
+          const MortarPair<R> Q = pair_of(M);
+          unsigned long long r = r0 + __popcll(mask);
+          for (uint32_t bits = fmask; bits; bits &= bits - 1) {
+            const int idx = __ffs(bits) - 1;
+            R bm[3] = {0, 0, 0}, pt[18];
+            if (idx < 12) {  // edge k, Gauss point jj
+              const int k = idx >> 2, jj = idx & 3, k1 = k == 2 ? 0 : k + 1;
+              R t0, t1;
+              clip_seg(Q.q[k], Q.q[k1], t0, t1);
+              const R eta = t0 + (t1 - t0) * (R)gl[2 * jj];
+              bm[k] = R(1) - eta;
+              bm[k1] = eta;
+              const R u = Q.q[k][0] + eta * (Q.q[k1][0] - Q.q[k][0]), v = Q.q[k][1] + eta * (Q.q[k1][1] - Q.q[k][1]);
+              const R gam = delta_e > R(0) ? hermite(eta, delta_e) * hermite(R(1) - eta, delta_e) : R(1);
+              const R w = Q.len[k] * (t1 - t0) * (R)gl[2 * jj + 1];
+              term(r++, M, u, v, bm, (R(1) - eta) * Q.h[k] + eta * Q.h[k1], kappa_e * w * gam, kappa_e, gam, pt);
+            } else {  // vertex k: one point sample, weight 1
+              const int k = idx - 12;
+              bm[k] = R(1);
+              term(r++, M, Q.q[k][0], Q.q[k][1], bm, Q.h[k], kappa_p, kappa_p, R(1), pt);
+            }
+            for (int z = 0; z < 6; ++z) pr.mm[z] += pt[z];
+            for (int z = 0; z < 9; ++z) pr.sm[z] += pt[6 + z];
+            for (int z = 0; z < 3; ++z) pr.gm[z] += pt[15 + z];
+          }
         }
+        a.pair[pslot] = pr;
+        atomicAdd(&a.mp_cnt[M], 1);
       }
-      a.pair[pslot] = pr;
-      atomicAdd(&a.mp_cnt[M], 1);
+      wave_sync();  // the chunk's polygons, frames and tables are reused by the next
     }
     for (int z = 0; z < 9; ++z)
       for (int o = 32; o > 0; o >>= 1) ts_[z] += __shfl_xor(ts_[z], o, kWave);
@@ -872,6 +1003,12 @@ __global__ __launch_bounds__(kWave) void k_mortar(NarrowArgs<R> a) {
   for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, kWave);
   if (lane == 0) a.tile_E[tile_id] = E;
 }
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_mortar_f32(
+    NarrowArgs<float> a) {
+  mortar_body<float>(a);
+}
+__global__ __launch_bounds__(kWave) void k_mortar_f64(NarrowArgs<double> a) { mortar_body<double>(a); }
 
 // ---------------------------------------------------- pairs by master tri
 // pass 0: count pairs per master triangle; pass 1: place (slave triangle,
@@ -1757,7 +1894,10 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   prof_mark(c, ST_NARROW, 0);
   if (c->n_tiles) {
     if (c->mortar) {
-      hipLaunchKernelGGL(k_mortar<R>, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
+      if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL(k_mortar_f32, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
+      else
+        hipLaunchKernelGGL(k_mortar_f64, dim3((unsigned)c->n_tiles), dim3(kWave), 0, s, na);
       hipLaunchKernelGGL(k_mortar_counts, dim3(1), dim3(64), 0, s, b.status);
     } else
       if constexpr (sizeof(R) == 4)
