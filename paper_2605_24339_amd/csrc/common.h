@@ -21,7 +21,7 @@ constexpr int kWave = 64;
 constexpr int kMaxRule = 4;            // n <= 4  => <= 16 samples per triangle
 constexpr int kRuleDoubles = kMaxRule * 16 * 3 + kMaxRule * 4 * 2;  // 2D rules, then 1D Gauss-Legendre
 constexpr int kGaussOff = kMaxRule * 16 * 3;
-constexpr int kQueryBlocks = 2048;  // fixed grid of the list-walking query (8 blocks of 4 waves per CU)
+constexpr int kQueryBlocks = 2048;  // largest grid of the list-walking query (its per-block candidate slots)
 constexpr int kTilePerBlock = 4;       // narrow phase: 4 waves, one tile each
 
 // ---------------------------------------------------------------- status
@@ -171,11 +171,25 @@ struct gmcp_ctx {
   bool samples_built, broadphase_done, assembled;
   bool swept_ready;  // gmcp_ccd_swept enqueued, gmcp_ccd_finish not yet
   int query_blocks;  // grid of the last query (its entries of b.cand_blk are valid)
+  int n_cu;          // compute units of the context's device
   gmcp::Buffers b;
   size_t scan_tmp_elems;
 };
 
 namespace gmcp {
+
+// Blocks of `kernel` (threads per block, dynamic LDS bytes) resident on the
+// device at once, at least one per compute unit.  A kernel that walks a
+// work list with a fixed grid sizes it by this when it has the device to
+// itself: blocks beyond it would start only as the first ones finish and
+// walk their share of the list alone.
+template <typename K>
+inline int64_t resident_blocks(const gmcp_ctx *c, K kernel, int threads, size_t lds) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return (int64_t)per_cu * (c->n_cu > 0 ? c->n_cu : 1);
+}
 
 // ------------------------------------------------------------ launchers
 // each returns hipSuccess or the launch error

@@ -328,6 +328,14 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->assembled = false;
   c->swept_ready = false;
   c->query_blocks = 0;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      c->n_cu = ncu;
+    else
+      c->n_cu = 1;
+  }
   plan_workspace(s, *caps, (char *)workspace, &c->b, &c->scan_tmp_elems);
 
   // ---- topology back to the host

@@ -296,9 +296,11 @@ class Context:
         """One pass of the whole hot path: broad phase, assembly (energy,
         gradient, BSR Hessian), step bound.  Unchecked and not profiled, the
         step bound's swept part (grid + additive CCD, independent of the
-        assembly) runs on a second stream, forked from and joined back into
-        the current one, so it overlaps the broad phase and the assembly (also
-        inside a captured graph)."""
+        assembly) runs on a second stream, forked from the current one after
+        the broad phase and joined back before the final bound, so it overlaps
+        the assembly (also inside a captured graph); the broad phase, whose
+        query walks its list with a grid sized to the whole device, runs
+        alone."""
         if check or self._profiling:
             self.broadphase(xs, xm, check=check)
             A = self.assemble(xs, xm, check=check)
@@ -307,10 +309,10 @@ class Context:
         main = torch.cuda.current_stream(self.device)
         if self._side is None:
             self._side = torch.cuda.Stream(self.device)  # default priority
+        self.broadphase(xs, xm, check=False)
         self._side.wait_stream(main)
         with torch.cuda.stream(self._side):
             self.ccd_swept(xs, xm, dxs, dxm)
-        self.broadphase(xs, xm, check=False)
         A = self.assemble(xs, xm, check=False)
         main.wait_stream(self._side)
         alpha = self.ccd_finish(dxs, dxm)
