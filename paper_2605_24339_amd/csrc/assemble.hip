@@ -1004,10 +1004,7 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
   if (lane == 0) a.tile_E[tile_id] = E;
 }
 
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_mortar_f32(
-    NarrowArgs<float> a) {
-  mortar_body<float>(a);
-}
+__global__ __launch_bounds__(kWave) void k_mortar_f32(NarrowArgs<float> a) { mortar_body<float>(a); }
 __global__ __launch_bounds__(kWave) void k_mortar_f64(NarrowArgs<double> a) { mortar_body<double>(a); }
 
 // ---------------------------------------------------- pairs by master tri

@@ -713,10 +713,10 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   prof_mark(c, ST_QUERY_PRE, 1);
   // the wave kernels walk the query list with a fixed grid, all of it
   // resident at once
-  const int64_t qb = std::min<int64_t>(
-      (c->Ts + kQueryWaves - 1) / kQueryWaves,
-      std::min<int64_t>(kQueryBlocks, sizeof(R) == 4 ? resident_blocks(c, k_query_f32, kThreads, 0)
-                                                     : resident_blocks(c, k_query_f64, kThreads, 0)));
+  if (c->query_grid_max == 0)
+    c->query_grid_max = std::min<int64_t>(kQueryBlocks, sizeof(R) == 4 ? resident_blocks(c, k_query_f32, kThreads, 0)
+                                                                      : resident_blocks(c, k_query_f64, kThreads, 0));
+  const int64_t qb = std::min<int64_t>((c->Ts + kQueryWaves - 1) / kQueryWaves, c->query_grid_max);
   const dim3 qgrid((unsigned)(qb > 0 ? qb : 1));
   prof_mark(c, ST_QUERY_COUNT, 0);
   c->query_blocks = c->Ts ? (int)qgrid.x : 0;

@@ -172,6 +172,7 @@ struct gmcp_ctx {
   bool swept_ready;  // gmcp_ccd_swept enqueued, gmcp_ccd_finish not yet
   int query_blocks;  // grid of the last query (its entries of b.cand_blk are valid)
   int n_cu;          // compute units of the context's device
+  int64_t query_grid_max;  // resident query blocks (0 until the first broad phase)
   gmcp::Buffers b;
   size_t scan_tmp_elems;
 };

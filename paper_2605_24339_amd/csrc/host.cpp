@@ -328,6 +328,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->assembled = false;
   c->swept_ready = false;
   c->query_blocks = 0;
+  c->query_grid_max = 0;
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
