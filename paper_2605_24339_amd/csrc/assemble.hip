@@ -1079,7 +1079,12 @@ struct RowArgs {
 };
 
 constexpr int kRowWaves = 2;
-constexpr int kRowBlocks = 4096;  // fixed grid of the list-walking row kernels
+// fixed grids of the list-walking row kernels, many times the blocks resident
+// at once: a block's share of the list is short, so blocks that start late
+// (the device is shared with the other stream's kernels) finish soon after
+// the rest
+constexpr int kRowBlocks = 65536;    // light rows
+constexpr int kHeavyBlocks = 2048;   // heavy rows (large LDS tables, few resident)
 
 // slot of column `col` in an open-addressing table of `slots` (power of 2)
 __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full) {
@@ -1952,7 +1957,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   // small LDS tables, heavy rows with tables of up to 4096 slots
   const int64_t rneed = (c->V + nw - 1) / nw;
   const dim3 rgrid((unsigned)(rneed < kRowBlocks ? (rneed > 0 ? rneed : 1) : kRowBlocks));
-  const dim3 hgrid(256);
+  const dim3 hgrid(kHeavyBlocks);
   const int32_t *light = b.rlist, *heavy = b.rlist + c->V;
   const int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
