@@ -928,8 +928,8 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
           seg = cl;
           const uint64_t cm = maskbuf[ch][cl];
           if ((cm >> local) & 1ull) {
-            R u, v, b1, b2, g, a2;
-            face(cl, s, qq, u, v, b1, b2, g, a2);  // accepted: not degenerate
+            R u = 0, v = 0, b1 = 0, b2 = 0, g = 0, a2 = 0;  // a degenerate item (never accepted) weighs 0
+            face(cl, s, qq, u, v, b1, b2, g, a2);
             const R bm[3] = {R(1) - b1 - b2, b1, b2};
             const R gam = deltaT > R(0) ? hermite(fmin(bm[0], fmin(bm[1], bm[2])), deltaT) : R(1);
             const R wq = (R)rule[3 * qq + 2];
