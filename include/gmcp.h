@@ -314,7 +314,7 @@ int gmcp_profile_read(gmcp_ctx *ctx, double *ms, int64_t *count);
 
 /*
  * Synchronises and writes host out[4] for the last assembly with a Hessian:
- * BSR rows processed as light rows (at most 256 contributions, small LDS
+ * BSR rows processed as light rows (at most 128 contributions, small LDS
  * tables), heavy rows, and the blocks written by each class (counted on the
  * host from row_ptr, the [V+1] device array of that assembly's BSR).  For
  * per-kernel byte accounting of the profiled stages.

@@ -1168,7 +1168,10 @@ __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ p
 // a much finer slave mesh) in separate lists, so that the light rows run
 // with small LDS tables and full occupancy.  Nothing is listed when the
 // pair records overflowed.
-constexpr int kLightEnt = 256;
+constexpr int kLightEnt = 128;
+// the light rows' column tables have 2 kLightEnt slots and the hash tables
+// inside them grow in powers of two up to that size
+static_assert((2 * kLightEnt & (2 * kLightEnt - 1)) == 0, "2 kLightEnt must be a power of two");
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__restrict__ rlist,
