@@ -1973,9 +1973,12 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   }
   if (H) {
     // per wave: distinct-column set and list (8 B per slot) plus, in the
-    // writing pass, the row's contributions (<= kRowEnt)
+    // writing pass, the row's contributions (<= kRowEnt).  Heavy tables start
+    // at 512 slots (a row's distinct columns never exceed its insertions, so
+    // rows below 512 insertions always fit) and grow with the capacity
+    // reported by a row that did not fit
     const int lslots = 2 * kLightEnt;
-    int hslots = 1024;
+    int hslots = 512;
     while (hslots < c->caps.row_entries && hslots < 4096) hslots <<= 1;
     auto lds = [&](int sl, int pass, bool heavy) { return (size_t)nw * row_lds_wave<R>(sl, pass, heavy); };
     if ((e = fork()) != hipSuccess) return e;
