@@ -95,9 +95,10 @@ def time_replays(g, steps: int, stream) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False):
+def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False, features=None):
     """Autotune, capture, time; per-kernel stage times; roofline of the
-    dominant kernel."""
+    dominant kernel.  features = (kappa_edge, kappa_point, delta_e) adds the
+    edge and point samples to the clipped face samples."""
     import numpy as np
     import torch
 
@@ -107,10 +108,13 @@ def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False
     xs, xm, dxs, dxm = t(batch.xs), t(batch.xm), t(batch.dxs), t(batch.dxm)
 
     def make(cells):
+        fe = {} if features is None else dict(features=True, kappa_edge=[features[0]] * len(envs),
+                                              kappa_point=[features[1]] * len(envs),
+                                              delta_e=[features[2]] * len(envs))
         return Context(batch.ts, batch.tm, batch.slave_v_off, batch.slave_t_off, batch.master_v_off,
                        batch.master_t_off, [w.rule_n for w in envs], [w.kappa for w in envs],
                        [w.dhat for w in envs], [w.delta_T for w in envs], cells, dtype=torch.float32,
-                       device=dev, mortar=mortar)
+                       device=dev, mortar=mortar, **fe)
 
     cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache if not mortar else None,
                                  scales=autotune.SCALES if not mortar else (0.0,))
@@ -434,6 +438,13 @@ def main():
         out["mortar"] = {"workload": w.name + " with clipped mortar face samples", "ms_per_step": mo["ms"],
                          "slave_samples_per_s": mo["value"], "clipped_active_samples": mo["sizes"]["n_active"],
                          "pairs": mo["sizes"]["n_pairs"], "stage_ms": mo["stages"]}
+        fe = measure(w.name + "/features", [w], workloads.concat([w]), max(10, args.steps // 5), 3, dev,
+                     mortar=True, features=(w.kappa * 1e-3, w.kappa * 1e-7, 0.1))
+        out["features"] = {"workload": w.name + " with clipped face, edge and point samples (kappa_edge = "
+                                       "1e-3 kappa, kappa_point = 1e-7 kappa, delta_e = 0.1)",
+                           "ms_per_step": fe["ms"], "slave_samples_per_s": fe["value"],
+                           "active_samples": fe["sizes"]["n_active"], "pairs": fe["sizes"]["n_pairs"],
+                           "stage_ms": fe["stages"]}
         out["patch_test"] = measure_patch(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
