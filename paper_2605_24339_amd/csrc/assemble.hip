@@ -631,11 +631,18 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
     auto pair_of = [&](int M) { return mortar_pair(a, M, s0, e1, e2, n, gi11, gi12, gi22, eps); };
 
     // ---- feature ownership: an edge or vertex belongs to the smallest-index
-    // opposing candidate master triangle that contains it
+    // opposing candidate master triangle that contains it.  The counting
+    // pass searches the triangle's candidate ids in LDS (the pair sums'
+    // array, which only the writing pass uses)
+    int32_t *cids = reinterpret_cast<int32_t *>(&pacc[0][0]);
+    static_assert(sizeof(pacc) >= sizeof(int32_t) * kMortarChunks * kWave, "candidate ids fit the pair sums");
     if (features) {
       wave_sync();
-      for (int ci = lane; ci < cn && ci < kMortarChunks * kWave; ci += kWave)
-        oflag[ci] = pair_of(a.cand[cb + ci]).opposing ? 1 : 0;
+      for (int ci = lane; ci < cn && ci < kMortarChunks * kWave; ci += kWave) {
+        const int M = a.cand[cb + ci];
+        cids[ci] = M;
+        oflag[ci] = pair_of(M).opposing ? 1 : 0;
+      }
       wave_sync();
     }
     auto cand_opposing = [&](int t) -> bool {
@@ -643,10 +650,10 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
       const int end = hi;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (a.cand[cb + mid] < t) lo = mid + 1;
+        if (cids[mid] < t) lo = mid + 1;
         else hi = mid;
       }
-      return lo < end && a.cand[cb + lo] == t && oflag[lo];
+      return lo < end && cids[lo] == t && oflag[lo];
     };
     auto owns_edge = [&](int M, int k) -> bool {
       const int o = a.m_opp[3 * (int64_t)M + k];
