@@ -36,14 +36,32 @@ class OracleError(RuntimeError):
         self.index = index
 
 
-def lib():
+def use_library(path: str):
+    """Load the oracle from another build of gmcp_oracle.c (for example the
+    -march=native build that times the oracle); later calls use it."""
+    global _LIB
+    _LIB = None
+    return lib(path)
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops."""
+    lib().ora_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().ora_max_threads())
+
+
+def lib(path: str | None = None):
     global _LIB
     if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
-        src = os.path.join(HERE, "gmcp_oracle.c")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
-            from .build import build
-            build()
+        if path is None:
+            path = os.path.join(HERE, "liboracle.so")
+            src = os.path.join(HERE, "gmcp_oracle.c")
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+                from .build import build
+                build()
         L = C.CDLL(path)
         d, i, i64 = C.c_double, C.c_int, C.c_int64
         P = C.c_void_p
@@ -78,6 +96,12 @@ def lib():
         L.ora_accd.argtypes = [P, P, P, P, P, P, P, P, d, d]
         L.ora_ccd_step.restype = d
         L.ora_ccd_step.argtypes = [i, i, P, P, i, i, P, P, i, P, P, P, P, d, i, P, P, P]
+        L.ora_swept_count.restype = i64
+        L.ora_swept_count.argtypes = [i, P, P, i, P, P, i, P, P, P, d, d, i]
+        L.ora_set_threads.restype = None
+        L.ora_set_threads.argtypes = [i]
+        L.ora_max_threads.restype = i
+        L.ora_max_threads.argtypes = []
         _LIB = L
     return _LIB
 
@@ -347,6 +371,18 @@ def ccd_step(P: Problem, M, dxs, dxm=None, s=0.1, use_grid=True) -> StepBound:
                            _p(None if dxm is None else _f64(dxm)), float(s), int(use_grid),
                            C.byref(ns), C.byref(al), C.byref(aa))
     return StepBound(a, al.value, aa.value, ns.value)
+
+
+def swept_count(P: Problem, dxs, dxm=None, pad_rel: float = 0.0, pad_abs: float = 0.0,
+                use_grid: bool = True) -> int:
+    """Number of (sample point, master triangle) pairs whose boxes over the
+    linear motion overlap (the pairs the step bound's additive CCD runs
+    over; Eq. (global_ccd) and the additive CCD reading).  A margin pad_rel
+    |c| + pad_abs grows every box bound outward (a count for boxes widened
+    by rounding); 0 is the definition."""
+    return int(lib().ora_swept_count(P.ts.shape[0], _p(P.xs), _p(P.ts), P.tm.shape[0], _p(P.xm), _p(P.tm),
+                                     P.nq, _p(P.rule), _p(_f64(dxs)), _p(None if dxm is None else _f64(dxm)),
+                                     float(pad_rel), float(pad_abs), int(use_grid)))
 
 
 def weights(P: Problem) -> np.ndarray:

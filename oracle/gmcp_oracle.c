@@ -26,6 +26,9 @@
  * Compiled with gcc (optionally -fopenmp); see oracle/build.py.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1030,4 +1033,101 @@ double ora_ccd_step(int Vs, int Ts, const double *xs, const int *ts, int Vm, int
   if (al < alpha) alpha = al;
   if (amin < alpha) alpha = amin;
   return alpha;
+}
+
+/* ------------------------------------------------ swept-pair count
+ * Number of (sample point, master triangle) pairs whose axis-aligned boxes
+ * over the linear motion t in [0, 1] overlap: the pair set that additive CCD
+ * runs over in the step bound (the count ora_ccd_step reports as n_swept).
+ * With pad_rel = pad_abs = 0 this is that definition.  A positive margin
+ * grows every box (both the point's and the triangle's) outward by
+ * pad_rel * |coordinate| + pad_abs per bound, which gives the count for
+ * boxes widened by a rounding margin: an upper bound for an implementation
+ * that rounds its boxes outward by no more than that.                   */
+int64_t ora_swept_count(int Ts, const double *xs, const int *ts, int Tm, const double *xm, const int *tm,
+                        int nq, const double *rule, const double *dxs, const double *dxm, double pad_rel,
+                        double pad_abs, int use_grid) {
+  double *blo = (double *)malloc(sizeof(double) * 3 * (size_t)(Tm ? Tm : 1));
+  double *bhi = (double *)malloc(sizeof(double) * 3 * (size_t)(Tm ? Tm : 1));
+  for (int t = 0; t < Tm; ++t)
+    for (int d = 0; d < 3; ++d) {
+      double lo = 1e300, hi = -1e300;
+      for (int j = 0; j < 3; ++j) {
+        const int64_t v = tm[3 * t + j];
+        double v0 = xm[3 * v + d], v1 = v0 + (dxm ? dxm[3 * v + d] : 0.0);
+        double l0 = v0 - (pad_rel * fabs(v0) + pad_abs), h0 = v0 + (pad_rel * fabs(v0) + pad_abs);
+        double l1 = v1 - (pad_rel * fabs(v1) + pad_abs), h1 = v1 + (pad_rel * fabs(v1) + pad_abs);
+        if (l0 < lo) lo = l0;
+        if (l1 < lo) lo = l1;
+        if (h0 > hi) hi = h0;
+        if (h1 > hi) hi = h1;
+      }
+      blo[3 * t + d] = lo;
+      bhi[3 * t + d] = hi;
+    }
+  ogrid grid;
+  int have_grid = use_grid ? ogrid_build(&grid, Tm, blo, bhi, 0.0) : 0;
+  int64_t npairs = 0;
+#pragma omp parallel reduction(+ : npairs)
+  {
+    int cap = Tm > 0 ? Tm : 1;
+    int *cand = (int *)malloc(sizeof(int) * (size_t)cap);
+    int *stamp = NULL;
+    if (have_grid) {
+      stamp = (int *)malloc(sizeof(int) * (size_t)cap);
+      for (int i = 0; i < Tm; ++i) stamp[i] = -1;
+    }
+#pragma omp for schedule(dynamic, 64)
+    for (int T = 0; T < Ts; ++T) {
+      const double *A = xs + 3 * (int64_t)ts[3 * T], *B = xs + 3 * (int64_t)ts[3 * T + 1],
+                   *C = xs + 3 * (int64_t)ts[3 * T + 2];
+      const double *dA = dxs + 3 * (int64_t)ts[3 * T], *dB = dxs + 3 * (int64_t)ts[3 * T + 1],
+                   *dC = dxs + 3 * (int64_t)ts[3 * T + 2];
+      for (int q = 0; q < nq; ++q) {
+        int64_t k = (int64_t)T * nq + q;
+        double xi = rule[3 * q], eta = rule[3 * q + 1], b0 = 1.0 - xi - eta;
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+          double p = b0 * A[d] + xi * B[d] + eta * C[d];
+          double e = p + (b0 * dA[d] + xi * dB[d] + eta * dC[d]);
+          double l = p < e ? p : e, h = p > e ? p : e;
+          lo[d] = l - (pad_rel * fabs(l) + pad_abs);
+          hi[d] = h + (pad_rel * fabs(h) + pad_abs);
+        }
+        if (have_grid) {
+          npairs += ogrid_query(&grid, lo, hi, blo, bhi, stamp, (int)(k & 0x7fffffff), cand, 0);
+        } else {
+          for (int t = 0; t < Tm; ++t) {
+            const double *a = blo + 3 * t, *b = bhi + 3 * t;
+            if (a[0] > hi[0] || b[0] < lo[0] || a[1] > hi[1] || b[1] < lo[1] || a[2] > hi[2] || b[2] < lo[2])
+              continue;
+            ++npairs;
+          }
+        }
+      }
+    }
+    free(stamp);
+    free(cand);
+  }
+  if (have_grid) ogrid_free(&grid);
+  free(blo);
+  free(bhi);
+  return npairs;
+}
+
+/* Thread count of the OpenMP loops above (for timing at 1 and at n threads). */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int ora_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

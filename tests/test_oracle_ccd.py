@@ -134,3 +134,43 @@ def test_swept_pairs_grid_equals_brute(small):
     b = oracle.ccd_step(P, nr.M, small.dxs, small.dxm, use_grid=False)
     assert a.n_swept == b.n_swept and a.alpha == b.alpha and a.alpha_accd == b.alpha_accd
     assert 0 < a.alpha < 1
+
+
+def test_swept_count_brute_force_tiny():
+    """The swept-pair count is the number of (sample point, master triangle)
+    pairs whose boxes over t in [0, 1] overlap: brute force over boxes built
+    here from the vertex paths, on a small random scene with motion of both
+    surfaces; the count equals the step bound's n_swept, and a positive box
+    margin can only add pairs."""
+    rng = np.random.default_rng(17)
+    from gen import meshes
+    xs, ts = meshes.pad(4, 2e-3)
+    xm = rng.uniform(-1.2e-3, 1.2e-3, size=(12, 3))
+    xm[:, 2] = rng.uniform(1e-4, 6e-4, size=12)
+    tm = rng.integers(0, 12, size=(10, 3))
+    tm = tm[(tm[:, 0] != tm[:, 1]) & (tm[:, 1] != tm[:, 2]) & (tm[:, 0] != tm[:, 2])]
+    dxs = rng.uniform(-2e-4, 2e-4, size=xs.shape)
+    dxm = rng.uniform(-2e-4, 2e-4, size=xm.shape)
+    P = oracle.Problem(xs, ts, xm, tm, rule_n=2)
+    # sample points and their paths from the rule written out here
+    pts = []
+    for T in range(ts.shape[0]):
+        for q in range(P.nq):
+            xi, eta = P.rule[q, 0], P.rule[q, 1]
+            b = np.array([1 - xi - eta, xi, eta])
+            p0 = b @ xs[ts[T]]
+            p1 = p0 + b @ dxs[ts[T]]
+            pts.append((np.minimum(p0, p1), np.maximum(p0, p1)))
+    brute = 0
+    for t in range(tm.shape[0]):
+        ends = np.concatenate([xm[tm[t]], xm[tm[t]] + dxm[tm[t]]])
+        lo, hi = ends.min(axis=0), ends.max(axis=0)
+        for plo, phi in pts:
+            brute += bool(np.all(plo <= hi) and np.all(lo <= phi))
+    assert brute > 5
+    assert oracle.swept_count(P, dxs, dxm) == brute
+    assert oracle.swept_count(P, dxs, dxm, use_grid=False) == brute
+    nr = oracle.narrow(P)
+    assert oracle.ccd_step(P, nr.M, dxs, dxm).n_swept == brute
+    assert oracle.swept_count(P, dxs, dxm, pad_rel=1e-3, pad_abs=1e-5) >= brute
+    assert oracle.swept_count(P, dxs, dxm, pad_abs=1.0) == len(pts) * tm.shape[0]

@@ -212,10 +212,36 @@ def test_gradient_hessian_frozen_fd_curved(small):
             fd = (E_at(h) - E_at(-h)) / (2 * h)
             an = A.grad[v, d]
             assert abs(fd - an) <= 1e-5 * np.abs(A.grad).max(), (v, d, fd, an)
-    # Hessian: symmetric, PSD, and equal to the frozen FD of the gradient
+    # Hessian: symmetric, PSD, and equal to second differences of the frozen
+    # energy (four-point mixed differences, h = 1e-8 m) on entries coupling
+    # the slave and master vertices of the samples with the smallest, median
+    # and largest active gap
     assert np.max(np.abs(H - H.T)) <= 1e-14 * np.abs(H).max()
     ev = np.linalg.eigvalsh(H)
     assert ev.min() >= -1e-12 * ev.max()
+
+    def E2(moves):
+        xs2, xm2 = x_s.copy(), x_m.copy()
+        for (v, d, dh) in moves:
+            if v < P.Vs:
+                xs2[v, d] += dh
+            else:
+                xm2[v - P.Vs, d] += dh
+        return _frozen_energy(P, nr, A, xs2, xm2)
+
+    act = np.nonzero(nr.M >= 0)[0]
+    order = act[np.argsort(nr.g[act])]
+    h, Hmax, big = 1e-8, np.abs(H).max(), 0
+    for k in order[[0, len(order) // 2, -1]]:
+        vs = [int(v) for v in P.ts[k // P.nq]] + [P.Vs + int(v) for v in P.tm[nr.M[k]]]
+        for (v, d, u, e) in [(vs[0], 2, vs[1], 2), (vs[0], 2, vs[3], 2), (vs[4], 0, vs[5], 2),
+                             (vs[2], 1, vs[2], 1), (vs[1], 2, vs[4], 1)]:
+            fd = (E2([(v, d, h), (u, e, h)]) - E2([(v, d, h), (u, e, -h)]) - E2([(v, d, -h), (u, e, h)])
+                  + E2([(v, d, -h), (u, e, -h)])) / (4 * h * h)
+            an = H[3 * v + d, 3 * u + e]
+            assert abs(fd - an) <= 1e-5 * Hmax, (v, d, u, e, fd, an)
+            big += abs(an) >= 1e-2 * Hmax
+    assert big >= 2       # some checked entries are large, so a wrong term would show
 
 
 def test_gradient_and_hessian_full_fd_flat_punch():
