@@ -286,6 +286,14 @@ int gmcp_energy_frozen(gmcp_ctx *ctx, const void *x_slave, const void *x_master,
 int gmcp_sample_results(gmcp_ctx *ctx, int32_t *master, void *gap, void *bary_m, void *c1,
                         void *c2, void *pressure);
 
+/* Contact pairs of the last assembly: T [n], M [n] (device int32) receive
+ * the slave and master triangle of each distinct (slave triangle, master
+ * triangle) contact, for n = min(cap, n_pairs of gmcp_status) entries in
+ * storage order (contiguous per slave triangle).  For checks of which
+ * pairs the selection (whole-triangle samples) or the clipping (mortar
+ * samples, Sec. 4.1) produced.  GMCP_E_ARG before any assembly. */
+int gmcp_pairs(gmcp_ctx *ctx, int32_t *T, int32_t *M, int64_t cap);
+
 /* Candidate lists of the last broad phase: cand_off [Ts+1], cand [cap]
  * (master triangle ids, ascending within a slave triangle). */
 int gmcp_candidates(gmcp_ctx *ctx, int32_t *cand_off, int32_t *cand, int64_t cap);

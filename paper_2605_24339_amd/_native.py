@@ -46,7 +46,7 @@ class Bsr(C.Structure):
 
 EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_stream",
            "gmcp_build_samples", "gmcp_num_samples", "gmcp_broadphase", "gmcp_assemble",
-           "gmcp_ccd_step", "gmcp_ccd_swept", "gmcp_ccd_finish", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_candidates", "gmcp_status",
+           "gmcp_ccd_step", "gmcp_ccd_swept", "gmcp_ccd_finish", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_pairs", "gmcp_candidates", "gmcp_status",
            "gmcp_strerror", "gmcp_profile", "gmcp_profile_stages", "gmcp_profile_stage_name",
            "gmcp_profile_read", "gmcp_rule", "gmcp_row_classes"]
 # include/gmcp_mlp.h
@@ -103,6 +103,8 @@ def lib():
         L.gmcp_energy_frozen.argtypes = [P, P, P, P]
         L.gmcp_sample_results.restype = C.c_int
         L.gmcp_sample_results.argtypes = [P, P, P, P, P, P, P]
+        L.gmcp_pairs.restype = C.c_int
+        L.gmcp_pairs.argtypes = [P, P, P, C.c_int64]
         L.gmcp_candidates.restype = C.c_int
         L.gmcp_candidates.argtypes = [P, P, P, C.c_int64]
         L.gmcp_status.restype = C.c_int

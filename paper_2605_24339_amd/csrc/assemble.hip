@@ -1751,6 +1751,18 @@ __global__ void k_export(const Rec<R> *__restrict__ rec, const DevStatus *st, in
   if (p) p[r.k] = r.p;
 }
 
+// (slave triangle, master triangle) of every contact pair of the last
+// assembly, in storage order (contiguous per slave triangle)
+template <typename R>
+__global__ void k_pair_export(const Pair<R> *__restrict__ pair, const DevStatus *st, int64_t cap_pairs, int64_t cap,
+                              int32_t *T, int32_t *M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t np = (int64_t)st->n_pairs;
+  if (np > cap_pairs || i >= np || i >= cap) return;
+  T[i] = pair[i].T;
+  M[i] = pair[i].M;
+}
+
 // HVP, step 1: per slave triangle, s_k = c2 (grad g_k . v_x + v_d[k]);
 // out_d[k] = s_k; triangle sums s_k bs_a; pair sums s_k bm_j
 template <typename R>
@@ -2059,6 +2071,14 @@ hipError_t launch_sample_results(gmcp_ctx *c, int32_t *M, R *g, R *bm, R *c1, R 
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_pair_export(gmcp_ctx *c, int32_t *T, int32_t *M, int64_t cap) {
+  const int64_t n = std::min<int64_t>(cap, c->caps.pairs);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_export<R>, dim3(nblk(n)), dim3(kThreads), 0, c->stream, (const Pair<R> *)c->b.pair,
+                     c->b.status, c->caps.pairs, cap, T, M);
+  return hipGetLastError();
+}
 
 // Energy of the last assembly's samples at new positions, every sample
 // frozen: slave triangle normal n_T, rule point, master triangle and its
@@ -2145,7 +2165,8 @@ hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy
                                          const gmcp_bsr *);                                                     \
   template hipError_t launch_hvp<R>(gmcp_ctx *, const R *, const R *, R *, R *);                                \
   template hipError_t launch_sample_results<R>(gmcp_ctx *, int32_t *, R *, R *, R *, R *, R *);                \
-  template hipError_t launch_energy_frozen<R>(gmcp_ctx *, const R *, const R *, R *);
+  template hipError_t launch_energy_frozen<R>(gmcp_ctx *, const R *, const R *, R *);                         \
+  template hipError_t launch_pair_export<R>(gmcp_ctx *, int32_t *, int32_t *, int64_t);
 GMCP_INST(float)
 GMCP_INST(double)
 

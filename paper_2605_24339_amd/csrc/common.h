@@ -237,6 +237,8 @@ template <typename R>
 hipError_t launch_energy_frozen(gmcp_ctx *c, const R *xs, const R *xm, R *energy);
 template <typename R>
 hipError_t launch_sample_results(gmcp_ctx *c, int32_t *M, R *g, R *bm, R *c1, R *c2, R *p);
+template <typename R>
+hipError_t launch_pair_export(gmcp_ctx *c, int32_t *T, int32_t *M, int64_t cap);
 
 // ---------------------------------------------------------- device utils
 __device__ inline uint32_t float_to_ordered(float f) {

@@ -667,6 +667,12 @@ int gmcp_sample_results(gmcp_ctx *c, int32_t *M, void *g, void *bm, void *c1, vo
   return fail(c, e);
 }
 
+int gmcp_pairs(gmcp_ctx *c, int32_t *T, int32_t *M, int64_t cap) {
+  if (!c || !T || !M || cap < 0 || !c->assembled) return GMCP_E_ARG;
+  hipError_t e = c->f64 ? launch_pair_export<double>(c, T, M, cap) : launch_pair_export<float>(c, T, M, cap);
+  return fail(c, e);
+}
+
 int gmcp_candidates(gmcp_ctx *c, int32_t *cand_off, int32_t *cand, int64_t cap) {
   if (!c || !cand_off || !c->broadphase_done) return GMCP_E_ARG;
   hipError_t e = build_candidate_csr(c);

@@ -372,6 +372,16 @@ class Context:
                "gmcp_sample_results")
         return dict(M=M, g=g, bm=bm, c1=c1, c2=c2, p=p)
 
+    def pairs(self):
+        """(slave triangle, master triangle) of every contact pair of the last
+        assembly: int32 tensors T [n], M [n] in storage order."""
+        n = int(self.status().n_pairs)
+        T = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        M = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        self._bind()
+        _check(N.lib().gmcp_pairs(self._ctx, _ptr(T), _ptr(M), n), "gmcp_pairs")
+        return T[:n], M[:n]
+
     def candidates(self):
         info = self.status()
         n = int(info.n_candidates)

@@ -7,8 +7,9 @@
   overlapping the broad phase and assembly) equals the one-call step bound
   bit for bit; the second call without the first is rejected.
 * The 256-environment batch (uneven pads, rules, indenters) runs in one
-  launch sequence; sampled environments match the FP64 oracle (energy,
-  gradient, step bound, selection outside the ambiguity band).
+  launch sequence; sampled environments (always the smallest and the
+  largest) match the FP64 oracle (energy, gradient, BSR Hessian, step
+  bound, selection outside the ambiguity band).
 """
 import numpy as np
 import pytest
@@ -97,8 +98,39 @@ def test_overlapped_step_bound_matches_sequential():
     assert e.value.code == _native.GMCP_E_ARG
 
 
+def _env_bsr(B, e, row_ptr, col, val):
+    """Environment e's rows of the batch's BSR (global numbering: every
+    slave vertex, then every master vertex) in the environment's own
+    numbering (its slave vertices, then its master vertices)."""
+    Vs = B.xs.shape[0]
+    s0, s1 = B.slave_v_off[e], B.slave_v_off[e + 1]
+    m0, m1 = B.master_v_off[e], B.master_v_off[e + 1]
+    rows = list(range(s0, s1)) + list(range(Vs + m0, Vs + m1))
+    ns = s1 - s0
+
+    def local(c):
+        c = c.astype(np.int64)
+        out = np.where(c < Vs, c - s0, c - Vs - m0 + ns)
+        ok = np.where(c < Vs, (c >= s0) & (c < s1), (c >= Vs + m0) & (c < Vs + m1))
+        assert ok.all(), "a block couples two environments"
+        return out
+
+    rp, cl, vl = [0], [], []
+    for r in rows:
+        a, b = row_ptr[r], row_ptr[r + 1]
+        cl.append(local(col[a:b]))
+        vl.append(val[a:b])
+        rp.append(rp[-1] + (b - a))
+    return np.array(rp), np.concatenate(cl), np.concatenate(vl)
+
+
 def test_batch_256_envs_sampled_parity():
+    """Sampled environments of the batch, always including the ones with
+    the fewest and the most samples: selection, energy, gradient, BSR
+    Hessian (blocks of the environment's own rows, no block coupling two
+    environments) and step bound against the oracle."""
     need_gpu()
+    from gpu_helpers import bsr_rel_error
     B = workloads.batched()
     ctx = _batch_ctx(B)
     X, XM = to_dev(B.xs, torch.float32), to_dev(B.xm, torch.float32)
@@ -109,10 +141,14 @@ def test_batch_256_envs_sampled_parity():
     E = A.energy.double().cpu().numpy()
     al = alpha.double().cpu().numpy()
     grad = A.grad.double().cpu().numpy()
+    H = A.hessian
+    row_ptr, col, val = H.row_ptr.cpu().numpy(), H.col.cpu().numpy(), H.val.double().cpu().numpy()
     M = ctx.sample_results()["M"].cpu().numpy()
     samp0 = np.cumsum([0] + [w.n_samples for w in B.envs])
+    ns = np.array([w.n_samples for w in B.envs])
     rng = np.random.default_rng(0)
-    for e in sorted(rng.choice(len(B.envs), 6, replace=False)):
+    pick = set(rng.choice(len(B.envs), 6, replace=False).tolist()) | {int(ns.argmin()), int(ns.argmax())}
+    for e in sorted(pick):
         w = B.envs[e]
         P = workloads.to_problem(w)
         nr = oracle.narrow(P)
@@ -122,7 +158,7 @@ def test_batch_256_envs_sampled_parity():
         assert np.array_equal(Me[ok], nr.M[ok]), e
         Mx = nr.M.copy()
         Mx[~ok] = Me[~ok]
-        Ar = oracle.assemble(P, Mx, hessian=False)
+        Ar = oracle.assemble(P, Mx, project=False)
         if Ar.energy > 0:
             assert abs(E[e] / Ar.energy - 1) <= 1e-5, e
         else:
@@ -130,5 +166,7 @@ def test_batch_256_envs_sampled_parity():
         gs = grad[B.slave_v_off[e]:B.slave_v_off[e + 1]]
         gm = grad[B.xs.shape[0] + B.master_v_off[e]:B.xs.shape[0] + B.master_v_off[e + 1]]
         assert rel_fro(np.concatenate([gs, gm]), Ar.grad) <= 1e-4, e
+        rp, cl, vl = _env_bsr(B, e, row_ptr, col, val)
+        assert bsr_rel_error(rp, cl, vl, Ar.row_ptr, Ar.col, Ar.val) <= 1e-4, e
         sb = oracle.ccd_step(P, Mx, w.dxs, w.dxm)
         assert al[e] <= sb.alpha and (sb.alpha - al[e]) / sb.alpha <= 1e-3, (e, al[e], sb.alpha)

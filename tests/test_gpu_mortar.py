@@ -69,6 +69,68 @@ def test_small_indent_mortar_matches_oracle(dtype):
     assert a <= ref and (ref - a) / ref <= 1e-3
 
 
+def _band(g, dhat):
+    """Clipped samples whose activity float32 rounding can flip: a gap
+    within 1e-4 dhat of the support edge, or within 1e-6 dhat of zero."""
+    return abs(g - dhat) <= 1e-4 * dhat or abs(g) <= 1e-6 * dhat
+
+
+def _pair_sets(ctx, P, smps):
+    """GPU contact pairs and the oracle's pairs with an active clipped
+    sample; the pairs only one side has must have every sample of that
+    pair in the float32 band."""
+    T, M = (t.cpu().numpy() for t in ctx.pairs())
+    got = list(zip(T.tolist(), M.tolist()))
+    assert len(got) == len(set(got)) == int(ctx.status().n_pairs)
+    by_pair = {}
+    for s in smps:
+        by_pair.setdefault((s.T, s.M), []).append(s.g)
+    ref = {k for k, gs in by_pair.items() if any(0.0 < g < P.dhat for g in gs)}
+    diff = set(got) ^ ref
+    for k in diff:
+        assert all(_band(g, P.dhat) for g in by_pair.get(k, [])), (k, by_pair.get(k))
+    return set(got), ref, diff
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_small_indent_mortar_pair_set(dtype):
+    """The (slave triangle, master triangle) pairs with active clipped
+    samples (Sec. 4.1): equal to the oracle's outside the float32 band."""
+    need_gpu()
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    w = workloads.small_indent(fp32=fp32)
+    ctx, xs, xm, A = _run(w, tdt)
+    P = workloads.to_problem(w)
+    got, ref, diff = _pair_sets(ctx, P, om.samples(P))
+    assert len(ref) > 300
+    assert len(diff) <= 2
+
+
+def test_large_indent_mortar_pair_set_sampled():
+    """Full-size sphere indentation: the pairs of 300 sampled slave
+    triangles that touch the indenter against the oracle's clipping of
+    those triangles."""
+    need_gpu()
+    w = workloads.large_indent()
+    ctx, xs, xm, A = _run(w, torch.float32)
+    P = workloads.to_problem(w)
+    T, M = (t.cpu().numpy() for t in ctx.pairs())
+    touched = np.unique(T)
+    assert touched.size > 1000
+    rng = np.random.default_rng(4)
+    pick = np.sort(rng.choice(touched, 300, replace=False))
+    smps = om.samples(P, pick)
+    sel = np.isin(T, pick)
+    got = set(zip(T[sel].tolist(), M[sel].tolist()))
+    by_pair = {}
+    for s in smps:
+        by_pair.setdefault((s.T, s.M), []).append(s.g)
+    ref = {k for k, gs in by_pair.items() if any(0.0 < g < P.dhat for g in gs)}
+    for k in got ^ ref:
+        assert all(_band(g, P.dhat) for g in by_pair.get(k, [])), (k, by_pair.get(k))
+
+
 def test_flat_punch_mortar_exact_area_on_gpu():
     """Independently meshed smaller punch: the energy is kappa B(g0) times
     the punch area (whole-triangle samples only approximate it)."""
@@ -172,6 +234,63 @@ def test_small_indent_face_edge_point_samples_match_oracle(dtype):
     # the frozen energy reproduces the assembled one (feature weights included)
     e0 = float(ctx.energy_frozen(xs, xm).double().sum())
     assert abs(e0 / float(A.energy.double().sum()) - 1) <= te
+
+
+def _feature_step_scene(kind):
+    """One master triangle over a flat 6 x 6 pad (10 mm) whose lowest
+    feature descends: 'point' lowers one vertex that projects inside the
+    pad (its point sample binds the step), 'edge' lowers an edge whose
+    vertices project outside the pad (its edge samples bind it).  Returns
+    (xs, ts, xm, tm, dxs, dxm)."""
+    from gen import meshes
+    xs, ts = meshes.pad(6, 1e-2)
+    if kind == "point":
+        xm = np.array([[-1.1e-3, -0.7e-3, 3e-4], [7.3e-3, -6.9e-3, 5e-4], [0.4e-3, 8.6e-3, 6e-4]])
+        dxm = np.array([[0.0, 0.0, -6e-4], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    else:
+        xm = np.array([[-8e-3, -2.1e-3, 3e-4], [8e-3, -2.1e-3, 3e-4], [0.3e-3, 2.0e-3, 9e-4]])
+        dxm = np.array([[0.0, 0.0, -6e-4], [0.0, 0.0, -6e-4], [0.0, 0.0, 0.0]])
+    tm = np.array([[0, 2, 1]])
+    return xs, ts, xm, tm, np.zeros_like(xs), dxm
+
+
+@pytest.mark.parametrize("kind", ["point", "edge"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_feature_samples_bound_the_step(kind, dtype):
+    """Step bound with edge and point samples (Sec. 4.1 samples, Eq. (ccd)
+    over every active sample, plus additive CCD over the rule points): the
+    scene is built so that the descending feature's samples give the
+    smallest bound, strictly below what the face samples and the additive
+    CCD allow, so the GPU bound can only match the oracle's by including
+    them."""
+    need_gpu()
+    from paper_2605_24339_amd import Context
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    xs, ts, xm, tm, dxs, dxm = _feature_step_scene(kind)
+    if fp32:
+        xs, xm, dxm = (a.astype(np.float32).astype(np.float64) for a in (xs, xm, dxm))
+    ke, kp = 1e2, 1e-2
+    ctx = Context.single(ts, tm, xs.shape[0], 3, rule_n=2, kappa=1e5, dhat=1e-3, dtype=tdt, features=True,
+                         kappa_edge=ke, kappa_point=kp)
+    X, XM = to_dev(xs, tdt), to_dev(xm, tdt)
+    ctx.build_samples(X)
+    ctx.broadphase(X, XM)
+    ctx.assemble(X, XM)
+    a = float(ctx.ccd_step(X, XM, to_dev(dxs, tdt), to_dev(dxm, tdt))[0])
+    P = oracle.Problem(xs, ts, xm, tm, 2, 1e5, 1e-3, 0.0, None, xs)
+    O = om.assemble(P, om.samples(P, features=True), kappa_edge=ke, kappa_point=kp)
+    want = 0 if kind == "point" else 1
+    feat = [s for s in O.active if s.kind == want]
+    face = [s for s in O.active if s.kind == 2]
+    assert feat and face
+    a_feat = om.linear_step(P, feat, dxs, dxm)
+    a_face = om.linear_step(P, face, dxs, dxm)
+    a_accd = oracle.ccd_step(P, oracle.narrow(P).M, dxs, dxm).alpha_accd
+    ref = min(1.0, om.linear_step(P, O.active, dxs, dxm), a_accd)
+    assert ref == a_feat < 1.0
+    assert min(a_face, a_accd) > 1.02 * a_feat
+    assert a <= ref and (ref - a) / ref <= 1e-3, (a, ref)
 
 
 def test_single_master_triangle_features_exact():

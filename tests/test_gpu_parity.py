@@ -47,12 +47,44 @@ def _check(w, dtype, tol_e, tol_g, tol_h, ccd=True, min_active=1):
     for r in range(len(rp) - 1):
         c = col[rp[r]:rp[r + 1]]
         assert np.all(np.diff(c) > 0)
+    # contact pairs: the distinct (slave triangle, master triangle) of the
+    # active samples, from the oracle's selection (the HIP path's choice
+    # only on the flagged samples)
+    T, Mp = (t.cpu().numpy() for t in G["ctx"].pairs())
+    nq = w.rule_n ** 2
+    ka = np.nonzero(O["M"] >= 0)[0]
+    ref = {(int(k // nq), int(O["M"][k])) for k in ka}
+    got = list(zip(T.tolist(), Mp.tolist()))
+    assert len(got) == len(set(got)) == int(G["status"].n_pairs)
+    assert set(got) == ref
     if ccd:
         sb = O["sb"]
         ag = G["alpha"]
         assert ag <= sb.alpha, (ag, sb.alpha)
         assert (sb.alpha - ag) / sb.alpha <= 1e-3, (ag, sb.alpha)
+        check_swept_count(O["P"], w, int(G["ccd_status"].n_swept))
     return G, O
+
+
+# Float32 swept boxes: every bound is widened outward by 4e-7 of its
+# magnitude, and the point's start is formed with a few roundings of the
+# scene's coordinates (|x| <= 2e-2 m here).  The oracle's count with boxes
+# shrunk and grown by a margin that covers both brackets the float count.
+SWEPT_REL, SWEPT_ABS = 1e-6, 1e-8
+
+
+def check_swept_count(P, w, n_gpu):
+    """The step bound's swept (sample point, master triangle) pair count
+    lies between the oracle's counts for boxes shrunk and grown by the float
+    margin (the definition: boxes over the linear motion overlap), and that
+    bracket is narrow."""
+    import oracle
+    lo = oracle.swept_count(P, w.dxs, w.dxm, -SWEPT_REL, -SWEPT_ABS)
+    hi = oracle.swept_count(P, w.dxs, w.dxm, SWEPT_REL, SWEPT_ABS)
+    exact = oracle.swept_count(P, w.dxs, w.dxm)
+    assert lo <= exact <= hi
+    assert lo <= n_gpu <= hi, (lo, n_gpu, hi)
+    assert hi - lo <= max(2, 1e-3 * exact), (lo, hi)
 
 
 def oracle_area(O):
@@ -80,6 +112,7 @@ def test_small_indent_fp64():
     assert rel_fro(G["grad"], A.grad) <= 1e-10
     assert bsr_rel_error(G["row_ptr"], G["col"], G["val"], A.row_ptr, A.col, A.val) <= 1e-10
     assert G["alpha"] <= O["sb"].alpha and (O["sb"].alpha - G["alpha"]) / O["sb"].alpha <= 1e-3
+    check_swept_count(O["P"], w, int(G["ccd_status"].n_swept))
 
 
 def test_small_indent_face_weight_fp32():
@@ -284,7 +317,14 @@ def test_frozen_energy_matches_oracle(dtype):
     if fp32:
         xs1, xm1 = xs1.astype(np.float32).astype(np.float64), xm1.astype(np.float32).astype(np.float64)
     e1 = float(ctx.energy_frozen(to_dev(xs1, tdt), to_dev(xm1, tdt)).double().sum().item())
-    P = oracle.Problem(w.xs, w.ts, w.xm, w.tm, w.rule_n, w.kappa, w.dhat, w.delta_T, None, w.xs_rest)
-    ref = oracle.frozen_energy(P, G["M"], G["bm"], xs1, xm1)
+    # the oracle's own selection and barycentrics; on the samples it flags as
+    # ambiguous it takes the HIP path's master triangle and computes their
+    # barycentrics itself
+    O = run_oracle(w, G["M"], ccd=False)
+    P, M = O["P"], O["M"]
+    bm = O["nr"].bm.copy()
+    for k in np.nonzero(O["flagged"] & (M >= 0))[0]:
+        bm[k] = oracle.sample_geom(P, int(k), int(M[k]))[1]
+    ref = oracle.frozen_energy(P, M, bm, xs1, xm1)
     assert abs(e1 / ref - 1) <= (1e-4 if fp32 else 1e-10)
     assert abs(e1 / e0 - 1) > 1e-4        # the displacement changed the energy
