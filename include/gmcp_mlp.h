@@ -44,6 +44,21 @@ int gmcp_mlp_backward(const float *params, const float *x, const float *act, con
 int gmcp_mlp_mse(const float *y, const float *t, int64_t B, int n_out, float *loss, float *dy, void *work,
                  size_t work_bytes, void *stream);
 
+/* The same loss and gradient as gmcp_mlp_mse for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid allocation): no work argument, and no
+ * allocation of any kind.  Its per-block partial sums live in a static
+ * device array of 4 MiB that every GPU the library runs on holds until the
+ * process ends, so B is limited to gmcp_mlp_mse_noalloc_max_rows() rows
+ * (larger B: GMCP_E_ARG, nothing enqueued).  `stream` must belong to the
+ * current device (else GMCP_E_ARG).  All calls on one GPU share that array:
+ * calls that overlap on one GPU (other streams, other threads) race. */
+int gmcp_mlp_mse_noalloc(const float *y, const float *t, int64_t B, int n_out, float *loss, float *dy,
+                         void *stream);
+
+/* Largest B that gmcp_mlp_mse_noalloc accepts (host only). */
+int64_t gmcp_mlp_mse_noalloc_max_rows(void);
+
 /* One Adam step (bias-corrected, step >= 1) on n parameters. */
 int gmcp_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr, float beta1,
                   float beta2, float eps, int step, void *stream);

@@ -51,7 +51,8 @@ EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_strea
            "gmcp_profile_read", "gmcp_rule", "gmcp_row_classes"]
 # include/gmcp_mlp.h
 MLP_EXPORTS = ["gmcp_mlp_param_count", "gmcp_mlp_work_bytes", "gmcp_mlp_forward", "gmcp_mlp_backward",
-               "gmcp_mlp_mse", "gmcp_mlp_adam", "gmcp_gemm_bf16"]
+               "gmcp_mlp_mse", "gmcp_mlp_mse_noalloc", "gmcp_mlp_mse_noalloc_max_rows", "gmcp_mlp_adam",
+               "gmcp_gemm_bf16"]
 # include/gmcp_fem.h
 FEM_EXPORTS = ["gmcp_fem_workspace_size", "gmcp_fem_create", "gmcp_fem_destroy", "gmcp_fem_constrain",
                "gmcp_fem_set_stream",

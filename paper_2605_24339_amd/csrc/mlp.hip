@@ -16,9 +16,18 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/gmcp_mlp.h"
 #include "common.h"
+
+// Scratch of gmcp_mlp_mse_noalloc (the per-block partial losses), in static
+// device memory: every GPU the library runs on holds its own copy until the
+// process ends.  Host code must not pass this name to a kernel (on the host
+// it is only a stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns for each device.
+constexpr int64_t kMseScratch = int64_t(1) << 20;  // floats, 4 MiB per GPU
+static __device__ __align__(256) float scratch[kMseScratch];
 
 namespace {
 
@@ -190,6 +199,31 @@ hipError_t gemm(hipStream_t s, const float *A, int lda, int tA, const float *B, 
   return hipGetLastError();
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(hipStream_t s, float **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GMCP_E_HIP;
+  if (s) {
+    hipDevice_t sd = 0;
+    if (hipStreamGetDevice(s, &sd) != hipSuccess) return GMCP_E_HIP;
+    if ((int)sd != dev) return GMCP_E_ARG;  // the stream must belong to the current device
+  }
+  if (dev < 0 || dev >= kMaxDevices) return GMCP_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GMCP_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (float *)g_scratch_ptr[dev];
+  return GMCP_OK;
+}
+
 constexpr int kSplitRows = 4096;  // batch rows per split-K chunk of a weight gradient
 
 int splits_for(int64_t B) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (B + kSplitRows - 1) / kSplitRows)); }
@@ -296,6 +330,23 @@ int gmcp_mlp_mse(const float *y, const float *t, int64_t B, int n_out, float *lo
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_mse, dim3((unsigned)blocks), dim3(256), 0, s, y, t, B, n_out, dy, (float *)work);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float *)work, blocks, loss);
+  return hipGetLastError() == hipSuccess ? GMCP_OK : GMCP_E_HIP;
+}
+
+int64_t gmcp_mlp_mse_noalloc_max_rows(void) { return kMseScratch * 256 / OUT; }
+
+int gmcp_mlp_mse_noalloc(const float *y, const float *t, int64_t B, int n_out, float *loss, float *dy,
+                         void *stream) {
+  if (!y || !t || !loss || !dy || B <= 0 || n_out < 1 || n_out > OUT) return GMCP_E_ARG;
+  if (B > gmcp_mlp_mse_noalloc_max_rows()) return GMCP_E_ARG;
+  const int64_t blocks = (B * OUT + 255) / 256;  // <= kMseScratch partials
+  hipStream_t s = (hipStream_t)stream;
+  float *part = nullptr;
+  const int rc = scratch_address(s, &part);
+  if (rc != GMCP_OK) return rc;
+  // k_mse writes every partial it reads back, so nothing needs clearing
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)blocks), dim3(256), 0, s, y, t, B, n_out, dy, part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float *)part, blocks, loss);
   return hipGetLastError() == hipSuccess ? GMCP_OK : GMCP_E_HIP;
 }
 

@@ -35,6 +35,10 @@ def _lib():
         L.gmcp_mlp_backward.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_size_t, P]
         L.gmcp_mlp_mse.restype = C.c_int
         L.gmcp_mlp_mse.argtypes = [P, P, C.c_int64, C.c_int, P, P, P, C.c_size_t, P]
+        L.gmcp_mlp_mse_noalloc.restype = C.c_int
+        L.gmcp_mlp_mse_noalloc.argtypes = [P, P, C.c_int64, C.c_int, P, P, P]
+        L.gmcp_mlp_mse_noalloc_max_rows.restype = C.c_int64
+        L.gmcp_mlp_mse_noalloc_max_rows.argtypes = []
         L.gmcp_mlp_adam.restype = C.c_int
         L.gmcp_mlp_adam.argtypes = [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int, P]
         L.gmcp_gemm_bf16.restype = C.c_int
