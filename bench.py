@@ -3,16 +3,27 @@
 
 One step = one pass of the whole path over the resident input: broad phase,
 assembly (selection, barrier, energy, gradient, BSR Hessian) and the step
-bound (linearised gap + additive CCD).  Headline workload: the single large
-indentation - 128x128 noisy gel pad (32768 triangles, 4x4 samples each =
-524288 samples) under a 40500-triangle perturbed geodesic sphere, float32.
-The step is captured once into a HIP graph and replayed; the broad-phase
-cell size is chosen by the autotuner first.
+bound (linearised gap + additive CCD).  Headline workload: the batch of 256
+environments of uneven size (pads of 32x32 to 128x128 quads, 2x2 to 4x4
+samples per triangle, 980 to 40500-triangle indenters; 35.5 M samples),
+float32, captured once into a HIP graph and replayed; the broad-phase cell
+size is chosen by the autotuner first.  The single large indentation
+(128x128 pad, 524288 samples, 40500-triangle sphere) is measured the same
+way beside it.
+
+Algorithmic bytes per step follow the scope's definition: positions,
+triangles, rest areas, gradient, BSR values + columns + row pointers and
+energies for the assembly; positions and displacements, triangles, the
+20-byte active-sample records and the bounds for the step bound.  The
+counts they need (active samples, BSR blocks) and the swept-pair count of
+the CCD rate are the oracle's (tests/golden/unit_counts.json, written by a
+script that calls only the oracle), so neither depends on the HIP path.
 
 Prints one JSON line: samples/s over the timed steps (inputs already in
-HBM), per-kernel HIP-event times, the roofline of the dominant kernel, the
-same figures for the 256-environment batch, and the FP64 oracle's
-throughput on the host cores (a reported baseline, not the target).
+HBM), per-kernel HIP-event times, the roofline of the dominant kernel and of
+the whole step, the same figures for the single large indentation, and the
+FP64 oracle's throughput on the host cores (a reported baseline, not the
+target).
 """
 from __future__ import annotations
 
@@ -35,52 +46,51 @@ KERNEL_STAGES = {"query": "k_query_f32", "cand_move": "k_cand_move", "narrow": "
                  "ccd_linear": "k_ccd_linear<float>", "ccd_accd": "k_ccd_accd<float>"}
 
 
+# sources of the step's kernels and launches (the traffic counters of a
+# kernel are reported only while these are unchanged)
+STEP_SOURCES = ("common.h", "util.hip", "broadphase.hip", "assemble.hip", "ccd.hip", "host.cpp")
+
+
 def src_hash() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2605_24339_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in STEP_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def kernel_bytes(stage: str, sz: dict) -> int:
-    """Algorithmic bytes of one launch: each input the kernel's function
-    needs, read once, and each output it produces, written once (float32)."""
-    Vs, Vm, Ts, Tm = sz["Vs"], sz["Vm"], sz["Ts"], sz["Tm"]
-    na, npair, nc, nnzb, ntile = sz["n_active"], sz["n_pairs"], sz["n_cand"], sz["nnzb"], sz["n_tiles"]
-    V = Vs + Vm
-    if stage == "narrow":
-        # slave x / triangles / areas, candidate CSR, master triangles + x;
-        # records 64 B per active sample, per-triangle normal+sums+counters
-        # 64 B, pairs 80 B, tile energies 8 B
-        return 12 * Vs + 16 * Ts + 4 * (Ts + 1) + 4 * nc + 12 * Tm + 12 * Vm + 64 * na + 64 * Ts + 80 * npair + 8 * ntile
-    if stage == "query":
-        # slave positions / triangles, master boxes; out: per-triangle counts
-        # and scratch offsets, sorted scratch lists
-        return 12 * Vs + 12 * Ts + 48 * Tm + 8 * Ts + 4 * nc
-    if stage == "cand_move":
-        return 12 * Ts + 8 * nc
-    if stage in ("rows_count", "rows_fill"):
-        # light rows: active slave triangles' sums and normals, their pairs,
-        # slave adjacency; out: counts, or blocks + row gradients
-        rl, nl = sz["rows_light"], sz["nnzb_light"]
-        ta = min(Ts, npair)
-        inp = 48 * ta + 80 * npair + 12 * Ts + 4 * (Vs + 1) + 8 * rl
-        return inp + (4 * rl if stage == "rows_count" else 40 * nl + 12 * rl)
-    if stage in ("rows_count_heavy", "rows_fill_heavy"):
-        # heavy rows: per-master-triangle blocks, bucket keys and the pairs'
-        # slave triangles, master adjacency; out: counts, or blocks + gradients
-        rh, nh = sz["rows_heavy"], sz["nnzb_heavy"]
-        tma = min(Tm, npair)
-        inp = 180 * tma + 8 * npair + 12 * npair + 4 * (Tm + 1) + 12 * Tm + 4 * (Vm + 1) + 8 * rh
-        return inp + (4 * rh if stage == "rows_count_heavy" else 40 * nh + 12 * rh)
-    if stage == "ccd_linear":
-        # records, slave normals and triangles, slave / master displacements, master triangles
-        return 64 * na + 24 * Ts + 12 * Vs + 12 * Tm + 12 * Vm
-    if stage == "ccd_accd":
-        return 24 * Vs + 12 * Ts + 24 * Vm + 12 * Tm + 48 * Tm
-    return 0
+def unit_counts(workload: str) -> dict | None:
+    """The oracle's counts for a workload (active samples, BSR blocks, swept
+    pairs, mesh sizes), if stored and written from the current generator
+    and oracle sources."""
+    p = os.path.join(ROOT, "tests", "golden", "unit_counts.json")
+    if not os.path.exists(p):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        import make_unit_counts as muc
+    finally:
+        sys.path.pop(0)
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != muc.source_hash():
+        return None
+    return d.get(workload)
+
+
+def step_bytes(c: dict) -> dict:
+    """Algorithmic bytes of one step (float32, 4-byte ids): the assembly
+    reads positions, triangles and rest areas and writes the gradient, the
+    BSR (3x3 values + column per block, row pointers) and the energies; the
+    step bound reads positions and displacements, triangles and the 20-byte
+    record of every active sample and writes the bounds."""
+    V = c["Vs"] + c["Vm"]
+    T = c["Ts"] + c["Tm"]
+    b_asm = 12 * V + 12 * T + 4 * c["Ts"] + 12 * V + 40 * c["nnzb"] + 4 * (V + 1) + 4 * c["n_env"]
+    b_ccd = 24 * V + 12 * T + 20 * c["active"] + 4 * c["n_env"]
+    return {"assembly": int(b_asm), "step_bound": int(b_ccd), "total": int(b_asm + b_ccd),
+            "per_sample": (b_asm + b_ccd) / c["samples"]}
 
 
 def time_replays(g, steps: int, stream) -> float:
@@ -116,9 +126,11 @@ def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False
                        [w.dhat for w in envs], [w.delta_T for w in envs], cells, dtype=torch.float32,
                        device=dev, mortar=mortar, **fe)
 
-    cells, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache if not mortar else None,
-                                 scales=autotune.SCALES if not mortar else (0.0,))
+    cells, tuning, table = autotune.tune(make, envs, (xs, xm, dxs, dxm), cache=tune_cache if not mortar else None,
+                                         scales=autotune.SCALES if not mortar else (0.0,),
+                                         shapes=autotune.SHAPES if not mortar else None)
     ctx = make(cells)
+    ctx.set_tuning(**tuning)
     ctx.build_samples(xs)
     g = ctx.capture(xs, xm, dxs, dxm)
     stream = torch.cuda.current_stream(dev)
@@ -136,28 +148,48 @@ def measure(name, envs, batch, steps, warmup, dev, tune_cache=None, mortar=False
     st = ctx.status()
     stages = {k: v[0] / v[1] for k, v in prof.items() if v[1] > 0}
     Ns = sum(w.n_samples for w in envs)
-    sz = dict(Vs=batch.xs.shape[0], Vm=batch.xm.shape[0], Ts=batch.ts.shape[0], Tm=batch.tm.shape[0],
-              n_active=int(st.n_active), n_pairs=int(st.n_pairs), n_cand=int(st.n_candidates),
-              nnzb=int(st.nnzb), n_tiles=sum((w.ts.shape[0] * w.rule_n ** 2 + 63) // 64 for w in envs),
-              **ctx.row_classes())
+    gpu = dict(n_env=len(envs), Vs=int(batch.xs.shape[0]), Vm=int(batch.xm.shape[0]), Ts=int(batch.ts.shape[0]),
+               Tm=int(batch.tm.shape[0]), samples=int(Ns), active=int(st.n_active), nnzb=int(st.nnzb),
+               swept=int(st.n_swept), pairs=int(st.n_pairs), candidates=int(st.n_candidates))
+    ora = None if mortar else unit_counts(name)
+    counts = ora if ora is not None else gpu
+    sb = step_bytes(counts)
     kern = {k: v for k, v in stages.items() if k in KERNEL_STAGES}
     dom = max(kern, key=kern.get)
-    byts = kernel_bytes(dom, sz)
-    achieved = byts / (kern[dom] * 1e-3) / 1e9
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        with open(tf) as fh:
-            rec = json.load(fh).get(f"{name}/{dom}")
-        if rec and rec.get("src_hash") == src_hash():
-            traffic = rec.get("bytes_per_launch")
+    traffic = load_traffic(name)
+    dom_traffic = traffic.get("kernels", {}).get(KERNEL_STAGES[dom]) if traffic else None
+    achieved = sb["total"] / (kern[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": KERNEL_STAGES[dom],
-            "stage": dom, "algorithmic_bytes": int(byts), "avg_ms": round(kern[dom], 5)}
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None if dom_traffic is None else round(dom_traffic),
+            "kernel": KERNEL_STAGES[dom], "stage": dom, "avg_ms": round(kern[dom], 5),
+            "algorithmic_bytes": sb["total"], "bytes_per_sample": round(sb["per_sample"], 3),
+            "samples_per_launch": int(Ns)}
+    step_gbs = sb["total"] / (ms * 1e-3) / 1e9
+    roof_step = {"bound": "hbm", "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(step_gbs / HBM_PEAK_GBS, 5),
+                 "traffic": None if not traffic else round(traffic["step_bytes"]),
+                 "algorithmic_bytes": sb, "ms": round(ms, 5)}
     ccd_ms = stages.get("ccd_linear", 0) + stages.get("ccd_grid", 0) + stages.get("ccd_accd", 0)
     return dict(ms=ms, value=Ns / (ms * 1e-3), samples=Ns, stages={k: round(v, 5) for k, v in stages.items()},
-                roofline=roof, sizes=sz, n_swept=int(st.n_swept), ccd_ms=ccd_ms, autotune=table,
-                cells=cells[:4])
+                roofline=roof, roofline_step=roof_step, gpu_counts=gpu, counts=counts,
+                counts_source="oracle" if ora is not None else "gpu", ccd_ms=ccd_ms, autotune=table,
+                tuning=ctx.tuning(), cells=cells[:4])
+
+
+def load_traffic(workload: str) -> dict | None:
+    """Measured HBM traffic of the workload's kernels (rocprofv3 counters,
+    copy-calibrated; profiles/traffic.json), if taken on the current step
+    sources: {"kernels": {name: bytes per launch}, "step_bytes": bytes per
+    step}."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as fh:
+        rec = json.load(fh).get(workload)
+    if not rec or rec.get("src_hash") != src_hash():
+        return None
+    return rec
 
 
 def _event_ms(fn, reps: int) -> float:
@@ -281,24 +313,65 @@ def cpu_patch(kappa: float = 1e6) -> dict:
                                                     "6x6x3 cube blocks (one quasi-static solve per sample kind)"}
 
 
-def cpu_baseline(w, budget_s: float) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads() -> int:
+    """Host threads the oracle may use: the process's CPU share (the
+    OMP_NUM_THREADS limit when set, else the affinity mask)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    return min(n, int(env)) if env and env.isdigit() and int(env) > 0 else n
+
+
+def cpu_baseline(envs, budget_s: float, threads: int) -> dict:
+    """The FP64 oracle as it stands (built -O3 -march=native for this host)
+    on a bounded sample of the workload: full passes (narrow phase,
+    assembly with the BSR Hessian, step bound) over the environments in
+    order, until the time budget is spent; samples/s over the passes done."""
     import oracle
     from gen import workloads
-    P = workloads.to_problem(w)
-    threads = len(os.sched_getaffinity(0))
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    oracle.use_library(oracle_native_lib())
+    oracle.set_threads(threads)
+    problems = {}
+    done, n_pass, busy = 0, 0, 0.0
+    while busy < budget_s:
+        i = n_pass % len(envs)
+        w = envs[i]
+        if i not in problems:               # problem set-up is not timed
+            problems[i] = workloads.to_problem(w)
+        P = problems[i]
+        t0 = time.perf_counter()
         nr = oracle.narrow(P)
         oracle.assemble(P, nr.M, project=False)
         oracle.ccd_step(P, nr.M, w.dxs, w.dxm)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": P.Ns * reps / dt, "unit": "samples/s",
-            "cores": int(os.environ.get("OMP_NUM_THREADS", threads)), "kind": "oracle",
-            "sample": f"{reps} full passes (narrow phase + assembly with BSR + step bound) over all "
-                      f"{P.Ns} samples of the same workload, FP64, OpenMP, {dt:.1f} s"}
+        busy += time.perf_counter() - t0
+        done += P.Ns
+        n_pass += 1
+    what = (f"environments 0..{min(n_pass, len(envs)) - 1} of the {len(envs)}" if len(envs) > 1
+            else "the whole workload")
+    return {"value": done / busy, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_pass} full passes (narrow phase + assembly with BSR + step bound) over {what} "
+                      f"({done} samples), FP64, {threads} thread(s), {busy:.1f} s"}
+
+
+_NATIVE = None
+
+
+def oracle_native_lib() -> str:
+    global _NATIVE
+    if _NATIVE is None:
+        from oracle import build as obuild
+        _NATIVE = obuild.build_native()
+    return _NATIVE
 
 
 def _counter_means(path: str, counter: str) -> dict:
@@ -318,30 +391,63 @@ def _counter_means(path: str, counter: str) -> dict:
     return {k: v[0] / v[1] for k, v in acc.items()}
 
 
-def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, stage, kernel):
-    """HBM traffic of one kernel from two counter runs (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
-    reads for a plain device copy of known size; stored in
-    profiles/traffic.json under the current source hash."""
+def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, ref_kernel="k_narrow_f32"):
+    """HBM traffic of every kernel of a workload's step from two counter runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for a plain device copy of known size.  Launches per
+    step are the kernel's dispatches over those of ref_kernel (once per
+    step).  Stored in profiles/traffic.json under the current source hash."""
+    import csv
     copy_bytes = 4 * 64 * 1024 * 1024
     cf = _counter_means(copy_fetch_csv, "FETCH_SIZE")
     cw = _counter_means(copy_write_csv, "WRITE_SIZE")
     ck = max(cf, key=cf.get)                    # the copy kernel is the largest dispatch
     f_scale = copy_bytes / (cf[ck] * 1024.0)
     w_scale = copy_bytes / (cw[ck] * 1024.0)
-    f = _counter_means(fetch_csv, "FETCH_SIZE")[kernel] * 1024.0 * f_scale
-    w = _counter_means(write_csv, "WRITE_SIZE")[kernel] * 1024.0 * w_scale
+    f = _counter_means(fetch_csv, "FETCH_SIZE")
+    w = _counter_means(write_csv, "WRITE_SIZE")
+
+    def dispatches(path):
+        import re
+        n = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != "FETCH_SIZE":
+                    continue
+                name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+                name = re.sub(r"\(.*", "", re.sub(r"^void ", "", name)).split("::")[-1]
+                n[name] = n.get(name, 0) + 1
+        return n
+
+    nd = dispatches(fetch_csv)
+    per_step = {k: nd[k] / nd[ref_kernel] for k in nd}
+    kernels = {k: f[k] * 1024.0 * f_scale + w.get(k, 0.0) * 1024.0 * w_scale for k in f}
+    step = sum(kernels[k] * round(per_step[k], 2) for k in kernels if k.startswith("k_"))
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     known = {}
     if os.path.exists(tf):
         with open(tf) as fh:
             known = json.load(fh)
-    known[f"{workload}/{stage}"] = {"kernel": kernel, "src_hash": src_hash(), "fetch_bytes": f, "write_bytes": w,
-                                    "bytes_per_launch": f + w, "copy_kernel": ck,
-                                    "fetch_scale": f_scale, "write_scale": w_scale}
+    known[workload] = {"src_hash": src_hash(), "kernels": {k: round(v) for k, v in kernels.items()
+                                                           if k.startswith("k_")},
+                       "launches_per_step": {k: round(v, 2) for k, v in per_step.items() if k.startswith("k_")},
+                       "step_bytes": round(step), "copy_kernel": ck, "fetch_scale": f_scale, "write_scale": w_scale}
     with open(tf, "w") as fh:
         json.dump(known, fh, indent=1)
-    print(json.dumps(known[f"{workload}/{stage}"]))
+    print(json.dumps({"workload": workload, "step_bytes": round(step),
+                      "kernels": sorted(((round(v), k) for k, v in kernels.items()), reverse=True)[:12]}))
+
+
+def _workload_line(r: dict, name: str) -> dict:
+    """Figures of one measured workload."""
+    c = r["counts"]
+    ccd_pairs = c["active"] + c["swept"]
+    return {"workload": name, "samples": r["samples"], "value": r["value"], "unit": "samples/s",
+            "ms_per_step": r["ms"], "active_samples_per_s": c["active"] / (r["ms"] * 1e-3),
+            "ccd_pairs_per_s": ccd_pairs / (r["ccd_ms"] * 1e-3) if r["ccd_ms"] > 0 else None,
+            "ccd_ms": r["ccd_ms"], "counts": c, "counts_source": r["counts_source"], "gpu_counts": r["gpu_counts"],
+            "stage_ms": r["stages"], "autotune_ms": r["autotune"], "tuning": r["tuning"], "roofline": r["roofline"],
+            "roofline_step": r["roofline_step"]}
 
 
 def main():
@@ -350,20 +456,20 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--indenter", default="sphere", choices=["sphere", "letter"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="oracle time budget of the headline CPU baseline (the other legs take fractions of it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the autograd and MLP measurements")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="measure only the 256-environment batch (for per-workload kernel profiles)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other rows (autograd, MLP, dual mesh, mortar, features, patch test)")
+    ap.add_argument("--workload", default=None, choices=["batched_256_envs", "large_indent"],
+                    help="measure only this workload's step (for per-workload kernel profiles)")
     ap.add_argument("--autotune-cache", default=None,
                     help="JSON file of autotuned cell sizes to reuse (default: tune every run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--ingest-counters", nargs=7, default=None,
-                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "WORKLOAD", "STAGE",
-                             "KERNEL"),
-                    help="CPU only: record the kernel's HBM traffic from rocprofv3 --pmc CSVs")
+    ap.add_argument("--ingest-counters", nargs=5, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "WORKLOAD"),
+                    help="CPU only: record the workload's per-kernel HBM traffic from rocprofv3 --pmc CSVs")
     args = ap.parse_args()
 
     if args.ingest_counters:
@@ -390,66 +496,75 @@ def main():
     from gen import workloads
 
     dev = torch.device("cuda", 0)
-    if args.batched_only:
-        B = workloads.batched()
-        bt = measure("batched_256", B.envs, B, args.steps, args.warmup, dev, args.autotune_cache)
-        print(json.dumps({"workload": "batched_256_envs", "samples": bt["samples"], "value": bt["value"],
-                          "unit": "samples/s", "ms_per_step": bt["ms"], "stage_ms": bt["stages"],
-                          "roofline": bt["roofline"], "autotune_ms": bt["autotune"]}))
-        return
     w = workloads.large_indent(indenter=args.indenter)
-    single = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev, args.autotune_cache)
+    if args.workload == "large_indent":
+        r = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev, args.autotune_cache)
+        print(json.dumps(_workload_line(r, w.name)))
+        return
+    B = workloads.batched()
+    bt = measure("batched_256_envs", B.envs, B, args.steps, args.warmup, dev, args.autotune_cache)
+    if args.workload == "batched_256_envs":
+        print(json.dumps(_workload_line(bt, "batched_256_envs")))
+        return
+    head = _workload_line(bt, "batched_256_envs")
+    rules = sorted({e.rule_n for e in B.envs})
     out = {
         "metric": METRIC,
-        "value": single["value"],
+        "value": bt["value"],
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": single["ms"],
+        "ms_per_step": bt["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "slave_tris": int(w.ts.shape[0]), "samples": int(w.n_samples),
-                   "master_tris": int(w.tm.shape[0]), "rule": f"{w.rule_n}x{w.rule_n}", "dhat": w.dhat,
-                   "kappa": w.kappa},
-        "ccd_pairs_per_s": (single["sizes"]["n_active"] + single["n_swept"]) / (single["ccd_ms"] * 1e-3),
-        "active_samples": single["sizes"]["n_active"],
-        "swept_pairs": single["n_swept"],
-        "nnzb": single["sizes"]["nnzb"],
-        "stage_ms": single["stages"],
-        "autotune_ms": single["autotune"],
-        "roofline": single["roofline"],
+        "config": {"workload": "batched_256_envs", "n_env": len(B.envs), "samples": int(bt["samples"]),
+                   "slave_tris": int(B.ts.shape[0]), "master_tris": int(B.tm.shape[0]),
+                   "pads": "32x32..128x128 quads", "rules": "/".join(f"{n}x{n}" for n in rules),
+                   "indenter_tris": "980..40500", "dhat": B.envs[0].dhat, "kappa": B.envs[0].kappa},
+        "ccd_pairs_per_s": head["ccd_pairs_per_s"],
+        "active_samples_per_s": head["active_samples_per_s"],
+        "counts": head["counts"],
+        "counts_source": head["counts_source"],
+        "gpu_counts": head["gpu_counts"],
+        "stage_ms": head["stage_ms"],
+        "autotune_ms": head["autotune_ms"],
+        "tuning": head["tuning"],
+        "roofline": head["roofline"],
+        "roofline_step": head["roofline_step"],
     }
-    if not args.no_batched:
-        B = workloads.batched()
-        bt = measure("batched_256", B.envs, B, max(5, args.steps // 10), 2, dev, args.autotune_cache)
-        out["batched"] = {"workload": "batched_256_envs", "samples": bt["samples"], "value": bt["value"],
-                          "unit": "samples/s", "ms_per_step": bt["ms"], "stage_ms": bt["stages"],
-                          "ccd_pairs_per_s": (bt["sizes"]["n_active"] + bt["n_swept"]) / (bt["ccd_ms"] * 1e-3),
-                          "roofline": bt["roofline"], "autotune_ms": bt["autotune"]}
+    single = measure(w.name, [w], workloads.concat([w]), args.steps, args.warmup, dev, args.autotune_cache)
+    out["large_indent"] = _workload_line(single, w.name)
     if not args.no_extras:
         out["autograd"] = measure_autograd(w, dev)
         out["mlp"] = measure_mlp(dev)
         out["dualmesh"] = measure_dualmesh(dev)
         mo = measure(w.name + "/mortar", [w], workloads.concat([w]), max(10, args.steps // 5), 3, dev, mortar=True)
         out["mortar"] = {"workload": w.name + " with clipped mortar face samples", "ms_per_step": mo["ms"],
-                         "slave_samples_per_s": mo["value"], "clipped_active_samples": mo["sizes"]["n_active"],
-                         "pairs": mo["sizes"]["n_pairs"], "stage_ms": mo["stages"]}
+                         "slave_samples_per_s": mo["value"], "clipped_active_samples": mo["gpu_counts"]["active"],
+                         "pairs": mo["gpu_counts"]["pairs"], "stage_ms": mo["stages"]}
         fe = measure(w.name + "/features", [w], workloads.concat([w]), max(10, args.steps // 5), 3, dev,
                      mortar=True, features=(w.kappa * 1e-3, w.kappa * 1e-7, 0.1))
         out["features"] = {"workload": w.name + " with clipped face, edge and point samples (kappa_edge = "
                                        "1e-3 kappa, kappa_point = 1e-7 kappa, delta_e = 0.1)",
                            "ms_per_step": fe["ms"], "slave_samples_per_s": fe["value"],
-                           "active_samples": fe["sizes"]["n_active"], "pairs": fe["sizes"]["n_pairs"],
+                           "active_samples": fe["gpu_counts"]["active"], "pairs": fe["gpu_counts"]["pairs"],
                            "stage_ms": fe["stages"]}
         out["patch_test"] = measure_patch(dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        nt = oracle_threads()
+        cb = cpu_baseline(B.envs, args.cpu_seconds, nt)
+        cb["cpu_model"] = cpu_model()
+        cb["build"] = "gcc -O3 -march=native -fopenmp"
+        cb["single_thread"] = cpu_baseline(B.envs, args.cpu_seconds / 2, 1)
+        cb["large_indent"] = {"threads": cpu_baseline([w], args.cpu_seconds / 2, nt),
+                              "single_thread": cpu_baseline([w], args.cpu_seconds / 2, 1)}
         if not args.no_extras:
-            out["cpu_baseline"]["patch_test"] = cpu_patch()
+            cb["patch_test"] = cpu_patch()
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

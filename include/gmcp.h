@@ -33,9 +33,11 @@
  * active for 0 < g < dhat (-dhat < g <= 0 is a penetration, reported with
  * the slave triangle's index).  Every opposing pair contributes (no
  * closest-triangle selection).  Clipped samples have no fixed ids: in this
- * mode gmcp_assemble takes no g_ref / delta_gap, gmcp_hvp no v_d / out_d,
- * and gmcp_sample_results is unavailable (GMCP_E_ARG); the active capacity
- * counts clipped samples.
+ * mode gmcp_assemble takes no delta_gap, gmcp_hvp no v_d / out_d, and
+ * gmcp_sample_results is unavailable (GMCP_E_ARG); g_ref holds one
+ * reference gap per slave triangle ([Ts]: every clipped sample of T has
+ * eps = min(0.9 g_ref[T], eps_max), Eq. (adaptive_eps)); the active
+ * capacity counts clipped samples.
  *
  * Edge and point samples (GMCP_FEATURES with GMCP_MORTAR, Sec. 4.1).  The
  * edges and vertices of the opposing candidate master triangles of a slave
@@ -151,6 +153,25 @@ typedef struct {
   int64_t cap_nnzb;
 } gmcp_bsr;
 
+/* Launch shapes of the list-walking kernels, for an autotuner: later calls
+ * on the context use them (a captured graph keeps the shapes it was
+ * captured with).  Zero selects the default.  Results do not depend on
+ * them, except that a BSR row's class (light or heavy table) follows
+ * light_row_bound.
+ *   query_blocks      grid of the broad-phase query, 1..2048
+ *                     (default: the blocks resident at once, at most 2048)
+ *   light_row_bound   column insertions of a BSR row processed with the
+ *                     small tables (2 x bound slots): 32, 64, 128 or 256
+ *                     (default 128); longer rows use the large tables
+ *   light_row_blocks  grid of the light-row kernels, 1..2^20 (default 65536)
+ *   heavy_row_blocks  grid of the heavy-row kernels, 1..65536 (default 2048) */
+typedef struct {
+  int32_t query_blocks;
+  int32_t light_row_bound;
+  int32_t light_row_blocks;
+  int32_t heavy_row_blocks;
+} gmcp_tuning;
+
 typedef struct gmcp_ctx gmcp_ctx;
 
 /* Bytes of workspace needed for this layout and these capacities. */
@@ -175,6 +196,12 @@ void gmcp_destroy(gmcp_ctx *ctx);
 
 /* Changes the stream later calls are enqueued on. */
 int gmcp_set_stream(gmcp_ctx *ctx, void *stream);
+
+/* Sets (GMCP_E_ARG if a field is out of range, nothing changed) or reads
+ * the launch shapes; gmcp_get_tuning reports the values in effect, with
+ * the defaults filled in (query_blocks 0 until the first broad phase). */
+int gmcp_set_tuning(gmcp_ctx *ctx, const gmcp_tuning *tuning);
+int gmcp_get_tuning(const gmcp_ctx *ctx, gmcp_tuning *tuning);
 
 /*
  * Sample table (Sec. 4.1, face samples; Eq. (gmcp_potential) weights).
@@ -211,6 +238,7 @@ int gmcp_broadphase(gmcp_ctx *ctx, const void *x_slave, const void *x_master);
  * +beta^m_j n_T (master vertex j), and the Hessian sum_k c2 grad g grad g^T.
  * Sec. 4.2 and Eqs. (gap), (gram), (smoothstep), (gamma), (adaptive_eps).
  *   g_ref     [Ns] nullable: reference gaps, eps_k = min(0.9 g_ref, eps_max)
+ *             (mortar mode: [Ts], one per slave triangle)
  *   delta_gap [Ns] nullable: gap offsets added after selection (g += delta)
  *   energy    [n_env] output (sum per environment)
  *   grad      [V][3] nullable output

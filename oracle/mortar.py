@@ -22,7 +22,10 @@ Readings (the paper does not fix them):
   triangle's REST area (2 |area in (u, v)| A_rest(T_s)), so the weights of a
   fully covered slave triangle sum to its rest area;
 * pairs: every opposing master triangle; samples with 0 < g < eps are
-  active (eps = dhat), -eps < g <= 0 is a penetration error;
+  active, -eps < g <= 0 is a penetration error; eps = dhat, or with
+  reference gaps (Eq. (adaptive_eps)) one per slave triangle,
+  eps_T = min(0.9 g_ref[T], dhat) for every sample of T (clipped samples
+  have no fixed identity, the slave triangle is what they keep);
 * gamma = H(min beta^m, delta_T) (1 when delta_T = 0), kappa for faces.
 
 Energy, gradient and Hessian of the samples follow Sec. 4.2 with the
@@ -70,6 +73,7 @@ class Sample:
     mv: np.ndarray = None   # master vertex ids (3 face, 2 edge, 1 point)
     kind: int = 2           # 2 face, 1 edge, 0 point (Eq. (gmcp_potential))
     eta: float = 0.0        # edge parameter (edge samples)
+    eps: float = None       # support radius (None: the problem's dhat)
 
 
 def pair_samples(P: "oracle.Problem", T: int, M: int, area_rest: float, rule):
@@ -182,18 +186,20 @@ def feature_samples(P: "oracle.Problem", T: int, opposing):
     return out
 
 
-def samples(P: "oracle.Problem", tris=None, features: bool = False):
+def samples(P: "oracle.Problem", tris=None, features: bool = False, g_ref_tri=None):
     """All clipped face samples of the slave triangles `tris` (default all)
     against every opposing master triangle, and with `features` the edge
-    and point samples of those triangles' edges and vertices.  Raises
+    and point samples of those triangles' edges and vertices.  g_ref_tri
+    (optional, one per slave triangle) sets the triangle's support radius
+    eps_T = min(0.9 g_ref_tri[T], dhat), Eq. (adaptive_eps).  Raises
     OracleError(PENETRATION) for a sample with -eps < g <= 0 (index = slave
     triangle)."""
     area = oracle.rest_area(P.xs_rest, P.ts)
     rule = P.rule
-    eps = P.dhat
     tris = range(P.ts.shape[0]) if tris is None else tris
     out = []
     for T in tris:
+        eps = P.dhat if g_ref_tri is None else min(0.9 * float(g_ref_tri[T]), P.dhat)
         s0, e1, e2, n, _ = _frame(P, T)
         # heights of the master vertices above the slave plane: the gap is
         # their barycentric combination, so a master triangle entirely
@@ -209,6 +215,7 @@ def samples(P: "oracle.Problem", tris=None, features: bool = False):
             opposing = np.nonzero(N @ n < 0.0)[0]
             got += feature_samples(P, T, opposing)
         for smp in got:
+            smp.eps = eps
             if -eps < smp.g <= 0.0:
                 raise oracle.OracleError(oracle.E_PENETRATION, T)
         out += got
@@ -251,12 +258,13 @@ def assemble(P: "oracle.Problem", smps, kinematic: bool = False, with_hessian: b
     act, c1s, c2s = [], [], []
     kap = {2: P.kappa, 1: kappa_edge, 0: kappa_point}
     for smp in smps:
-        if not (0.0 < smp.g < P.dhat):
+        eps = P.dhat if smp.eps is None else smp.eps
+        if not (0.0 < smp.g < eps):
             continue
         kw = kap[smp.kind] * smp.w * gamma(P, smp, delta_e)
-        E += kw * oracle.barrier(smp.g, P.dhat)
-        c1 = kw * oracle.barrier_d1(smp.g, P.dhat)
-        c2 = max(kw * oracle.barrier_d2(smp.g, P.dhat), 0.0)
+        E += kw * oracle.barrier(smp.g, eps)
+        c1 = kw * oracle.barrier_d1(smp.g, eps)
+        c2 = max(kw * oracle.barrier_d2(smp.g, eps), 0.0)
         act.append(smp)
         c1s.append(c1)
         c2s.append(c2)
@@ -283,8 +291,9 @@ def frozen_energy(P: "oracle.Problem", active, xs_new, xm_new, kappa_edge: float
         g = float(s.n @ (s.bm @ xm_new[s.mv] - s.bs @ xs_new[P.ts[s.T]]))
         if g <= 0.0:
             return float("inf")
-        if g < P.dhat:
-            E += kap[s.kind] * s.w * gamma(P, s, delta_e) * oracle.barrier(g, P.dhat)
+        eps = P.dhat if s.eps is None else s.eps
+        if g < eps:
+            E += kap[s.kind] * s.w * gamma(P, s, delta_e) * oracle.barrier(g, eps)
     return E
 
 

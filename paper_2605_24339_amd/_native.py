@@ -40,11 +40,17 @@ class StatusInfo(C.Structure):
                 ("n_candidates", C.c_int64), ("n_swept", C.c_int64), ("need", Caps)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("query_blocks", C.c_int32), ("light_row_bound", C.c_int32), ("light_row_blocks", C.c_int32),
+                ("heavy_row_blocks", C.c_int32)]
+
+
 class Bsr(C.Structure):
     _fields_ = [("row_ptr", P), ("col", P), ("val", P), ("cap_nnzb", C.c_int64)]
 
 
-EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_stream",
+EXPORTS = ["gmcp_workspace_size", "gmcp_create", "gmcp_destroy", "gmcp_set_stream", "gmcp_set_tuning",
+           "gmcp_get_tuning",
            "gmcp_build_samples", "gmcp_num_samples", "gmcp_broadphase", "gmcp_assemble",
            "gmcp_ccd_step", "gmcp_ccd_swept", "gmcp_ccd_finish", "gmcp_hvp", "gmcp_energy_frozen", "gmcp_sample_results", "gmcp_pairs", "gmcp_candidates", "gmcp_status",
            "gmcp_strerror", "gmcp_profile", "gmcp_profile_stages", "gmcp_profile_stage_name",
@@ -104,6 +110,10 @@ def lib():
         L.gmcp_energy_frozen.argtypes = [P, P, P, P]
         L.gmcp_sample_results.restype = C.c_int
         L.gmcp_sample_results.argtypes = [P, P, P, P, P, P, P]
+        L.gmcp_set_tuning.restype = C.c_int
+        L.gmcp_set_tuning.argtypes = [P, C.POINTER(Tuning)]
+        L.gmcp_get_tuning.restype = C.c_int
+        L.gmcp_get_tuning.argtypes = [P, C.POINTER(Tuning)]
         L.gmcp_pairs.restype = C.c_int
         L.gmcp_pairs.argtypes = [P, P, P, C.c_int64]
         L.gmcp_candidates.restype = C.c_int

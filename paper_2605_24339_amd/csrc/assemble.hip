@@ -581,7 +581,7 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
   if (tile_id >= a.n_tiles) return;
   const Tile tl = a.tiles[tile_id];
   const EnvInfo &ev = a.env[tl.env];
-  const R eps = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
+  const R dhat = (R)ev.dhat, kappa = (R)ev.kappa, deltaT = (R)ev.delta_T;
   const R kappa_e = (R)ev.kappa_e, kappa_p = (R)ev.kappa_p, delta_e = (R)ev.delta_e;
   const int nq = ev.nq, ng = ev.rule_n;
   const double *rule = a.rule + (ev.rule_n - 1) * 16 * 3;
@@ -596,6 +596,9 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
   for (int j = 0; j < tl.count; ++j) {
     const int T = a.s_order[tl.first + j];
     const int cn = a.cand_cnt[T], cb = cn > 0 ? a.cand_pos[T] : 0;
+    // support radius of the triangle's samples, Eq. (adaptive_eps): in this
+    // mode the reference gaps are one per slave triangle
+    const R eps = a.g_ref ? fmin(R(0.9) * a.g_ref[T], dhat) : dhat;
     // slave frame
     R s0[3], e1[3], e2[3], n[3];
     {
@@ -1083,15 +1086,15 @@ struct RowArgs {
   R *val;
   int64_t cap_nnzb;
   R *grad;   // nullable: written by the writing pass (pass 1) or alone (pass 2)
+  int light_bound;  // column insertions of a light row (32, 64, 128 or 256)
 };
 
 constexpr int kRowWaves = 2;
-// fixed grids of the list-walking row kernels, many times the blocks resident
-// at once: a block's share of the list is short, so blocks that start late
+// the list-walking row kernels use fixed grids, by default many times the
+// blocks resident at once (kDefaultRowBlocks light, kDefaultHeavyBlocks
+// heavy): a block's share of the list is short, so blocks that start late
 // (the device is shared with the other stream's kernels) finish soon after
 // the rest
-constexpr int kRowBlocks = 65536;    // light rows
-constexpr int kHeavyBlocks = 2048;   // heavy rows (large LDS tables, few resident)
 
 // slot of column `col` in an open-addressing table of `slots` (power of 2)
 __device__ inline int row_slot(int32_t *key, int slots, int32_t col, bool *full) {
@@ -1171,14 +1174,12 @@ __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ p
 // Thread per BSR row: counts the row's contributions (the entries the row
 // kernel enumerates).  Rows without any get their count and gradient zeroed
 // here; the others are listed for the wave kernels - light rows (at most
-// kLightEnt entries, the common case) and heavy rows (master vertices under
+// a.light_bound entries, the common case) and heavy rows (master vertices under
 // a much finer slave mesh) in separate lists, so that the light rows run
 // with small LDS tables and full occupancy.  Nothing is listed when the
-// pair records overflowed.
-constexpr int kLightEnt = 128;
-// the light rows' column tables have 2 kLightEnt slots and the hash tables
-// inside them grow in powers of two up to that size
-static_assert((2 * kLightEnt & (2 * kLightEnt - 1)) == 0, "2 kLightEnt must be a power of two");
+// pair records overflowed.  A light row has at most a.light_bound column
+// insertions (a power of two); its column table has 2 a.light_bound slots
+// and the hash tables inside it grow in powers of two up to that size.
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__restrict__ rlist,
@@ -1207,7 +1208,8 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
   // list appends: wave ballots, block prefix in LDS, one atomic per block and list
   __shared__ int wl[kThreads / kWave], wh[kThreads / kWave], bl, bh;
   const int w = threadIdx.x / kWave;
-  const uint64_t ml = __ballot(n_ent > 0 && n_ent <= kLightEnt), mh = __ballot(n_ent > kLightEnt);
+  const int lb = a.light_bound;
+  const uint64_t ml = __ballot(n_ent > 0 && n_ent <= lb), mh = __ballot(n_ent > lb);
   if (lane == 0) {
     wl[w] = __popcll(ml);
     wh[w] = __popcll(mh);
@@ -1227,8 +1229,8 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
   }
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1;
-  if (n_ent > 0 && n_ent <= kLightEnt) rlist[bl + wl[w] + __popcll(ml & below)] = (int32_t)row;
-  if (n_ent > kLightEnt) rlist[a.V + bh + wh[w] + __popcll(mh & below)] = (int32_t)row;
+  if (n_ent > 0 && n_ent <= lb) rlist[bl + wl[w] + __popcll(ml & below)] = (int32_t)row;
+  if (n_ent > lb) rlist[a.V + bh + wh[w] + __popcll(mh & below)] = (int32_t)row;
 }
 
 // One wave per listed BSR row (k_row_pre), a fixed grid walking the list.
@@ -1253,7 +1255,7 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
 // their blocks equal block (a, j) of slave row a (each contribution is a
 // symmetric coef n n^T), so PASS 3 copies them after PASS 1 has written the
 // slave rows.  Columns are ranked and written ascending.
-constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows: kLightEnt)
+constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows: their bound)
 constexpr int kRowSrc = kWave;   // incident triangles of a slave row kept in LDS
 
 // LDS bytes of one wave of k_rows: hash set and dense list (slots each),
@@ -1262,9 +1264,9 @@ constexpr int kRowSrc = kWave;   // incident triangles of a slave row kept in LD
 // vertices: three distinct columns, the table index, three coefficients) -
 // and the incident triangles' normals; a multiple of 16 bytes
 template <typename R>
-constexpr size_t row_lds_wave(int slots, int pass, bool heavy) {
+constexpr size_t row_lds_wave(int slots, int pass, bool heavy, int light_bound) {
   return ((size_t)slots * 8 + (size_t)8 * kRowSrc * 4 +
-          (pass == 1 ? (size_t)((heavy ? kRowEnt : kLightEnt) / 3 + 1) * (16 + 3 * sizeof(R)) +
+          (pass == 1 ? (size_t)((heavy ? kRowEnt : light_bound) / 3 + 1) * (16 + 3 * sizeof(R)) +
                            (size_t)kRowSrc * 3 * sizeof(R)
                      : 0) +
           15) / 16 * 16;
@@ -1276,8 +1278,8 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  constexpr int ecap = HEAVY ? kRowEnt : kLightEnt;
-  const size_t per_wave = row_lds_wave<R>(slots, pass, HEAVY);
+  const int ecap = HEAVY ? kRowEnt : a.light_bound;
+  const size_t per_wave = row_lds_wave<R>(slots, pass, HEAVY, a.light_bound);
   int32_t *key = reinterpret_cast<int32_t *>(smem + (size_t)w * per_wave);
   int32_t *dense = key + slots;
   int32_t *sip = dense + slots;  // incident-triangle table: item prefix, contribution
@@ -1286,7 +1288,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   int32_t *sco = stt + kRowSrc;
   int32_t *spb = sco + kRowSrc;
   int32_t *stv = spb + kRowSrc;  // master rows: the triangle's three vertex ids
-  constexpr int gcap = ecap / 3 + 1;
+  const int gcap = ecap / 3 + 1;
   int4 *egrp = reinterpret_cast<int4 *>(stv + 3 * kRowSrc);  // PASS 1 stash: three columns + table index,
   R *ecoef = reinterpret_cast<R *>(egrp + gcap);          // three coefficients per group
   R *snrm = ecoef + 3 * gcap;                             // normals of the table's triangles
@@ -1294,7 +1296,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   // the waves walk the list of rows with contributions (k_row_pre)
   const int64_t nlist = *rcount;
   const int nw = blockDim.x / kWave;
-  for (int64_t li = (int64_t)blockIdx.x * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
+  // logical block: consecutive logical blocks run on one XCD, so neighbouring
+  // rows (which share triangles and pairs) are read through one L2
+  const int lblk = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t li = (int64_t)lblk * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
     [&](const int64_t row) {
   wave_sync();  // the previous row's LDS reads are done
   const bool slave = row < a.Vs;
@@ -1405,7 +1410,8 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     }
     if (__any(full)) {
       if (lane == 0) {
-        atomicMax(&a.st->need_row, (unsigned long long)(2 * slots));
+        // a table of n_ent slots always fits (distinct columns <= insertions)
+        atomicMax(&a.st->need_row, (unsigned long long)max(2 * slots, min(n_ent, 4096)));
         atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
         if (pass == 0) a.row_cnt[row] = 0;
       }
@@ -1584,7 +1590,8 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   }
   if (__any(full)) {
     if (lane == 0) {
-      atomicMax(&a.st->need_row, (unsigned long long)(2 * slots));
+      // a table of n_ent slots always fits (distinct columns <= insertions)
+      atomicMax(&a.st->need_row, (unsigned long long)max(2 * slots, min(n_ent, 4096)));
       atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
       if (pass == 0) a.row_cnt[row] = 0;
     }
@@ -1853,6 +1860,7 @@ RowArgs<R> row_args(gmcp_ctx *c, const gmcp_bsr *H) {
   ra.val = H ? (R *)H->val : nullptr;
   ra.cap_nnzb = H ? H->cap_nnzb : 0;
   ra.grad = nullptr;
+  ra.light_bound = light_row_bound(c);
   return ra;
 }
 
@@ -1978,8 +1986,9 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   // the row kernels walk the two row lists with fixed grids: light rows with
   // small LDS tables, heavy rows with tables of up to 4096 slots
   const int64_t rneed = (c->V + nw - 1) / nw;
-  const dim3 rgrid((unsigned)(rneed < kRowBlocks ? (rneed > 0 ? rneed : 1) : kRowBlocks));
-  const dim3 hgrid(kHeavyBlocks);
+  const int64_t rmax = light_row_blocks(c);
+  const dim3 rgrid((unsigned)(rneed < rmax ? (rneed > 0 ? rneed : 1) : rmax));
+  const dim3 hgrid((unsigned)heavy_row_blocks(c));
   const int32_t *light = b.rlist, *heavy = b.rlist + c->V;
   const int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
@@ -1996,10 +2005,12 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
     // at 512 slots (a row's distinct columns never exceed its insertions, so
     // rows below 512 insertions always fit) and grow with the capacity
     // reported by a row that did not fit
-    const int lslots = 2 * kLightEnt;
+    const int lslots = 2 * ra.light_bound;
     int hslots = 512;
     while (hslots < c->caps.row_entries && hslots < 4096) hslots <<= 1;
-    auto lds = [&](int sl, int pass, bool heavy) { return (size_t)nw * row_lds_wave<R>(sl, pass, heavy); };
+    auto lds = [&](int sl, int pass, bool heavy) {
+      return (size_t)nw * row_lds_wave<R>(sl, pass, heavy, ra.light_bound);
+    };
     if ((e = fork()) != hipSuccess) return e;
     if (sums) mtri(hs);  // read by the writing pass
     prof_mark(c, ST_ROWS_COUNT_H, 0);

@@ -457,9 +457,13 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
   __shared__ int32_t ipfx[kQueryWaves][kWave], istart[kQueryWaves][kWave], islab[kQueryWaves][kWave];
   __shared__ int blk_req;  // candidates requested by this block's triangles (LDS atomics)
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  // logical block: consecutive logical blocks run on one XCD, so each XCD
+  // walks its own contiguous stretch of every sweep over the list and the
+  // master boxes and cells of neighbouring triangles stay in its L2
+  const int lblk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t nlist = *qcount;
   if (cell_start[total_cells] > cap_items) {  // grid incomplete
-    for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
+    for (int64_t li = (int64_t)lblk * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
       if (lane == 0) cand_cnt[qlist[li]] = 0;
     if (threadIdx.x == 0) cand_blk[blockIdx.x] = 0;
     return;
@@ -471,7 +475,7 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
   if (threadIdx.x == 0) blk_req = 0;
   __syncthreads();
   // the waves walk the query list (triangles whose prism meets occupied cells)
-  for (int64_t li = (int64_t)blockIdx.x * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
+  for (int64_t li = (int64_t)lblk * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
     [&](const int64_t t) {
   wave_sync();  // the previous triangle's LDS reads are done
   const int e = s_env[t];
@@ -716,7 +720,8 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (c->query_grid_max == 0)
     c->query_grid_max = std::min<int64_t>(kQueryBlocks, sizeof(R) == 4 ? resident_blocks(c, k_query_f32, kThreads, 0)
                                                                       : resident_blocks(c, k_query_f64, kThreads, 0));
-  const int64_t qb = std::min<int64_t>((c->Ts + kQueryWaves - 1) / kQueryWaves, c->query_grid_max);
+  const int64_t qmax = c->tune.query_blocks > 0 ? c->tune.query_blocks : c->query_grid_max;
+  const int64_t qb = std::min<int64_t>((c->Ts + kQueryWaves - 1) / kQueryWaves, qmax);
   const dim3 qgrid((unsigned)(qb > 0 ? qb : 1));
   prof_mark(c, ST_QUERY_COUNT, 0);
   c->query_blocks = c->Ts ? (int)qgrid.x : 0;

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
                                                           const double *__restrict__ rule, const R *__restrict__ dxs,
                                                           const R *__restrict__ dxm, uint32_t *bits) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int tile_id = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * (kThreads / kWave) + threadIdx.x / kWave;
   const bool ok = tile_id < n_tiles && (int64_t)st->n_active <= cap_active;
   float a = INFINITY;
   int e = -1;
@@ -115,7 +115,9 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
 }
 
 // squared distance from the origin-relative point p to triangle (a, b, c):
-// closest point by Voronoi regions of the vertices, edges and face
+// closest point by Voronoi regions of the vertices, edges and face (the
+// published closest-point-on-triangle method: C. Ericson, Real-Time
+// Collision Detection, Morgan Kaufmann 2005, Sec. 5.1.5)
 template <typename R>
 __device__ inline R pt_tri_dist2(const R p[3], const R a[3], const R b[3], const R c[3]) {
   R ab[3], ac[3], ap[3];
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
   __shared__ int32_t pcnt[kThreads / kWave][kWave];
   __shared__ int32_t qpt[kThreads / kWave][2 * kWave], qm[kThreads / kWave][2 * kWave];  // pair queue
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int tile_id = blockIdx.x * (kThreads / kWave) + w;
+  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * (kThreads / kWave) + w;
   float amin = INFINITY;
   int e = -1;
   unsigned long long npairs = 0;

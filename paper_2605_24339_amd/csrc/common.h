@@ -173,6 +173,7 @@ struct gmcp_ctx {
   int query_blocks;  // grid of the last query (its entries of b.cand_blk are valid)
   int n_cu;          // compute units of the context's device
   int64_t query_grid_max;  // resident query blocks (0 until the first broad phase)
+  gmcp_tuning tune;        // launch shapes (gmcp_set_tuning; zeros = defaults)
   gmcp::Buffers b;
   size_t scan_tmp_elems;
 };
@@ -190,6 +191,20 @@ inline int64_t resident_blocks(const gmcp_ctx *c, K kernel, int threads, size_t 
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   return (int64_t)per_cu * (c->n_cu > 0 ? c->n_cu : 1);
+}
+
+// launch shapes in effect (gmcp_tuning, defaults for zeros)
+constexpr int kDefaultLightBound = 128;   // column insertions of a light BSR row
+constexpr int kDefaultRowBlocks = 65536;  // light-row grid
+constexpr int kDefaultHeavyBlocks = 2048; // heavy-row grid
+inline int light_row_bound(const gmcp_ctx *c) {
+  return c->tune.light_row_bound ? c->tune.light_row_bound : kDefaultLightBound;
+}
+inline int light_row_blocks(const gmcp_ctx *c) {
+  return c->tune.light_row_blocks ? c->tune.light_row_blocks : kDefaultRowBlocks;
+}
+inline int heavy_row_blocks(const gmcp_ctx *c) {
+  return c->tune.heavy_row_blocks ? c->tune.heavy_row_blocks : kDefaultHeavyBlocks;
 }
 
 // ------------------------------------------------------------ launchers

@@ -329,6 +329,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   c->swept_ready = false;
   c->query_blocks = 0;
   c->query_grid_max = 0;
+  c->tune = gmcp_tuning{0, 0, 0, 0};
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -517,6 +518,26 @@ int gmcp_set_stream(gmcp_ctx *c, void *stream) {
   return GMCP_OK;
 }
 
+int gmcp_set_tuning(gmcp_ctx *c, const gmcp_tuning *t) {
+  if (!c || !t) return GMCP_E_ARG;
+  const int lb = t->light_row_bound;
+  if (t->query_blocks < 0 || t->query_blocks > gmcp::kQueryBlocks) return GMCP_E_ARG;
+  if (lb != 0 && lb != 32 && lb != 64 && lb != 128 && lb != 256) return GMCP_E_ARG;
+  if (t->light_row_blocks < 0 || t->light_row_blocks > (1 << 20)) return GMCP_E_ARG;
+  if (t->heavy_row_blocks < 0 || t->heavy_row_blocks > 65536) return GMCP_E_ARG;
+  c->tune = *t;
+  return GMCP_OK;
+}
+
+int gmcp_get_tuning(const gmcp_ctx *c, gmcp_tuning *t) {
+  if (!c || !t) return GMCP_E_ARG;
+  t->query_blocks = c->tune.query_blocks ? c->tune.query_blocks : (int32_t)c->query_grid_max;
+  t->light_row_bound = gmcp::light_row_bound(c);
+  t->light_row_blocks = gmcp::light_row_blocks(c);
+  t->heavy_row_blocks = gmcp::heavy_row_blocks(c);
+  return GMCP_OK;
+}
+
 int64_t gmcp_num_samples(const gmcp_ctx *c) { return c ? c->Ns : -1; }
 
 int gmcp_rule(int n, double *out) {
@@ -602,7 +623,7 @@ int gmcp_assemble(gmcp_ctx *c, const void *xs, const void *xm, const void *g_ref
                   void *energy, void *grad, const gmcp_bsr *H) {
   if (!c || !xs || (c->Tm > 0 && !xm) || !energy || !c->samples_built || !c->broadphase_done)
     return GMCP_E_ARG;
-  if (c->mortar && (g_ref || dgap)) return GMCP_E_ARG;  // clipped samples have no fixed ids
+  if (c->mortar && dgap) return GMCP_E_ARG;  // clipped samples have no fixed ids (g_ref: one per slave triangle)
   if (H && (!H->row_ptr || (H->cap_nnzb > 0 && (!H->col || !H->val)) || H->cap_nnzb < 0 ||
             H->cap_nnzb >= (int64_t(1) << 31)))
     return GMCP_E_ARG;

@@ -82,6 +82,7 @@ class Context:
         self.kinematic = bool(kinematic)
         self._side = None          # second stream of the overlapped step (created on first use)
         self._profiling = False
+        self._tuning = None        # launch shapes (gmcp_set_tuning), kept across re-creation
         self.mortar = bool(mortar) or bool(features)
         self.features = bool(features)
         self.ts = torch.as_tensor(slave_tri, dtype=torch.int32).to(self.device).contiguous()
@@ -150,6 +151,8 @@ class Context:
         self.val = torch.zeros(self.cap_nnzb, 3, 3, dtype=self.dtype, device=self.device)
         self.alpha = torch.ones(self.n_env, dtype=self.dtype, device=self.device)
         self._bsr = N.Bsr(_ptr(self.row_ptr), _ptr(self.col), _ptr(self.val), self.cap_nnzb)
+        if self._tuning is not None:
+            _check(N.lib().gmcp_set_tuning(self._ctx, C.byref(self._tuning)), "gmcp_set_tuning")
         if self._x_rest is not None:
             self.build_samples(self._x_rest)
 
@@ -180,6 +183,23 @@ class Context:
         if v.dtype != self.dtype or v.device != self.device or not v.is_contiguous() or v.numel() != n:
             raise ValueError(f"{name}: expected contiguous [{n}] {self.dtype} on {self.device}")
         return v
+
+    TUNING_FIELDS = ("query_blocks", "light_row_bound", "light_row_blocks", "heavy_row_blocks")
+
+    def set_tuning(self, **shapes):
+        """Launch shapes of the list-walking kernels (gmcp_tuning; 0 = the
+        default); fields not given keep their current value."""
+        cur = self._tuning if self._tuning is not None else N.Tuning(0, 0, 0, 0)
+        vals = {f: int(shapes.get(f, getattr(cur, f))) for f in self.TUNING_FIELDS}
+        t = N.Tuning(*[vals[f] for f in self.TUNING_FIELDS])
+        _check(N.lib().gmcp_set_tuning(self._ctx, C.byref(t)), "gmcp_set_tuning")
+        self._tuning = t
+
+    def tuning(self) -> dict:
+        """Launch shapes in effect (defaults filled in)."""
+        t = N.Tuning()
+        _check(N.lib().gmcp_get_tuning(self._ctx, C.byref(t)), "gmcp_get_tuning")
+        return {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}
 
     def status(self) -> N.StatusInfo:
         info = N.StatusInfo()
@@ -238,9 +258,9 @@ class Context:
                  check: bool = True) -> Assembly:
         xs = self._x(xs, self.Vs, "x_slave")
         xm = self._x(xm, self.Vm, "x_master")
-        g_ref = self._vec(g_ref, self.Ns, "g_ref")
+        g_ref = self._vec(g_ref, self.Ts if self.mortar else self.Ns, "g_ref")
         delta_gap = self._vec(delta_gap, self.Ns, "delta_gap")
-        for _ in range(4):
+        for _ in range(6):  # capacities only grow; a row table grows to its final size at once
             self._bind()
             rc = N.lib().gmcp_assemble(self._ctx, _ptr(xs), _ptr(xm), _ptr(g_ref), _ptr(delta_gap),
                                        _ptr(self.energy), _ptr(self.grad) if grad else None,

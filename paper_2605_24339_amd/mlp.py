@@ -110,12 +110,15 @@ class MLP:
         _check(_lib().gmcp_mlp_adam(_ptr(self.p), _ptr(g), _ptr(self.m), _ptr(self.v), self.n, lr, b1, b2, eps,
                                     self.step, _stream(self.dev)), "gmcp_mlp_adam")
 
-    def train(self, X, T, epochs=3, batch=65536, lr=1e-3, seed=0, log=None):
-        """Minibatch Adam on rows (X [R][16], T [R][16] device tensors)."""
+    def train(self, X, T, epochs=3, batch=65536, lr=1e-3, seed=0, log=None, lr_min=None):
+        """Minibatch Adam on rows (X [R][16], T [R][16] device tensors); with
+        lr_min the rate follows a cosine from lr down to lr_min over the run."""
         R = X.shape[0]
         gen = torch.Generator(device="cpu").manual_seed(seed)
         hist = []
         act = torch.empty(batch, 6 * 128, dtype=torch.float32, device=self.dev)
+        total = max(1, epochs * (R // batch))
+        k = 0
         for ep in range(epochs):
             perm = torch.randperm(R, generator=gen).to(self.dev)
             tot, ns, nb = 0.0, 0, 0
@@ -125,7 +128,9 @@ class MLP:
                 y, a = self.forward(xb, act)
                 loss, dy = self.mse(y, tb)
                 g = self.backward(xb, a, dy)
-                self.adam(g, lr=lr)
+                rate = lr if lr_min is None else lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * k / total))
+                self.adam(g, lr=float(rate))
+                k += 1
                 if nb % 16 == 0:          # sampled batch losses (a host sync each)
                     tot += float(loss.item())
                     ns += 1
@@ -134,16 +139,6 @@ class MLP:
             if log:
                 log(f"epoch {ep}: {nb} batches")
         return hist
-
-
-def features(x_t, v_t, d_prev, center, L, h, dt):
-    """[V][16] inputs: (x_t - center)/L, v_t dt / h, d_prev / h, zero padding."""
-    V = x_t.shape[0]
-    f = torch.zeros(V, PAD, dtype=torch.float32, device=x_t.device)
-    f[:, 0:3] = ((x_t - center) / L).float()
-    f[:, 3:6] = (v_t * dt / h).float()
-    f[:, 6:9] = (d_prev / h).float()
-    return f
 
 
 def targets(x_star, x_t, v_t, dt, h):

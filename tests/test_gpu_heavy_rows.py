@@ -5,8 +5,8 @@ A fine pad (48 x 48 quads, one sample per triangle) under a punch of two
 master triangles that covers it: each of the punch's four vertices couples
 to about 1200-2400 slave vertices, so its BSR row needs the largest table
 (4096 slots).  The first assemblies report a capacity error from those rows;
-the binding grows the table three times (512 -> 1024 -> 2048 -> 4096 slots)
-and the grown result must match the oracle, in float and double."""
+the binding grows the table once, to the row's insertion count (4096
+slots), and the grown result must match the oracle, in float and double."""
 import numpy as np
 import pytest
 

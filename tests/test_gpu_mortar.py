@@ -131,6 +131,43 @@ def test_large_indent_mortar_pair_set_sampled():
         assert all(_band(g, P.dhat) for g in by_pair.get(k, [])), (k, by_pair.get(k))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_mortar_reference_gaps_per_slave_triangle(dtype):
+    """Eq. (adaptive_eps) for clipped samples: one reference gap per slave
+    triangle, eps_T = min(0.9 g_ref[T], dhat) for all of T's samples; energy,
+    gradient and Hessian against the oracle given the same gaps, and fewer
+    active samples than without them."""
+    need_gpu()
+    fp32 = dtype == "f32"
+    tdt = torch.float32 if fp32 else torch.float64
+    w = workloads.small_indent(fp32=fp32)
+    P = workloads.to_problem(w)
+    rng = np.random.default_rng(12)
+    g_ref = rng.uniform(0.2, 2.0, size=P.ts.shape[0]) * w.dhat
+    if fp32:
+        g_ref = g_ref.astype(np.float32).astype(np.float64)
+    ctx = _ctx(w, tdt)
+    xs, xm = to_dev(w.xs, tdt), to_dev(w.xm, tdt)
+    ctx.build_samples(to_dev(w.xs_rest, tdt))
+    ctx.broadphase(xs, xm)
+    A = ctx.assemble(xs, xm, g_ref=to_dev(g_ref, tdt))
+    n_act = int(ctx.status().n_active)
+    O = om.assemble(P, om.samples(P, g_ref_tri=g_ref))
+    O_plain = om.assemble(P, om.samples(P))
+    assert 300 < len(O.active) < len(O_plain.active)
+    assert abs(n_act - len(O.active)) <= 2
+    te, tg = (1e-5, 1e-4) if fp32 else (1e-10, 1e-10)
+    assert abs(float(A.energy.double().sum()) / O.energy - 1) <= te
+    assert rel_fro(A.grad.double().cpu().numpy(), O.grad) <= tg
+    rp, col, val = _oracle_bsr(O.blocks, P.Vs + P.Vm)
+    H = A.hessian
+    assert bsr_rel_error(H.row_ptr.cpu().numpy(), H.col.cpu().numpy(), H.val.double().cpu().numpy().reshape(-1, 9),
+                         rp, col, val) <= tg
+    # the frozen energy keeps each sample's radius
+    e0 = float(ctx.energy_frozen(xs, xm).double().sum())
+    assert abs(e0 / float(A.energy.double().sum()) - 1) <= te
+
+
 def test_flat_punch_mortar_exact_area_on_gpu():
     """Independently meshed smaller punch: the energy is kappa B(g0) times
     the punch area (whole-triangle samples only approximate it)."""
@@ -156,7 +193,7 @@ def test_mortar_deterministic_and_argument_rules():
     with pytest.raises(GMCPError):
         ctx.sample_results()
     with pytest.raises(GMCPError):
-        ctx.assemble(xs, xm, g_ref=torch.ones(ctx.Ns, device="cuda"))
+        ctx.assemble(xs, xm, delta_gap=torch.ones(ctx.Ns, device="cuda"))
 
 
 def test_large_indent_mortar_sampled_gradient_rows():

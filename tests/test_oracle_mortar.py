@@ -197,3 +197,28 @@ def test_feature_gradient_against_frozen_energy_differences():
     assert abs(fd - an) <= 1e-6 * abs(an)
     kinds = {s.kind for s in A.active}
     assert kinds == {0, 1, 2}
+
+
+def test_reference_gaps_per_slave_triangle_closed_form():
+    """Eq. (adaptive_eps) for clipped samples, one reference gap per slave
+    triangle: under a punch at uniform gap g0 that covers the pad, the energy
+    is sum_T kappa A_T B(g0, eps_T) with eps_T = min(0.9 g_ref[T], dhat) (B = 0
+    when g0 >= eps_T), and a triangle whose radius shrinks below the gap
+    keeps no active sample."""
+    g0 = 3e-4
+    w = workloads.flat_punch(gap=g0, n_pad=6, n_punch=5, rule_n=2)
+    P = workloads.to_problem(w)
+    rng = np.random.default_rng(3)
+    g_ref = rng.uniform(0.2e-3, 2e-3, size=P.ts.shape[0])
+    eps = np.minimum(0.9 * g_ref, P.dhat)
+    assert (eps <= g0).any() and ((eps > g0) & (eps < P.dhat)).any() and (eps == P.dhat).any()
+    S = mortar.samples(P, g_ref_tri=g_ref)
+    O = mortar.assemble(P, S)
+    area = oracle.rest_area(P.xs_rest, P.ts)
+    expect = sum(P.kappa * area[T] * oracle.barrier(g0, eps[T]) for T in range(P.ts.shape[0]))
+    assert abs(O.energy / expect - 1) <= 1e-10
+    active_tris = {s.T for s in O.active}
+    assert active_tris == set(np.nonzero(eps > g0)[0].tolist())
+    # without reference gaps every triangle has the full radius
+    O0 = mortar.assemble(P, mortar.samples(P))
+    assert abs(O0.energy / (P.kappa * area.sum() * oracle.barrier(g0, P.dhat)) - 1) <= 1e-10
