@@ -26,14 +26,17 @@ sys.path.insert(0, ROOT)
 OUT = os.path.join(HERE, "unit_counts.json")
 
 
+# the sources the counts depend on: the workload generators and the
+# whole-triangle oracle (selection, assembly, swept pairs)
+SOURCES = ("gen/meshes.py", "gen/workloads.py", "oracle/__init__.py", "oracle/gmcp_oracle.c", "oracle/rule.py")
+
+
 def source_hash() -> str:
     """Hash of the generator and oracle sources the counts depend on."""
     h = hashlib.sha256()
-    for d in ("gen", "oracle"):
-        for f in sorted(os.listdir(os.path.join(ROOT, d))):
-            if f.endswith((".py", ".c")):
-                with open(os.path.join(ROOT, d, f), "rb") as fh:
-                    h.update(f.encode() + fh.read())
+    for f in SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
