@@ -1296,9 +1296,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   // the waves walk the list of rows with contributions (k_row_pre)
   const int64_t nlist = *rcount;
   const int nw = blockDim.x / kWave;
-  // logical block: consecutive logical blocks run on one XCD, so neighbouring
-  // rows (which share triangles and pairs) are read through one L2
-  const int lblk = xcd_block(blockIdx.x, gridDim.x);
+  // rows in dispatch order: an XCD-by-XCD mapping of the list measured
+  // several times slower (the rows with work cluster in the list, so the
+  // XCDs holding them finish last)
+  const int lblk = blockIdx.x;
   for (int64_t li = (int64_t)lblk * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
     [&](const int64_t row) {
   wave_sync();  // the previous row's LDS reads are done

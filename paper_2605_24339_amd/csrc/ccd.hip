@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
   __shared__ int32_t pcnt[kThreads / kWave][kWave];
   __shared__ int32_t qpt[kThreads / kWave][2 * kWave], qm[kThreads / kWave][2 * kWave];  // pair queue
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * (kThreads / kWave) + w;
+  const int tile_id = blockIdx.x * (kThreads / kWave) + w;
   float amin = INFINITY;
   int e = -1;
   unsigned long long npairs = 0;

@@ -117,14 +117,14 @@ class ImplicitSolver:
         return x_t + a * d, a
 
     # ---------------------------------------------------------------- step
-    def solve_step(self, x_t, v_t, xm, fixed_pos, x_start=None, safeguard=False) -> tuple:
+    def solve_step(self, x_t, v_t, xm, fixed_pos, x_start=None, safeguard=False, log=None) -> tuple:
         """One implicit step.  fixed_pos: positions of the Dirichlet vertices
         at the end of the step ([V, 3] tensor, only fixed rows are read).
         x_start: optional starting guess (the plain start is x_t + dt v_t);
         it passes the same feasibility filter as the plain start.  With
         safeguard, both filtered starts are evaluated (two energy-only
         evaluations) and the one with the lower incremental potential is
-        used."""
+        used.  log(str), optional, receives one line per Newton iteration."""
         st = StepStats()
         fx = self.fem.fixed
         x_tilde = x_t + self.fem.dt * v_t
@@ -154,13 +154,17 @@ class ImplicitSolver:
             st.newton_iters += 1
             gn = float(g.norm().item())
             rtol = min(self.cg_rtol, max(1e-10, (st.residual / 10.0)))
-            d, cg_it, _ = self.fem.solve(H, (-g).contiguous(), rtol=rtol, max_iter=self.cg_max)
+            if log:
+                log(f"  newton {it}: E {E:.6e} r {st.residual:.3e} active {int(self.contact.status().n_active)} "
+                    f"cg rtol {rtol:.1e}")
+            d, cg_it, cg_res = self.fem.solve(H, (-g).contiguous(), rtol=rtol, max_iter=self.cg_max)
             st.cg_iters += cg_it
             slope = float((g * d).sum().item())
             if not slope < 0.0:      # not a descent direction: fall back to steepest descent
                 d = -g / max(gn, 1e-300)
                 slope = float((g * d).sum().item())
-            a = min(1.0, self._ccd(x, xm, d))
+            a_ccd = self._ccd(x, xm, d)
+            a = min(1.0, a_ccd)
             E0 = self.model_energy(x, x_tilde, xm)
             while True:
                 xn = (x + a * d).contiguous()
@@ -173,5 +177,8 @@ class ImplicitSolver:
                     break
                 a *= 0.5
             st.alphas.append(a)
+            if log:
+                log(f"    cg {cg_it} it, rel res {cg_res:.2e}; step {a:.3e} (bound {a_ccd:.3e}), "
+                    f"|d|inf {float(d.abs().max()):.3e}")
             x = xn
         return x, st

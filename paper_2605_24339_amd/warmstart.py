@@ -17,7 +17,12 @@ the gel's inertia is four orders of magnitude below its stiffness, so the
 response is quasi-static and the frame does not matter), which keeps the
 contact context's master mesh fixed between steps.  The tactile surface
 (slave) is the top face, 2 x 2 samples per triangle, dhat = 1 mm,
-kappa = 1e5.
+kappa = 2.5e6: a contact pressure of about 3e4 Pa (10 % strain of the gel)
+balances the barrier at a gap of about 0.1 mm, above the sag of the
+sphere's facets (25 to 70 um); at kappa = 1e5 the same pressure needs gaps
+of a few um, below the facets' sag, and the indenter's vertices then press
+between the slave samples where no sample resists them, which stalls
+Newton against the step bound.
 
 The network sees each vertex's position in the indenter's frame (lateral
 offset from the sphere's axis in radii and the log of the distance to its
@@ -48,7 +53,7 @@ from .mlp import MLP, PAD, targets
 from .newton import ImplicitSolver
 
 E_Y, NU, RHO, DT = 3e5, 0.45, 1000.0, 1e-3
-KAPPA = 1e5
+KAPPA = 2.5e6
 
 
 class Scene:
@@ -139,9 +144,9 @@ class Scaler:
 
 
 def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, log=None, scaler=None,
-                   safeguard=True):
+                   safeguard=True, newton_log=None):
     """Simulate; returns per-step records (features and targets kept on the
-    device when keep)."""
+    device when keep).  newton_log receives the solver's per-iteration lines."""
     dev = scene.device
     solver = scene.make_solver()
     x = torch.tensor(scene.X, device=dev)
@@ -164,9 +169,9 @@ def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, 
             pred = scaler.y(y).double() * scene.h
             if torch.isfinite(pred).all():
                 x_start = x + DT * v + pred
-        xn, st = solver.solve_step(x, v, xm, plate, x_start=x_start, safeguard=safeguard)
+        xn, st = solver.solve_step(x, v, xm, plate, x_start=x_start, safeguard=safeguard, log=newton_log)
         if net is not None and (not st.converged or st.start_alpha < 1e-3):
-            xn, st = solver.solve_step(x, v, xm, plate)     # fall back to the plain start
+            xn, st = solver.solve_step(x, v, xm, plate, log=newton_log)     # fall back to the plain start
             st.fallback = True
         el = time.perf_counter() - t0
         d = xn - (x + DT * v)
