@@ -31,7 +31,9 @@ int64_t gmcp_mlp_param_count(void);
 size_t gmcp_mlp_work_bytes(int64_t B);
 
 /* y [B][16] = MLP(x [B][16]); act [B][768] receives Z1|H1|Z2|H2|Z3|H3
- * (required: the backward pass reads it). */
+ * (nullable: inference; the backward pass reads it).  One fused launch:
+ * each wave runs all four layers on 32 rows with the activations in
+ * registers and the weights staged once per block in LDS as bf16. */
 int gmcp_mlp_forward(const float *params, const float *x, int64_t B, float *y, float *act, void *stream);
 
 /* grad [param_count] = d(loss)/d(params) given dy [B][16] = d(loss)/dy and

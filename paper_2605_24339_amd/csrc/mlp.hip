@@ -31,6 +31,7 @@ static __device__ __align__(256) float scratch[kMseScratch];
 
 namespace {
 
+using gmcp::kWave;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -186,6 +187,162 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ---------------------------------------------------------------- fused forward
+// The whole network for 32 rows per wave, activations in registers.  Each
+// layer is computed transposed, out^T (features x rows) = W^T (features x
+// k) . in^T (k x rows), on v_mfma_f32_32x32x16_bf16, so the accumulator of
+// a 32-feature output tile holds, in lane l, row (l & 31) and features
+// (r >> 2) * 8 + 4 (l >> 5) + (r & 3) of its register r.  Those registers
+// are exactly the B operand of the next layer's k-steps if the k slots are
+// taken in that order: slot j of lane half h in k-step s stands for input
+// feature 16 s + (j >> 2) * 8 + 4 h + (j & 3).  The weights are staged once
+// per block into LDS as bf16 A fragments in the same slot order (64 lanes x
+// 8 values, one 16-byte read per lane and MFMA), so the activations never
+// leave the registers between layers.
+constexpr int kFrag = kWave * 8;                     // bf16 per A fragment
+constexpr int kFragL1 = 4, kFragL2 = 32, kFragL3 = 32, kFragL4 = 8;  // 32-feature tiles x k-steps
+constexpr int kFragAll = kFragL1 + kFragL2 + kFragL3 + kFragL4;      // 76 fragments, 76 KB
+constexpr int kFusedWaves = 8;
+
+__device__ inline int slot_feature(int s, int h, int j) { return 16 * s + (j >> 2) * 8 + 4 * h + (j & 3); }
+
+template <bool SAVE>
+__global__ __launch_bounds__(kWave *kFusedWaves) void k_mlp_fwd(const float *__restrict__ P,
+                                                                const float *__restrict__ x, int64_t B,
+                                                                float *__restrict__ y, float *__restrict__ act) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16 *wf = reinterpret_cast<__bf16 *>(smem);  // [kFragAll][64 lanes][8]
+  // stage: fragment f of layer L = (tile t, k-step s), lane l, slot j holds
+  // W_L[k = slot_feature(s, l >> 5, j)][n = 32 t + (l & 31)] (0 beyond N).
+  // A fragment is the 16 x 32 block of W_L at rows 16 s.., columns 32 t..;
+  // consecutive threads read consecutive columns of a row (coalesced) and
+  // place each value at its lane and slot
+  // (eight loads in flight per thread: the staging is latency-bound)
+  constexpr int kStage = kFragAll * kFrag, kBatch = 8;
+  for (int e0 = threadIdx.x; e0 < kStage; e0 += kBatch * blockDim.x) {
+    float v[kBatch];
+    int dst[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * blockDim.x;
+      v[u] = 0.0f;
+      dst[u] = -1;
+      if (e < kStage) {
+        const int f = e / kFrag, kl = (e % kFrag) / 32, nl = e % 32;
+        int ff, S, N, K;
+        int64_t off;
+        if (f < kFragL1) { ff = f; S = 1; N = HID; K = IN; off = OFF_W1; }
+        else if (f < kFragL1 + kFragL2) { ff = f - kFragL1; S = 8; N = HID; K = HID; off = OFF_W2; }
+        else if (f < kFragL1 + kFragL2 + kFragL3) { ff = f - kFragL1 - kFragL2; S = 8; N = HID; K = HID; off = OFF_W3; }
+        else { ff = f - kFragL1 - kFragL2 - kFragL3; S = 8; N = OUT; K = HID; off = OFF_W4; }
+        const int t = ff / S, sk = ff % S;
+        const int n = 32 * t + nl, k = 16 * sk + kl;
+        // k local = (j >> 2) * 8 + 4 h + (j & 3)  <=>  h = (kl >> 2) & 1, j = (kl >> 3) * 4 + (kl & 3)
+        const int h = (kl >> 2) & 1, j = ((kl >> 3) << 2) | (kl & 3);
+        dst[u] = f * kFrag + (nl + 32 * h) * 8 + j;
+        if (n < N && k < K) v[u] = P[off + (int64_t)k * N + n];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (dst[u] >= 0) wf[dst[u]] = (__bf16)v[u];
+  }
+  __syncthreads();
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int h = lane >> 5;
+  const int64_t tiles = (B + 31) / 32;
+  const bf16x8 *frag = reinterpret_cast<const bf16x8 *>(wf);  // frag[f * 64 + lane]
+  for (int64_t tile = (int64_t)blockIdx.x * kFusedWaves + w; tile < tiles; tile += (int64_t)gridDim.x * kFusedWaves) {
+    const int64_t row = tile * 32 + (lane & 31);
+    const bool live = row < B;
+    // layer 1 input: x features {4h..4h+3, 8+4h..8+4h+3} of the lane's row
+    bf16x8 bin;
+    {
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
+      if (live) {
+        a = *reinterpret_cast<const float4 *>(x + row * IN + 4 * h);
+        c = *reinterpret_cast<const float4 *>(x + row * IN + 8 + 4 * h);
+      }
+      bin[0] = (__bf16)a.x; bin[1] = (__bf16)a.y; bin[2] = (__bf16)a.z; bin[3] = (__bf16)a.w;
+      bin[4] = (__bf16)c.x; bin[5] = (__bf16)c.y; bin[6] = (__bf16)c.z; bin[7] = (__bf16)c.w;
+    }
+    // a layer's output as the next layer's B operands (one per k-step);
+    // tiles run one at a time (not unrolled, so few fragments are in flight)
+    // and their operands are placed by selects, keeping every index static
+    bf16x8 hcur[8], hnext[8];
+    // bias + SiLU on the accumulator of output tile t, optional save of Z and
+    // H, and the bf16 operands of k-steps 2t (lo) and 2t + 1 (hi)
+    auto epilogue = [&](const f32x16 &acc, int t, const float *bias, int save_off) {
+      bf16x8 lo, hi;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // four groups of four consecutive features
+        const int f0 = 32 * t + q * 8 + 4 * h;
+        float z[4], hv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          z[i] = acc[4 * q + i] + bias[f0 + i];
+          hv[i] = silu(z[i]);
+          if (q < 2) lo[4 * q + i] = (__bf16)hv[i];
+          else hi[4 * (q - 2) + i] = (__bf16)hv[i];
+        }
+        if (SAVE && live) {
+          *reinterpret_cast<float4 *>(act + row * ACT + save_off + f0) = make_float4(z[0], z[1], z[2], z[3]);
+          *reinterpret_cast<float4 *>(act + row * ACT + save_off + HID + f0) =
+              make_float4(hv[0], hv[1], hv[2], hv[3]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k == 2 * t) hnext[k] = lo;
+        if (k == 2 * t + 1) hnext[k] = hi;
+      }
+    };
+    // layer 1: K = 16, one k-step
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+      f32x16 zero = {};
+      const f32x16 a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[t * kWave + lane], bin, zero, 0, 0, 0);
+      epilogue(a, t, P + OFF_B1, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) hcur[k] = hnext[k];
+    // layers 2 and 3: K = 128, eight k-steps per output tile
+#pragma unroll 1
+    for (int L = 0; L < 2; ++L) {
+      const int fbase = kFragL1 + L * kFragL2;
+#pragma unroll 1
+      for (int t = 0; t < 4; ++t) {
+        f32x16 a = {};
+#pragma unroll
+        for (int sk = 0; sk < 8; ++sk)
+          a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(fbase + t * 8 + sk) * kWave + lane], hcur[sk], a, 0, 0,
+                                                      0);
+        epilogue(a, t, P + (L == 0 ? OFF_B2 : OFF_B3), (L + 1) * 2 * HID);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) hcur[k] = hnext[k];
+    }
+    // layer 4: one 32-feature tile, the first 16 are the outputs
+    {
+      const int fbase = kFragL1 + kFragL2 + kFragL3;
+      f32x16 a = {};
+#pragma unroll
+      for (int sk = 0; sk < 8; ++sk)
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(fbase + sk) * kWave + lane], hcur[sk], a, 0, 0, 0);
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int f0 = q * 8 + 4 * h;
+          const float *b4 = P + OFF_B4;
+          *reinterpret_cast<float4 *>(y + row * OUT + f0) =
+              make_float4(a[4 * q] + b4[f0], a[4 * q + 1] + b4[f0 + 1], a[4 * q + 2] + b4[f0 + 2],
+                          a[4 * q + 3] + b4[f0 + 3]);
+        }
+      }
+    }
+  }
+}
+
 inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 template <int EPI>
@@ -244,18 +401,26 @@ size_t gmcp_mlp_work_bytes(int64_t B) {
 
 int gmcp_mlp_forward(const float *params, const float *x, int64_t B, float *y, float *act, void *stream) {
   if (!params || !x || !y || B <= 0 || B > (int64_t(1) << 30)) return GMCP_E_ARG;
-  if (!act) return GMCP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  const float *P = params;
-  const int ld = ACT;
-  float *Z1 = act, *H1 = act + HID, *Z2 = act + 2 * HID, *H2 = act + 3 * HID, *Z3 = act + 4 * HID,
-        *H3 = act + 5 * HID;
-  if (gemm<EPI_BIAS_SILU>(s, x, IN, 0, P + OFF_W1, HID, 0, (int)B, HID, IN, P + OFF_B1, Z1, ld, H1) != hipSuccess ||
-      gemm<EPI_BIAS_SILU>(s, H1, ld, 0, P + OFF_W2, HID, 0, (int)B, HID, HID, P + OFF_B2, Z2, ld, H2) != hipSuccess ||
-      gemm<EPI_BIAS_SILU>(s, H2, ld, 0, P + OFF_W3, HID, 0, (int)B, HID, HID, P + OFF_B3, Z3, ld, H3) != hipSuccess ||
-      gemm<EPI_BIAS>(s, H3, ld, 0, P + OFF_W4, OUT, 0, (int)B, OUT, HID, P + OFF_B4, y, OUT, nullptr) != hipSuccess)
-    return GMCP_E_HIP;
-  return GMCP_OK;
+  // one fused launch: every wave runs the whole network on 32 rows at a
+  // time (weights staged once per block); two blocks fit a CU's LDS
+  // persistent grid: two blocks per compute unit (their LDS), each walking
+  // many row tiles, so the weights are staged once per block
+  static int n_cu[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GMCP_E_HIP;
+  if (n_cu[dev] == 0 && (hipDeviceGetAttribute(&n_cu[dev], hipDeviceAttributeMultiprocessorCount, dev) !=
+                             hipSuccess || n_cu[dev] < 1))
+    n_cu[dev] = 256;
+  const int64_t tiles = (B + 31) / 32;
+  const int64_t want = (tiles + kFusedWaves - 1) / kFusedWaves;
+  const unsigned grid = (unsigned)std::min<int64_t>(want, 2 * (int64_t)n_cu[dev]);
+  const size_t lds = (size_t)kFragAll * kFrag * sizeof(__bf16);
+  if (act)
+    hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(kWave * kFusedWaves), lds, s, params, x, B, y, act);
+  else
+    hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(kWave * kFusedWaves), lds, s, params, x, B, y, act);
+  return hipGetLastError() == hipSuccess ? GMCP_OK : GMCP_E_HIP;
 }
 
 int gmcp_mlp_backward(const float *params, const float *x, const float *act, const float *dy, int64_t B, float *grad,

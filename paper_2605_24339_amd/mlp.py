@@ -86,6 +86,14 @@ class MLP:
                "gmcp_mlp_forward")
         return y, act
 
+    def predict(self, x):
+        """y [B][16] = MLP(x) without saving activations (inference)."""
+        B = x.shape[0]
+        y = torch.empty(B, PAD, dtype=torch.float32, device=self.dev)
+        _check(_lib().gmcp_mlp_forward(_ptr(self.p), _ptr(x), B, _ptr(y), None, _stream(self.dev)),
+               "gmcp_mlp_forward")
+        return y
+
     def backward(self, x, act, dy):
         B = x.shape[0]
         g = torch.empty_like(self.p)

@@ -165,7 +165,7 @@ def run_trajectory(scene: Scene, steps: int, net: MLP | None = None, keep=True, 
             feat = features(scene, x, v, d_prev, v_next)
         t0 = time.perf_counter()
         if net is not None:
-            y, _ = net.forward(scaler.x(feat).contiguous())
+            y = net.predict(scaler.x(feat).contiguous())
             pred = scaler.y(y).double() * scene.h
             if torch.isfinite(pred).all():
                 x_start = x + DT * v + pred
@@ -250,17 +250,21 @@ def normalized_loss(net: MLP, scaler: Scaler, X, T, batch=65536) -> float:
     for i in range(0, X.shape[0], batch):
         xb = scaler.x(X[i:i + batch]).contiguous()
         tb = scaler.t(T[i:i + batch])
-        y, _ = net.forward(xb)
+        y = net.predict(xb)
         num += float(((y[:, :3] - tb[:, :3]) ** 2).sum().item())
         den += float((tb[:, :3] ** 2).sum().item())
     return num / max(den, 1e-300)
 
 
 def study(train: int, test: int, steps: int, epochs: int, batch: int, lr: float, lr_min: float | None, n: int, nz: int,
-          safeguard: bool = True, seed0: int = 5000, log=None, save: str | None = None, net=None, scaler=None):
-    """Generate training trajectories with the plain start, train the
-    network on the GPU (unless one is given), and run the held-out
-    trajectories with both starts."""
+          safeguard: bool = True, seed0: int = 5000, log=None, save: str | None = None, net=None, scaler=None,
+          heldout_seed0: int | None = None):
+    """Generate training trajectories with the plain start (seeds seed0..),
+    train the network on the GPU (unless one is given), and run the
+    held-out trajectories (seeds heldout_seed0.., by default right after the
+    training seeds) with both starts."""
+    if heldout_seed0 is None:
+        heldout_seed0 = seed0 + train
     dev = "cuda"
     t0 = time.perf_counter()
     feats, targs, plain_train = [], [], []
@@ -292,7 +296,7 @@ def study(train: int, test: int, steps: int, epochs: int, batch: int, lr: float,
             save_checkpoint(save, net, scaler)
     plain, learned, vx, vt = [], [], [], []
     for j in range(test):
-        sc = Scene(seed0 + train + j, n, nz, device=dev)
+        sc = Scene(heldout_seed0 + j, n, nz, device=dev)
         p = run_trajectory(sc, steps, None, keep=True, log=log)
         for r in p:
             vx.append(r.pop("feat"))
@@ -332,7 +336,8 @@ def main():
     ap.add_argument("--nz", type=int, default=8)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained network and its scaling here (.npz)")
-    ap.add_argument("--load", default=None, help="evaluate this trained network instead of training one")
+    ap.add_argument("--load", default=None,
+                    help="evaluate this trained network (trained on the first --train seeds) instead of training one")
     ap.add_argument("--no-safeguard", action="store_true",
                     help="always start from the network's prediction (no energy comparison with the plain start)")
     args = ap.parse_args()
@@ -340,9 +345,10 @@ def main():
     net = scaler = None
     if args.load:
         net, scaler = load_checkpoint(args.load)
+    # a loaded network was trained on the first args.train seeds: held-out seeds follow them
     report, _, _ = study(0 if args.load else args.train, args.test, args.steps, args.epochs, args.batch, args.lr,
                          args.lr_min, args.n, args.nz, not args.no_safeguard, log=log, save=args.save, net=net,
-                         scaler=scaler)
+                         scaler=scaler, heldout_seed0=5000 + args.train)
     print(json.dumps({k: v for k, v in report.items() if k != "per_step_test"}))
     if args.out:
         with open(args.out, "w") as fh:
