@@ -252,6 +252,25 @@ def measure_mlp(dev, batch: int = 65536, reps: int = 20) -> dict:
         net.adam(net.backward(X, a, dy))
 
     ms = _event_ms(step, reps)
+    # fused forward (one launch, activations in registers): inference and
+    # the training forward that saves the activations
+    Bi = 1 << 18
+    Xi = torch.randn(Bi, PAD, generator=g).to(dev)
+    Xi[:, 9:] = 0.0
+    inf_ms = _event_ms(lambda: net.predict(Xi), reps)
+    acti = torch.empty(Bi, 6 * 128, dtype=torch.float32, device=dev)
+    fwd_ms = _event_ms(lambda: net.forward(Xi, acti), reps)
+    useful = 2 * (9 * 128 + 2 * 128 * 128 + 128 * 3)            # per row, the real network
+    executed = 2 * (16 * 128 + 2 * 128 * 128 + 128 * 32)        # per row, padded MFMA tiles
+    inf_tf = Bi * useful / (inf_ms * 1e-3) / 1e12
+    fused = {"rows": Bi, "inference_ms": inf_ms, "inference_rows_per_s": Bi / (inf_ms * 1e-3),
+             "inference_tflops_useful": inf_tf, "inference_tflops_executed": Bi * executed / (inf_ms * 1e-3) / 1e12,
+             "mfma_peak_tflops": 2500.0, "frac_mfma_peak_executed": Bi * executed / (inf_ms * 1e-3) / 1e12 / 2500.0,
+             "inference_gbs": Bi * 128 / (inf_ms * 1e-3) / 1e9,
+             "forward_saving_activations_ms": fwd_ms,
+             "forward_saving_activations_gbs": Bi * (128 + 4 * 768) / (fwd_ms * 1e-3) / 1e9,
+             "note": "inference reads 64 B and writes 64 B per row; the training forward also writes 3 KiB of "
+                     "activations per row (HBM-bound)"}
     flops = 3 * 2 * batch * (PAD * 128 + 2 * 128 * 128 + 128 * PAD)
     Mg, Ng, Kg = 1 << 18, 128, 128
     A = torch.randn(Mg, Kg, generator=g).to(dev)
@@ -259,10 +278,41 @@ def measure_mlp(dev, batch: int = 65536, reps: int = 20) -> dict:
     gms = _event_ms(lambda: gemm_bf16(A, B), reps)
     tf = 2 * Mg * Ng * Kg / (gms * 1e-3) / 1e12
     return {"train_rows_per_s": batch / (ms * 1e-3), "train_step_ms": ms, "batch": batch,
-            "train_tflops": flops / (ms * 1e-3) / 1e12,
+            "train_tflops": flops / (ms * 1e-3) / 1e12, "fused_forward": fused,
             "gemm": {"M": Mg, "N": Ng, "K": Kg, "ms": gms, "tflops": tf, "mfma_peak_tflops": 2500.0,
                      "gbs": 4 * (Mg * Kg + Kg * Ng + Mg * Ng) / (gms * 1e-3) / 1e9, "hbm_peak_gbs": HBM_PEAK_GBS,
                      "note": "float32 operands converted to bf16 on load, float32 out: HBM-bound at K = 128"}}
+
+
+WARMSTART_CHECKPOINT = os.path.join(ROOT, "paper_2605_24339_amd", "data", "warmstart_mlp.npz")
+
+
+def measure_warmstart(steps: int = 100, seeds=(5045, 5046)) -> dict | None:
+    """Newton iterations and assemblies per implicit step to reach the
+    1e-6 residual, plain start (x_t + dt v_t) against the learned start
+    (the committed network, trained on tap trajectories 5000..5019), on
+    held-out tap trajectories of the gel block; both starts pass the same
+    step-bound filter, the learned one also the energy safeguard."""
+    if not os.path.exists(WARMSTART_CHECKPOINT):
+        return None
+    from paper_2605_24339_amd import warmstart as W
+    net, scaler = W.load_checkpoint(WARMSTART_CHECKPOINT)
+    plain, learned = [], []
+    t0 = time.perf_counter()
+    for sd in seeds:
+        sc = W.Scene(sd)
+        plain += W.run_trajectory(sc, steps, None, keep=False)
+        learned += W.run_trajectory(sc, steps, net, keep=False, scaler=scaler, safeguard=True)
+    P, L = W.summarize(plain), W.summarize(learned)
+    out = {"workload": "64x64x8-cube gel block (38025 vertices) tapped by a sphere at 10-100 mm/s, dt = 1 ms, "
+                       f"held-out trajectories {list(seeds)}, {steps} steps each, residual 1e-6",
+           "newton_plain": P["newton"]["mean"], "newton_learned": L["newton"]["mean"],
+           "assemblies_plain": P["assemblies"]["mean"], "assemblies_learned": L["assemblies"]["mean"],
+           "energy_evals_plain": P["energy_evals"]["mean"], "energy_evals_learned": L["energy_evals"]["mean"],
+           "all_converged": bool(P["all_converged"] and L["all_converged"]),
+           "learned_start_chosen": L["learned_start_chosen"], "seconds": time.perf_counter() - t0}
+    out["newton_ratio_learned_over_plain"] = out["newton_learned"] / out["newton_plain"]
+    return out
 
 
 def measure_dualmesh(dev, reps: int = 50) -> dict:
@@ -554,6 +604,7 @@ def main():
                            "active_samples": fe["gpu_counts"]["active"], "pairs": fe["gpu_counts"]["pairs"],
                            "stage_ms": fe["stages"]}
         out["patch_test"] = measure_patch(dev)
+        out["newton_iters_learned_vs_plain"] = measure_warmstart()
     if not args.no_cpu_baseline:
         nt = oracle_threads()
         cb = cpu_baseline(B.envs, args.cpu_seconds, nt)
