@@ -381,7 +381,7 @@ int scratch_address(hipStream_t s, float **out) {
   return GMCP_OK;
 }
 
-constexpr int kSplitRows = 4096;  // batch rows per split-K chunk of a weight gradient
+constexpr int kSplitRows = 512;  // batch rows per split-K chunk of a weight gradient (enough blocks to fill the device)
 
 int splits_for(int64_t B) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (B + kSplitRows - 1) / kSplitRows)); }
 
