@@ -91,7 +91,9 @@ typedef enum {
   GMCP_E_PENETRATION = 3, /* an inside opposing hit with -eps < g <= 0         */
   GMCP_E_DEGENERATE = 4,  /* zero-area slave triangle at the current positions */
   GMCP_E_NONFINITE = 5,   /* NaN / Inf input position                          */
-  GMCP_E_HIP = 6          /* a HIP runtime call failed                         */
+  GMCP_E_HIP = 6,         /* a HIP runtime call failed                         */
+  GMCP_E_TIMEOUT = 7      /* a device-side wait passed its bound (internal
+                             error; the call's results are invalid)           */
 } gmcp_status_code;
 
 enum {
@@ -225,6 +227,9 @@ int gmcp_rule(int n, double *out);
  * triangle the narrow phase could accept or flag as penetrating.  Uses a
  * uniform grid per environment over the prism region.  x_slave [Vs][3],
  * x_master [Vm][3].  The lists stay in the workspace for gmcp_assemble.
+ * This culls the projection of master features onto slave triangles
+ * (Sec. 4.1) to those that can land inside the barrier's support
+ * (Sec. 4.2, 0 < g < eps); the paper fixes no acceleration structure.
  */
 int gmcp_broadphase(gmcp_ctx *ctx, const void *x_slave, const void *x_master);
 

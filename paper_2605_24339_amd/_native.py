@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmcp.so")
 
 GMCP_OK, GMCP_E_ARG, GMCP_E_CAPACITY, GMCP_E_PENETRATION = 0, 1, 2, 3
-GMCP_E_DEGENERATE, GMCP_E_NONFINITE, GMCP_E_HIP = 4, 5, 6
+GMCP_E_DEGENERATE, GMCP_E_NONFINITE, GMCP_E_HIP, GMCP_E_TIMEOUT = 4, 5, 6, 7
 GMCP_F64, GMCP_KINEMATIC_MASTER, GMCP_MORTAR, GMCP_FEATURES = 1, 2, 4, 8
 
 P = C.c_void_p

@@ -1182,17 +1182,17 @@ __global__ __launch_bounds__(kThreads) void k_mtri(const Pair<R> *__restrict__ p
 // and the hash tables inside it grow in powers of two up to that size.
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__restrict__ rlist,
+__global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int4 *__restrict__ rlist,
                                                        int32_t *__restrict__ rcount, int zero_cnt) {
   const int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  int n_ent = 0;
+  int n_ent = 0, sb = 0, se = 0;
   if (row < a.V) {
     if ((int64_t)a.st_r->n_pairs <= a.cap_pairs) {
       const bool slave = row < a.Vs;
       const int64_t vid = slave ? row : row - a.Vs;
-      const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
-      const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
+      sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
+      se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
       for (int src = sb; src < se; ++src) {
         const int t = (slave ? a.s_vt[src] : a.m_vt[src]) >> 2;
         const int np = slave ? a.tri_npair[t] : a.mp_off[t + 1] - a.mp_off[t];
@@ -1229,8 +1229,9 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
   }
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1;
-  if (n_ent > 0 && n_ent <= lb) rlist[bl + wl[w] + __popcll(ml & below)] = (int32_t)row;
-  if (n_ent > lb) rlist[a.V + bh + wh[w] + __popcll(mh & below)] = (int32_t)row;
+  const int4 rec = make_int4((int)row, sb, se, n_ent);
+  if (n_ent > 0 && n_ent <= lb) rlist[bl + wl[w] + __popcll(ml & below)] = rec;
+  if (n_ent > lb) rlist[a.V + bh + wh[w] + __popcll(mh & below)] = rec;
 }
 
 // One wave per listed BSR row (k_row_pre), a fixed grid walking the list.
@@ -1256,16 +1257,19 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int32_t *__r
 // symmetric coef n n^T), so PASS 3 copies them after PASS 1 has written the
 // slave rows.  Columns are ranked and written ascending.
 constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows: their bound)
-constexpr int kRowSrc = kWave;   // incident triangles of a slave row kept in LDS
+// incident triangles of a row taken per chunk (kept in LDS): a vertex has
+// far fewer than 32 in the common case, and the smaller table lets more
+// waves share a CU (LDS bounds the row kernels' occupancy)
+constexpr int kRowSrc = 32;
 
-// LDS bytes of one wave of k_rows: hash set and dense list (slots each),
+// LDS bytes of one wave of k_rows: hash set (slots, compacted in place),
 // the incident-triangle table, and in PASS 1 the contribution stash - in
 // groups of three (a triangle's own vertices, or one pair's master
 // vertices: three distinct columns, the table index, three coefficients) -
 // and the incident triangles' normals; a multiple of 16 bytes
 template <typename R>
 constexpr size_t row_lds_wave(int slots, int pass, bool heavy, int light_bound) {
-  return ((size_t)slots * 8 + (size_t)8 * kRowSrc * 4 +
+  return ((size_t)slots * 4 + (size_t)8 * kRowSrc * 4 +
           (pass == 1 ? (size_t)((heavy ? kRowEnt : light_bound) / 3 + 1) * (16 + 3 * sizeof(R)) +
                            (size_t)kRowSrc * 3 * sizeof(R)
                      : 0) +
@@ -1273,7 +1277,7 @@ constexpr size_t row_lds_wave(int slots, int pass, bool heavy, int light_bound) 
 }
 
 template <typename R, int PASS, bool HEAVY>  // HEAVY: the heavy-row list (large LDS tables), same code
-__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots, const int32_t *__restrict__ rlist,
+__global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slots, const int4 *__restrict__ rlist,
                                                            const int32_t *__restrict__ rcount) {
   constexpr int pass = PASS;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1281,8 +1285,8 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   const int ecap = HEAVY ? kRowEnt : a.light_bound;
   const size_t per_wave = row_lds_wave<R>(slots, pass, HEAVY, a.light_bound);
   int32_t *key = reinterpret_cast<int32_t *>(smem + (size_t)w * per_wave);
-  int32_t *dense = key + slots;
-  int32_t *sip = dense + slots;  // incident-triangle table: item prefix, contribution
+  int32_t *dense = key;          // the set compacted in place
+  int32_t *sip = key + slots;    // incident-triangle table: item prefix, contribution
   int32_t *seo = sip + kRowSrc;  // offset, triangle, corner, first pair
   int32_t *stt = seo + kRowSrc;
   int32_t *sco = stt + kRowSrc;
@@ -1300,9 +1304,12 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   // several times slower (the rows with work cluster in the list, so the
   // XCDs holding them finish last)
   const int lblk = blockIdx.x;
+  // each list entry carries the row's adjacency range and contribution
+  // count (k_row_pre), so a row starts with one load
   for (int64_t li = (int64_t)lblk * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
-    [&](const int64_t row) {
+    [&](const int4 rr) {
   wave_sync();  // the previous row's LDS reads are done
+  const int64_t row = rr.x;
   const bool slave = row < a.Vs;
 
   if (pass == 3) {
@@ -1327,9 +1334,8 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     return;
   }
 
-  const int64_t vid = slave ? row : row - a.Vs;
-  const int sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
-  const int se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
+  const int sb = rr.y, se = rr.z;
+  const int n_ent = rr.w;
 
   if (!slave) {
     // ------------------------------------------------------ master row
@@ -1348,13 +1354,6 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
         for (int d = 0; d < 3; ++d) a.grad[3 * row + d] = gr[d];
     }
     if (pass == 2) return;
-    int n_ent = 0;
-    for (int src = sb + lane; src < se; src += kWave) {
-      const int t = a.m_vt[src] >> 2;
-      const int np = a.mp_off[t + 1] - a.mp_off[t];
-      n_ent += np ? 3 + 3 * np : 0;
-    }
-    for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
     if (n_ent == 0) {
       if (pass == 0 && lane == 0) a.row_cnt[row] = 0;
       return;
@@ -1370,7 +1369,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     for (int s0 = sb; s0 < se; s0 += kRowSrc) {
       const int src = s0 + lane;
       int t = 0, corner = 0, np = 0, pb = 0, tv[3] = {0, 0, 0};
-      if (src < se) {
+      if (lane < kRowSrc && src < se) {
         const int ent = a.m_vt[src];
         t = ent >> 2;
         corner = ent & 3;
@@ -1387,11 +1386,13 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       }
       const int items = __shfl(iin, kWave - 1, kWave);
       wave_sync();  // the previous chunk's table reads are done
-      sip[lane] = iin - nit;
-      stt[lane] = np > 0 ? t : -1;  // -1: no pairs (no contribution)
-      sco[lane] = corner;
-      spb[lane] = pb;
-      for (int m = 0; m < 3; ++m) stv[3 * lane + m] = tv[m];
+      if (lane < kRowSrc) {
+        sip[lane] = iin - nit;
+        stt[lane] = np > 0 ? t : -1;  // -1: no pairs (no contribution)
+        sco[lane] = corner;
+        spb[lane] = pb;
+        for (int m = 0; m < 3; ++m) stv[3 * lane + m] = tv[m];
+      }
       wave_sync();
       for (int f = lane; f < items; f += kWave) {
         int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
@@ -1422,9 +1423,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     int nuniq = 0;
     for (int i0 = 0; i0 < tsz; i0 += kWave) {
       const int i = i0 + lane;
-      const bool used = i < tsz && key[i] >= 0;
+      const int32_t kv = i < tsz ? key[i] : -1;  // read before any lane writes (in place)
+      const bool used = kv >= 0;
       const uint64_t m = __ballot(used);
-      if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = key[i];
+      if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = kv;
       nuniq += __popcll(m);
     }
     if (pass == 0) {
@@ -1471,11 +1473,6 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
 
   // -------------------------------------------------------- slave row
   // contributions of one source (incident triangle), in canonical order
-  auto src_count = [&](int src) -> int {
-    const int t = a.s_vt[src] >> 2;
-    const int np = a.tri_npair[t];
-    return np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
-  };
   auto visit_src = [&](int src, auto &&visit) {
     const int ent = a.s_vt[src];
     const int t = ent >> 2, corner = ent & 3;
@@ -1491,9 +1488,6 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     }
   };
 
-  int n_ent = 0;
-  for (int src = sb + lane; src < se; src += kWave) n_ent += src_count(src);
-  for (int o = 32; o > 0; o >>= 1) n_ent += __shfl_xor(n_ent, o, kWave);
   if (pass != 0 && a.grad) {
     // gradient row: sum over incident triangles of -gs[T][a] n_T (lane
     // partials, fixed-order butterfly)
@@ -1534,7 +1528,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   for (int s0 = sb; s0 < se; s0 += kRowSrc) {
     const int src = s0 + lane;
     int t = 0, corner = 0, np = 0, pb = 0;
-    if (src < se) {
+    if (lane < kRowSrc && src < se) {
       const int ent = a.s_vt[src];
       t = ent >> 2;
       corner = ent & 3;
@@ -1553,13 +1547,15 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     }
     const int items = __shfl(iin, kWave - 1, kWave), ents = __shfl(ein, kWave - 1, kWave);
     wave_sync();  // the previous chunk's table reads are done
-    sip[lane] = iin - nit;
-    seo[lane] = run + ein - nen;
-    stt[lane] = t;
-    sco[lane] = corner;
-    spb[lane] = pb;
-    if (stash && np > 0)
-      for (int d = 0; d < 3; ++d) snrm[3 * lane + d] = a.tri_nrm[3 * (int64_t)t + d];
+    if (lane < kRowSrc) {
+      sip[lane] = iin - nit;
+      seo[lane] = run + ein - nen;
+      stt[lane] = t;
+      sco[lane] = corner;
+      spb[lane] = pb;
+      if (stash && np > 0)
+        for (int d = 0; d < 3; ++d) snrm[3 * lane + d] = a.tri_nrm[3 * (int64_t)t + d];
+    }
     wave_sync();
     for (int f = lane; f < items; f += kWave) {
       int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
@@ -1602,9 +1598,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   int nuniq = 0;
   for (int i0 = 0; i0 < tsz; i0 += kWave) {
     const int i = i0 + lane;
-    const bool used = i < tsz && key[i] >= 0;
+    const int32_t kv = i < tsz ? key[i] : -1;  // read before any lane writes (in place)
+    const bool used = kv >= 0;
     const uint64_t m = __ballot(used);
-    if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = key[i];
+    if (used) dense[nuniq + __popcll(m & ((1ull << lane) - 1))] = kv;
     nuniq += __popcll(m);
   }
   if (pass == 0) {
@@ -1990,7 +1987,7 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   const int64_t rmax = light_row_blocks(c);
   const dim3 rgrid((unsigned)(rneed < rmax ? (rneed > 0 ? rneed : 1) : rmax));
   const dim3 hgrid((unsigned)heavy_row_blocks(c));
-  const int32_t *light = b.rlist, *heavy = b.rlist + c->V;
+  const int4 *light = b.rlist, *heavy = b.rlist + c->V;
   const int32_t *nlight = b.rcount, *nheavy = b.rcount + 1;
   if (grad && !H) {  // gradient alone: the row kernel's gradient-only pass
     prof_mark(c, ST_GRAD, 0);

@@ -337,8 +337,9 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
                                                          const GridEnv *__restrict__ grid, int64_t Ts,
                                                          const int32_t *__restrict__ cell_start, int64_t cap_items,
                                                          int64_t total_cells, int32_t *__restrict__ cand_cnt,
-                                                         int32_t *__restrict__ qlist, int32_t *__restrict__ qcount,
-                                                         uint32_t *__restrict__ box, int n_env, DevStatus *st) {
+                                                         int32_t *__restrict__ qlist, float4 *__restrict__ qrec,
+                                                         int32_t *__restrict__ qcount, uint32_t *__restrict__ box,
+                                                         int n_env, DevStatus *st) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   if (i < n_env)  // the slave boxes were read by the grid kernels: empty them for the next call
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
     }
   bool active = false;
   int64_t t = -1;
+  float4 fr[3];  // the listed triangle's frame for the query kernel
   if (i < Ts) {
     t = s_order[i];
     R e1[3], e2[3], s0[3];
@@ -370,6 +372,9 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
       const float eps = (float)env[e].dhat;
       float tlo[3], thi[3], n[3];
       if (g.valid && tri_frame(xs, ts, t, tlo, thi, n)) {
+        fr[0] = make_float4(tlo[0], tlo[1], tlo[2], __int_as_float((int)t));
+        fr[1] = make_float4(thi[0], thi[1], thi[2], __int_as_float(e));
+        fr[2] = make_float4(n[0], n[1], n[2], 0.0f);
         float lo[3], hi[3];
         const float ew = eps * (1.0f + 1e-5f);
         slab_box(tlo, thi, n, -ew, ew, 4.0f * eps * 1e-6f, lo, hi);
@@ -424,7 +429,11 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
     qb = sum ? atomicAdd(qcount, sum) : 0;
   }
   __syncthreads();
-  if (active) qlist[qb + wq[w] + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
+  if (active) {
+    const int slot = qb + wq[w] + __popcll(m & ((1ull << lane) - 1));
+    qlist[slot] = (int32_t)t;
+    for (int k = 0; k < 3; ++k) qrec[3 * (int64_t)slot + k] = fr[k];
+  }
 }
 
 // One wave per slave triangle.  The support prism (|t| <= eps_max along n_T)
@@ -450,6 +459,7 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
                                                      int64_t cap_cand,
                                                      int64_t cap_items, int64_t total_cells,
                                                      const int32_t *__restrict__ qlist,
+                                                     const float4 *__restrict__ qrec,
                                                      const int32_t *__restrict__ qcount,
                                                      int32_t *__restrict__ cand_blk, DevStatus *st) {
   __shared__ int32_t set[kQueryWaves][kQuerySet];
@@ -474,15 +484,20 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
   const int64_t share = cap_cand / gridDim.x;
   if (threadIdx.x == 0) blk_req = 0;
   __syncthreads();
-  // the waves walk the query list (triangles whose prism meets occupied cells)
-  for (int64_t li = (int64_t)lblk * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves)
-    [&](const int64_t t) {
+  // the waves walk the query list (triangles whose prism meets occupied
+  // cells) with the frames the prepass stored: one load instead of the
+  // chain triangle -> vertex ids -> positions (loading the next entry's
+  // frame ahead measured slower: the registers it holds cause spills)
+  for (int64_t li = (int64_t)lblk * kQueryWaves + w; li < nlist; li += (int64_t)gridDim.x * kQueryWaves) {
+    const float4 f0 = qrec[3 * li], f1 = qrec[3 * li + 1], f2 = qrec[3 * li + 2];
+    [&] {
   wave_sync();  // the previous triangle's LDS reads are done
-  const int e = s_env[t];
+  const int64_t t = __float_as_int(f0.w);
+  const int e = __float_as_int(f1.w);
   const GridEnv g = grid[e];
   const float eps = (float)env[e].dhat;
-  float tlo[3], thi[3], n[3];
-  const bool ok = g.valid && tri_frame(xs, ts, t, tlo, thi, n);
+  const float tlo[3] = {f0.x, f0.y, f0.z}, thi[3] = {f1.x, f1.y, f1.z}, n[3] = {f2.x, f2.y, f2.z};
+  const bool ok = g.valid;
   const int S = ok ? max(1, min(kMaxSlabs, (int)ceilf(2.0f * eps / g.h))) : 0;
   const float dt = 2.0f * eps / (float)max(S, 1);
   const float margin = eps * 1e-6f;
@@ -606,7 +621,8 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
     l[r] = v;
   }
   wave_sync();  // the set is reused by the wave's next triangle
-    }(qlist[li]);
+    }();
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     cand_blk[blockIdx.x] = blk_req;  // summed by gmcp_status
@@ -623,20 +639,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const GridEnv *__restrict__ grid, int64_t Ts,
     const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items, const float4 *__restrict__ mbox,
     int32_t *__restrict__ cand_cnt, int32_t *__restrict__ tmp_off, int32_t *__restrict__ cand_tmp, int64_t cap_cand,
-    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount,
-    int32_t *__restrict__ cand_blk, DevStatus *st) {
+    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const float4 *__restrict__ qrec,
+    const int32_t *__restrict__ qcount, int32_t *__restrict__ cand_blk, DevStatus *st) {
   query_body<float>(xs, ts, s_order, s_env, env, grid, Ts, cell_start, items, mbox, cand_cnt, tmp_off, cand_tmp,
-                    cap_cand, cap_items, total_cells, qlist, qcount, cand_blk, st);
+                    cap_cand, cap_items, total_cells, qlist, qrec, qcount, cand_blk, st);
 }
 __global__ __launch_bounds__(kThreads) void k_query_f64(
     const double *__restrict__ xs, const int32_t *__restrict__ ts, const int32_t *__restrict__ s_order,
     const int32_t *__restrict__ s_env, const EnvInfo *__restrict__ env, const GridEnv *__restrict__ grid, int64_t Ts,
     const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items, const float4 *__restrict__ mbox,
     int32_t *__restrict__ cand_cnt, int32_t *__restrict__ tmp_off, int32_t *__restrict__ cand_tmp, int64_t cap_cand,
-    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount,
-    int32_t *__restrict__ cand_blk, DevStatus *st) {
+    int64_t cap_items, int64_t total_cells, const int32_t *__restrict__ qlist, const float4 *__restrict__ qrec,
+    const int32_t *__restrict__ qcount, int32_t *__restrict__ cand_blk, DevStatus *st) {
   query_body<double>(xs, ts, s_order, s_env, env, grid, Ts, cell_start, items, mbox, cand_cnt, tmp_off, cand_tmp,
-                    cap_cand, cap_items, total_cells, qlist, qcount, cand_blk, st);
+                    cap_cand, cap_items, total_cells, qlist, qrec, qcount, cand_blk, st);
 }
 
 // Each listed triangle's sorted list, from its scratch offset to its CSR
@@ -713,7 +729,7 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (c->Ts)
     hipLaunchKernelGGL(k_query_pre<R>, dim3(nblk(std::max<int64_t>(c->Ts, c->n_env))), dim3(kThreads), 0, s, xs, c->ts,
                        b.s_order, b.s_env, b.env, b.grid, c->Ts, b.cell_start, c->caps.grid_items, c->total_cells,
-                       b.cand_cnt, b.qlist, b.qcount, b.box, c->n_env, b.status);
+                       b.cand_cnt, b.qlist, b.qrec, b.qcount, b.box, c->n_env, b.status);
   prof_mark(c, ST_QUERY_PRE, 1);
   // the wave kernels walk the query list with a fixed grid, all of it
   // resident at once
@@ -730,11 +746,11 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
     if constexpr (sizeof(R) == 4)
       hipLaunchKernelGGL(k_query_f32, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.cand_blk, b.status);
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qrec, b.qcount, b.cand_blk, b.status);
     else
       hipLaunchKernelGGL(k_query_f64, qgrid, dim3(kThreads), 0, s, xs, c->ts, b.s_order, b.s_env, b.env, b.grid, c->Ts,
                        b.cell_start, b.items, b.mbox, b.cand_cnt, b.cand_tmp_off, b.cand_tmp, c->caps.candidates,
-                       c->caps.grid_items, c->total_cells, b.qlist, b.qcount, b.cand_blk, b.status);
+                       c->caps.grid_items, c->total_cells, b.qlist, b.qrec, b.qcount, b.cand_blk, b.status);
   }
   prof_mark(c, ST_QUERY_COUNT, 1);
   // the narrow phase reads every list where the query wrote it (count and

@@ -92,6 +92,7 @@ struct Buffers {
   int32_t *cand_tmp, *cand_tmp_off;             // one-pass query: scratch lists and their offsets
   int32_t *cand_blk;                            // [kQueryBlocks] candidates found by each query block
   int32_t *qlist, *qcount;                      // [Ts], [1]: slave triangles whose prism meets occupied cells
+  float4 *qrec;                                 // [Ts][3]: their frames (box lo | T, box hi | env, normal)
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
   void *tri_nrm;                                // [Ts][3] R
@@ -104,7 +105,9 @@ struct Buffers {
   void *mtri;                                   // [Tm][45] R: per master triangle, sum over its
                                                 // pairs of mm n n^T (6 vertex pairs x 6) and gm n (3 x 3)
   int32_t *row_cnt;                             // [V+1]
-  int32_t *rlist, *rcount;                      // [2V]: BSR rows with contributions (light | heavy); [2] counts
+  int4 *rlist;                                  // [2V]: BSR rows with contributions (light | heavy):
+                                                //   row, adjacency range [first, end), contributions
+  int32_t *rcount;                              // [2]: list lengths
   // step bound
   GridEnv *sgrid;
   uint32_t *sbox;

@@ -202,6 +202,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.cand_blk = p.take<int32_t>(kQueryBlocks);
   t.qlist = p.take<int32_t>(s.Ts);
   t.qcount = p.take<int32_t>(1);
+  t.qrec = p.take<float4>(3 * s.Ts);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
   t.tri_nrm = p.take<char>(rsz * 3 * s.Ts);
   t.tri_sum = p.take<char>(rsz * 9 * s.Ts);
@@ -217,7 +218,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.mp_key = p.take<long long>(cp.pairs);
   t.mtri = p.take<char>(s.kin ? 0 : rsz * 45 * s.Tm);
   t.row_cnt = p.take<int32_t>(s.V + 1);
-  t.rlist = p.take<int32_t>(2 * s.V);
+  t.rlist = p.take<int4>(2 * s.V);
   t.rcount = p.take<int32_t>(2);
   t.sgrid = p.take<GridEnv>(s.n_env);
   t.sbox = p.take<uint32_t>(6 * s.n_env);
@@ -471,7 +472,10 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   // zeroed counters the broad phase and bucketing rely on
   if (fill_i32(c, c->b.cell_cnt, 0, caps->grid_cells + 1) != hipSuccess ||
       fill_i32(c, c->b.scell_cnt, 0, caps->grid_cells + 1) != hipSuccess ||
-      fill_i32(c, c->b.mp_cnt, 0, s.Tm + 1) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+      fill_i32(c, c->b.mp_cnt, 0, s.Tm + 1) != hipSuccess ||
+      fill_i32(c, c->b.scan_tmp, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
+      fill_i32(c, c->b.scan_tmp2, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return GMCP_E_HIP;
   }
@@ -788,15 +792,16 @@ int gmcp_row_classes(gmcp_ctx *c, int64_t *out, const int32_t *row_ptr) {
   if (hipMemcpyAsync(h, c->b.rcount, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return GMCP_E_HIP;
-  std::vector<int32_t> rl((size_t)h[0] + h[1]), rp(c->V + 1);
-  if ((h[0] && hipMemcpy(rl.data(), c->b.rlist, sizeof(int32_t) * h[0], hipMemcpyDeviceToHost) != hipSuccess) ||
-      (h[1] && hipMemcpy(rl.data() + h[0], c->b.rlist + c->V, sizeof(int32_t) * h[1], hipMemcpyDeviceToHost) !=
+  std::vector<int4> rl((size_t)h[0] + h[1]);
+  std::vector<int32_t> rp(c->V + 1);
+  if ((h[0] && hipMemcpy(rl.data(), c->b.rlist, sizeof(int4) * h[0], hipMemcpyDeviceToHost) != hipSuccess) ||
+      (h[1] && hipMemcpy(rl.data() + h[0], c->b.rlist + c->V, sizeof(int4) * h[1], hipMemcpyDeviceToHost) !=
                    hipSuccess) ||
       hipMemcpy(rp.data(), row_ptr, sizeof(int32_t) * (c->V + 1), hipMemcpyDeviceToHost) != hipSuccess)
     return GMCP_E_HIP;
   int64_t nb[2] = {0, 0};
   for (int64_t i = 0; i < (int64_t)rl.size(); ++i) {
-    const int32_t r = rl[i];
+    const int32_t r = rl[i].x;
     if (r < 0 || r >= c->V) return GMCP_E_HIP;
     nb[i < h[0] ? 0 : 1] += rp[r + 1] - rp[r];
   }

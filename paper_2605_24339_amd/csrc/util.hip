@@ -5,9 +5,18 @@ namespace gmcp {
 
 namespace {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanPer = 4;
-constexpr int kScanBlock = kScanThreads * kScanPer;  // 1024 elements per block
+// When all tiles run at once, inclusive prefixes cross the array at one
+// look-back window per memory round trip: a window of 1024 descriptors (the
+// whole block reads) and 16 K elements per tile keep that rate far above the
+// array's read and write time.  (A 64-descriptor window over 4 K-element
+// tiles scanned the 64.6 M cells of a 256-environment grid at 2 TB/s.)
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 16;                         // consecutive elements per thread
+constexpr int kScanTile = kScanThreads * kScanPer;  // 16384 elements per tile
+// bound on the polls of one look-back window: a predecessor tile publishes
+// its sum right after its own loads, so a wait this long means the state
+// was corrupted; the kernel then reports an error instead of waiting on
+constexpr int kScanSpin = 1 << 20;
 
 __device__ inline int wave_incl_scan(int v, int lane) {
 #pragma unroll
@@ -18,66 +27,139 @@ __device__ inline int wave_incl_scan(int v, int lane) {
   return v;
 }
 
-// Exclusive scan of one 1024-element block; block totals to sums[blockIdx].
-__global__ __launch_bounds__(kScanThreads) void k_scan_block(const int32_t *__restrict__ in,
-                                                              int32_t *__restrict__ out,
-                                                              int32_t *__restrict__ sums, int64_t n) {
-  __shared__ int wsum[kScanThreads / kWave];
-  int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * kScanPer;
-  int v[kScanPer];
-  int run = 0;
-#pragma unroll
-  for (int i = 0; i < kScanPer; ++i) {
-    int64_t j = base + i;
-    v[i] = j < n ? in[j] : 0;
-    run += v[i];
-  }
-  int incl = wave_incl_scan(run, lane);
-  if (lane == kWave - 1) wsum[w] = incl;
-  __syncthreads();
-  int woff = 0;
-  for (int i = 0; i < w; ++i) woff += wsum[i];
-  int ex = woff + incl - run;
-#pragma unroll
-  for (int i = 0; i < kScanPer; ++i) {
-    int64_t j = base + i;
-    if (j < n) out[j] = ex;
-    ex += v[i];
-  }
-  if (tid == kScanThreads - 1 && sums) sums[blockIdx.x] = ex;
+// Tile descriptors of the single-pass scan: epoch (30 bits, the call) |
+// state (2 bits: 1 = the tile's own sum, 2 = its inclusive prefix) | value.
+// A descriptor of another epoch reads as "not yet published".
+__device__ inline unsigned long long scan_desc(uint32_t epoch, uint32_t state, int32_t v) {
+  return ((unsigned long long)(epoch & 0x3fffffffu) << 34) | ((unsigned long long)state << 32) | (uint32_t)v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *__restrict__ out,
-                                                            const int32_t *__restrict__ offs, int64_t n) {
-  int64_t j = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-  int add = offs[blockIdx.x];
-#pragma unroll
-  for (int i = 0; i < kScanPer; ++i, j += kScanThreads)
-    if (j < n) out[j] += add;
-}
-
-// Second launch of the two-launch scan (up to kScanTop blocks): block b
-// adds the sum of the block totals before it (its threads split them, wave
-// butterflies, the wave sums in LDS) to its 1024 elements.
-constexpr int64_t kScanTop = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_add_top(int32_t *__restrict__ out,
-                                                                const int32_t *__restrict__ sums, int64_t n) {
-  __shared__ int wsum[kScanThreads / kWave];
+// Exclusive scan in one launch (decoupled look-back, Merrill and Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
+// Tiles are numbered in the order blocks start (a ticket counter), so every
+// tile a block waits on belongs to a block already running.  The ticket word
+// holds the epoch (high 32 bits) and the tickets taken (low 32); the block
+// that takes the last ticket moves it to the next epoch with no tickets, so
+// the state is ready for the next call without a clearing pass, and the
+// descriptors of earlier calls no longer match.
+__global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const int32_t *__restrict__ in,
+                                                                int32_t *__restrict__ out, int64_t n,
+                                                                int64_t ntiles, unsigned long long *ticket,
+                                                                unsigned long long *desc, DevStatus *st) {
+  __shared__ uint32_t s_tile, s_epoch;
+  __shared__ int wsum[kScanPer / 4][kScanThreads / kWave];
+  __shared__ int lb_first[kScanThreads / kWave], lb_wait[kScanThreads / kWave], lb_sum[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const int b = blockIdx.x;
-  int s = 0;
-  for (int i = tid; i < b; i += kScanThreads) s += sums[i];
-  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-  if (lane == 0) wsum[w] = s;
+  if (tid == 0) {
+    const unsigned long long tk = atomicAdd(ticket, 1ull);
+    const uint32_t t = (uint32_t)(tk & 0xffffffffull);
+    if ((int64_t)t == ntiles - 1) atomicAdd(ticket, (1ull << 32) - (unsigned long long)ntiles);
+    s_tile = t;
+    s_epoch = (uint32_t)(tk >> 32) & 0x3fffffffu;
+  }
   __syncthreads();
-  int add = 0;
-  for (int i = 0; i < kScanThreads / kWave; ++i) add += wsum[i];
-  int64_t j = (int64_t)b * kScanBlock + tid;
+  const int64_t tile = (int64_t)s_tile;  // 0 .. 2^32 - 1
+  if (tile >= ntiles) {  // only if the ticket word was corrupted: no descriptor to write
+    if (tid == 0) set_error(st, GMCP_E_TIMEOUT, (unsigned long long)tile);
+    return;
+  }
+  const uint32_t epoch = s_epoch;
+  // coalesced loads: group k of the tile is elements [k * 4 * kScanThreads,
+  // (k + 1) * 4 * kScanThreads), four consecutive ones per thread
+  constexpr int kGroups = kScanPer / 4;
+  int4 q[kGroups];
+  int gs[kGroups], gi[kGroups];
 #pragma unroll
-  for (int i = 0; i < kScanPer; ++i, j += kScanThreads)
-    if (j < n) out[j] += add;
+  for (int k = 0; k < kGroups; ++k) {
+    const int64_t e0 = tile * kScanTile + ((int64_t)k * kScanThreads + tid) * 4;
+    if (e0 + 4 <= n) {
+      q[k] = reinterpret_cast<const int4 *>(in)[e0 >> 2];
+    } else {
+      q[k].x = e0 < n ? in[e0] : 0;
+      q[k].y = e0 + 1 < n ? in[e0 + 1] : 0;
+      q[k].z = e0 + 2 < n ? in[e0 + 2] : 0;
+      q[k].w = 0;
+    }
+    gs[k] = q[k].x + q[k].y + q[k].z + q[k].w;
+    gi[k] = wave_incl_scan(gs[k], lane);
+    if (lane == kWave - 1) wsum[k][w] = gi[k];
+  }
+  __syncthreads();
+  // offset of (group k, wave w) in the tile, and the tile's sum
+  int goff[kGroups], agg = 0;
+#pragma unroll
+  for (int k = 0; k < kGroups; ++k) {
+    goff[k] = agg;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+      if (i < w) goff[k] += wsum[k][i];
+      agg += wsum[k][i];
+    }
+  }
+  if (tid == 0)
+    __hip_atomic_store(&desc[tile], scan_desc(epoch, tile == 0 ? 2u : 1u, agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  // look back over windows of kScanThreads predecessors (thread k reads
+  // tile i - k) until one holds its inclusive prefix; tiles before 0 read as
+  // prefix 0.  The whole block takes each decision from the waves' summaries
+  // in LDS, so the loop is uniform.
+  int prefix = 0;
+  if (tile > 0) {
+    int spins = 0;
+    for (int64_t i = tile - 1;;) {
+      const int64_t j = i - tid;
+      const unsigned long long d =
+          j >= 0 ? __hip_atomic_load(&desc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : scan_desc(epoch, 2u, 0);
+      const uint32_t state = (uint32_t)(d >> 34) == epoch ? (uint32_t)(d >> 32) & 3u : 0u;
+      const uint64_t pm = __ballot(state == 2u), zm = __ballot(state == 0u);
+      const int first = pm ? __ffsll((unsigned long long)pm) - 1 : kWave;  // the wave's nearest prefix
+      const uint64_t need = first >= kWave - 1 ? ~0ull : (2ull << first) - 1;
+      int c = lane <= first ? (int)(uint32_t)d : 0;
+      for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+      if (lane == 0) {
+        lb_first[w] = first;
+        lb_wait[w] = (zm & need) != 0;
+        lb_sum[w] = c;
+      }
+      __syncthreads();
+      bool wait = false, found = false;
+      int add = 0;
+      for (int k = 0; k < kScanThreads / kWave && !found; ++k) {
+        wait = wait || lb_wait[k];
+        add += lb_sum[k];
+        found = lb_first[k] < kWave;
+      }
+      __syncthreads();  // the summaries are read before the next window's writes
+      if (wait) {
+        if (++spins > kScanSpin) {
+          if (tid == 0) set_error(st, GMCP_E_TIMEOUT, (unsigned long long)tile);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      prefix += add;
+      if (found) break;
+      i -= kScanThreads;
+    }
+    if (tid == 0)
+      __hip_atomic_store(&desc[tile], scan_desc(epoch, 2u, prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int k = 0; k < kGroups; ++k) {
+    const int64_t e0 = tile * kScanTile + ((int64_t)k * kScanThreads + tid) * 4;
+    int4 o;
+    o.x = prefix + goff[k] + gi[k] - gs[k];
+    o.y = o.x + q[k].x;
+    o.z = o.y + q[k].y;
+    o.w = o.z + q[k].z;
+    if (e0 + 4 <= n) {
+      reinterpret_cast<int4 *>(out)[e0 >> 2] = o;
+    } else {
+      if (e0 < n) out[e0] = o.x;
+      if (e0 + 1 < n) out[e0 + 1] = o.y;
+      if (e0 + 2 < n) out[e0 + 2] = o.z;
+    }
+  }
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -114,56 +196,17 @@ __global__ void k_stage_init(DevStatus *st, StageInit a, int n_env) {
 }  // namespace
 
 hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side) {
+  // one state per stream that scans (the side stream scans the swept grid):
+  // the ticket word, then one descriptor per tile
   int32_t *const scratch = side ? c->b.scan_tmp2 : c->b.scan_tmp;
-  // levels: out <- scan(in); block sums in tmp, scanned recursively in place
-  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  if (nb <= 0) return hipSuccess;
-  if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kScanThreads), 0, c->stream, in, out, nullptr, n);
-    return hipGetLastError();
-  }
-  if (nb <= kScanTop) {  // two launches: block scans + totals, then each block's offset
-    if (nb > (int64_t)c->scan_tmp_elems) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, in, out, scratch, n);
-    hipLaunchKernelGGL(k_scan_add_top, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream, out,
-                       (const int32_t *)scratch, n);
-    return hipGetLastError();
-  }
-  // the scratch holds every level's block sums back to back
-  int32_t *lvl_in[8], *lvl_out[8];
-  int64_t lvl_n[8];
-  int depth = 0;
-  int32_t *tmp = scratch;
-  int64_t used = 0;
-  int64_t cur = n;
-  const int32_t *src = in;
-  int32_t *dst = out;
-  for (;;) {
-    int64_t blocks = (cur + kScanBlock - 1) / kScanBlock;
-    int32_t *sums = blocks > 1 ? tmp + used : nullptr;
-    if (blocks > 1) {
-      if (used + 2 * blocks > (int64_t)c->scan_tmp_elems || depth >= 8) return hipErrorInvalidValue;
-    }
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)blocks), dim3(kScanThreads), 0, c->stream, src, dst,
-                       sums, cur);
-    lvl_in[depth] = dst;
-    lvl_out[depth] = sums;
-    lvl_n[depth] = cur;
-    ++depth;
-    if (blocks == 1) break;
-    int32_t *sums_scanned = tmp + used + blocks;
-    used += 2 * blocks;
-    src = sums;
-    dst = sums_scanned;
-    cur = blocks;
-  }
-  // propagate block offsets down: level d's sums were scanned into level d+1's dst
-  for (int d = depth - 2; d >= 0; --d) {
-    int64_t blocks = (lvl_n[d] + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)blocks), dim3(kScanThreads), 0, c->stream, lvl_in[d],
-                       lvl_in[d + 1], lvl_n[d]);
-  }
-  (void)lvl_out;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles <= 0) return hipSuccess;
+  if (2 * (ntiles + 1) > (int64_t)c->scan_tmp_elems || ntiles >= (int64_t(1) << 31) ||
+      ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15))
+    return hipErrorInvalidValue;
+  unsigned long long *ticket = reinterpret_cast<unsigned long long *>(scratch);
+  hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, out, n, ntiles,
+                     ticket, ticket + 1, c->b.status);
   return hipGetLastError();
 }
 
