@@ -220,20 +220,136 @@ __device__ inline int cell_coord(const GridEnv &g, float x, int d) {
   return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-// One wave per work tile, lane = (slave triangle j, rule point q) as in the
-// narrow phase.  The lanes of a triangle first gather, from the grid cells
-// its swept box covers, the master triangles whose swept boxes overlap it
-// (each once: the cell holding the lower corner of the overlap), into an
-// LDS slice; then every lane tests its own point's swept box against that
-// list, and the overlaps go through a per-wave queue that runs additive CCD
-// on 64 pairs at a time.  A triangle whose list overflows its slice walks
-// the cells point by point instead.
+// swept box of slave triangle T over dx (float, with a few ulps of slack):
+// it covers the swept box of every sample point of T
+__device__ inline void slack_box(float a, float b, float &lo, float &hi) {
+  const float mn = fminf(a, b), mx = fmaxf(a, b);
+  lo = mn - fabsf(mn) * 4e-7f - 1e-30f;
+  hi = mx + fabsf(mx) * 4e-7f + 1e-30f;
+}
+template <typename R>
+__device__ inline void swept_tri_box(const R *xs, const R *dxs, const int64_t v[3], float tlo[3], float thi[3]) {
+  for (int d = 0; d < 3; ++d) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int k = 0; k < 3; ++k) {
+      float l, h;
+      slack_box((float)xs[3 * v[k] + d], (float)(xs[3 * v[k] + d] + dxs[3 * v[k] + d]), l, h);
+      lo = fminf(lo, l);
+      hi = fmaxf(hi, h);
+    }
+    tlo[d] = lo;
+    thi[d] = hi;
+  }
+}
+
+__device__ inline bool box_in_grid(const GridEnv &g, const float lo[3], const float hi[3]) {
+  const float ext[3] = {g.nx * g.h, g.ny * g.h, g.nz * g.h};
+  for (int d = 0; d < 3; ++d)
+    if (hi[d] < g.lo[d] || lo[d] > g.lo[d] + ext[d]) return false;
+  return true;
+}
+
+// Thread per slave triangle (Morton order): lists the work tiles with a
+// triangle whose swept box meets an occupied cell of the swept grid.  Only
+// they can have swept pairs (every sample point's swept box lies inside its
+// triangle's), and they are usually few, so the CCD kernel walks this list
+// instead of every tile.  A tile is listed once: its first triangle to
+// claim the tile's flag appends it (the CCD kernel clears the flags of the
+// tiles it walks).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_ccd_pre(const R *__restrict__ xs, const R *__restrict__ dxs,
+                                                       const int32_t *__restrict__ ts,
+                                                       const int32_t *__restrict__ s_order,
+                                                       const int32_t *__restrict__ s_env,
+                                                       const EnvInfo *__restrict__ env,
+                                                       const GridEnv *__restrict__ grid, int64_t Ts,
+                                                       const int32_t *__restrict__ cell_start, int64_t cap_items,
+                                                       int64_t total_cells, int32_t *__restrict__ tflag,
+                                                       int32_t *__restrict__ list, int32_t *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  bool active = false;
+  int64_t t = -1;
+  int tile = -1;
+  if (i < Ts && cell_start[total_cells] <= cap_items) {
+    t = s_order[i];
+    const int e = s_env[t];
+    const GridEnv g = grid[e];
+    tile = env[e].tile0 + (int)((i - env[e].st0) / (kWave / env[e].nq));  // tiles cover the env's positions
+    if (g.valid) {
+      const int64_t v[3] = {ts[3 * t], ts[3 * t + 1], ts[3 * t + 2]};
+      float lo[3], hi[3];
+      swept_tri_box<R>(xs, dxs, v, lo, hi);
+      if (box_in_grid(g, lo, hi)) {
+        int c0[3], c1[3];
+        for (int d = 0; d < 3; ++d) {
+          c0[d] = cell_coord(g, lo[d], d);
+          c1[d] = cell_coord(g, hi[d], d);
+        }
+        const int64_t ncell = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+        if (ncell > 4096) {
+          active = true;  // too many cells to check here: the CCD kernel decides
+        } else {
+          const int64_t base = env[e].cell0;
+          // the (y, z) rows of the box, 8 at a time (their loads in flight
+          // together); a row's x-run of cells is contiguous
+          const int ny = c1[1] - c0[1] + 1, nrow = ny * (c1[2] - c0[2] + 1);
+          for (int r0 = 0; r0 < nrow && !active; r0 += 8) {
+            int32_t hi_s[8], lo_s[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int r = r0 + k;
+              hi_s[k] = lo_s[k] = 0;
+              if (r < nrow) {
+                const int64_t row = base + ((int64_t)(c0[2] + r / ny) * g.ny + c0[1] + r % ny) * g.nx;
+                hi_s[k] = cell_start[row + c1[0] + 1];
+                lo_s[k] = cell_start[row + c0[0]];
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) active = active || hi_s[k] > lo_s[k];
+          }
+        }
+      }
+    }
+  }
+  // the tile's first claim appends it: wave ballots, block prefix in LDS,
+  // one atomic per block
+  if (active) active = atomicExch(&tflag[tile], 1) == 0;
+  __shared__ int wq[kThreads / kWave], qb;
+  const int w = threadIdx.x / kWave;
+  const uint64_t m = __ballot(active);
+  if (lane == 0) wq[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) {
+      const int c0 = wq[k];
+      wq[k] = sum;
+      sum += c0;
+    }
+    qb = sum ? atomicAdd(count, sum) : 0;
+  }
+  __syncthreads();
+  if (active) list[qb + wq[w] + __popcll(m & ((1ull << lane) - 1))] = tile;
+}
+
+
+// One wave per listed work tile (k_ccd_pre), lane = (slave triangle j, rule
+// point q) as in the narrow phase.  The lanes of a triangle first gather,
+// from the grid cells its swept box covers, the master triangles whose
+// swept boxes overlap it (each once: the cell holding the lower corner of
+// the overlap), into an LDS slice; then every lane tests its own point's
+// swept box against that list, and the overlaps go through a per-wave queue
+// that runs additive CCD on 64 pairs at a time.  A triangle whose list
+// overflows its slice walks the cells point by point instead.
 constexpr int kAccdPool = 1024;  // LDS list entries per wave, split over the tile's triangles
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     const R *__restrict__ xs, const R *__restrict__ xm, const R *__restrict__ dxs, const R *__restrict__ dxm,
-    const int32_t *__restrict__ ts, const int32_t *__restrict__ tm, const Tile *__restrict__ tiles, int n_tiles,
+    const int32_t *__restrict__ ts, const int32_t *__restrict__ tm, const Tile *__restrict__ tiles,
+    const int32_t *__restrict__ list, const int32_t *__restrict__ count, int32_t *__restrict__ tflag,
     const int32_t *__restrict__ s_order, const EnvInfo *__restrict__ env, const double *__restrict__ rule,
     const GridEnv *__restrict__ grid, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ items,
     const float4 *__restrict__ smbox, int64_t cap_items, int64_t total_cells, uint32_t *bits, DevStatus *st) {
@@ -241,18 +357,22 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
   __shared__ int32_t pcnt[kThreads / kWave][kWave];
   __shared__ int32_t qpt[kThreads / kWave][2 * kWave], qm[kThreads / kWave][2 * kWave];  // pair queue
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int tile_id = blockIdx.x * (kThreads / kWave) + w;
-  float amin = INFINITY;
-  int e = -1;
-  unsigned long long npairs = 0;
-  auto slack_box = [](float a, float b, float &lo, float &hi) {
-    const float mn = fminf(a, b), mx = fmaxf(a, b);
-    lo = mn - fabsf(mn) * 4e-7f - 1e-30f;
-    hi = mx + fabsf(mx) * 4e-7f + 1e-30f;
-  };
-  if (tile_id < n_tiles && cell_start[total_cells] <= cap_items) {
+  const bool grid_ok = cell_start[total_cells] <= cap_items;
+  const int64_t nlist = *count;
+  // the waves walk the listed tiles (k_ccd_pre); each tile's flag is
+  // cleared once it is done, ready for the next call
+  for (int64_t li = (int64_t)blockIdx.x * (kThreads / kWave) + w; li < nlist;
+       li += (int64_t)gridDim.x * (kThreads / kWave)) {
+    const int tile_id = list[li];
+    if (!grid_ok) {  // nothing to test against: only the flag
+      if (lane == 0) tflag[tile_id] = 0;
+      continue;
+    }
+    wave_sync();  // the previous tile's LDS reads are done
+    float amin = INFINITY;
+    unsigned long long npairs = 0;
     const Tile tl = tiles[tile_id];
-    e = tl.env;
+    const int e = tl.env;
     const int j = lane / tl.nq, q = lane - j * tl.nq;
     const bool live = j < tl.count;
     const int64_t T = live ? s_order[tl.first + j] : 0;
@@ -270,17 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     float tlo[3], thi[3];
     if (live) {
       for (int k = 0; k < 3; ++k) v[k] = ts[3 * T + k];
-      for (int d = 0; d < 3; ++d) {  // the triangle's swept box covers every point's
-        float lo = INFINITY, hi = -INFINITY;
-        for (int k = 0; k < 3; ++k) {
-          float l, h;
-          slack_box((float)xs[3 * v[k] + d], (float)(xs[3 * v[k] + d] + dxs[3 * v[k] + d]), l, h);
-          lo = fminf(lo, l);
-          hi = fmaxf(hi, h);
-        }
-        tlo[d] = lo;
-        thi[d] = hi;
-      }
+      swept_tri_box<R>(xs, dxs, v, tlo, thi);  // covers every point's swept box
     }
     // ---- gather the triangle's swept candidates into its LDS slice
     if (live && q == 0) pcnt[w][j] = 0;
@@ -416,11 +526,18 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
             }
           }
     }
+    // the tile's minimum and pair count (one environment per tile)
+    unsigned long long tot = npairs;
+    for (int o = 32; o > 0; o >>= 1) {
+      tot += __shfl_xor(tot, o, kWave);
+      amin = fminf(amin, __shfl_xor(amin, o, kWave));
+    }
+    if (lane == 0) {
+      if (amin < INFINITY) atomicMin(&bits[e], __float_as_uint(amin));
+      if (tot) atomicAdd(&st->n_swept, tot);
+      tflag[tile_id] = 0;
+    }
   }
-  // pair count: wave sums, one atomic per block (with the minimum)
-  unsigned long long tot = npairs;
-  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
-  env_min(bits, e, amin, lane, tot, &st->n_swept);
 }
 
 template <typename R>
@@ -444,6 +561,8 @@ hipError_t launch_ccd_swept(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs,
   si.which = 4;
   si.box = b.sbox;
   si.alpha = b.alpha_bits;
+  si.zero[0] = b.scount;
+  si.nzero[0] = 1;
   hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_CCD_GRID, 0);
@@ -451,11 +570,18 @@ hipError_t launch_ccd_swept(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs,
   prof_mark(c, ST_CCD_GRID, 1);
   if (e != hipSuccess) return e;
   prof_mark(c, ST_CCD_ACCD, 0);
-  if (c->n_tiles)
-    hipLaunchKernelGGL(k_ccd_accd<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
-                       dim3(kThreads), 0, s, xs, xm, dxs, dxm, c->ts, c->tm, b.tiles, (int)c->n_tiles, b.s_order,
-                       b.env, b.rule, b.sgrid, b.scell_start, b.sitems, b.smbox, c->caps.grid_items, c->total_cells,
-                       b.alpha_bits, b.status);
+  // the tile-list walk uses a fixed grid (the list is usually short; its
+  // length is known on the device only)
+  const unsigned accd_blocks = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave), 2048));
+  if (c->n_tiles) {
+    hipLaunchKernelGGL(k_ccd_pre<R>, dim3((unsigned)((c->Ts + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, xs,
+                       dxs, c->ts, b.s_order, b.s_env, b.env, b.sgrid, c->Ts, b.scell_start, c->caps.grid_items,
+                       c->total_cells, b.tflag, b.slist, b.scount);
+    hipLaunchKernelGGL(k_ccd_accd<R>, dim3(accd_blocks), dim3(kThreads), 0, s, xs, xm, dxs, dxm, c->ts, c->tm,
+                       b.tiles, b.slist, b.scount, b.tflag, b.s_order, b.env, b.rule, b.sgrid, b.scell_start,
+                       b.sitems, b.smbox, c->caps.grid_items, c->total_cells, b.alpha_bits, b.status);
+  }
   prof_mark(c, ST_CCD_ACCD, 1);
   return hipGetLastError();
 }

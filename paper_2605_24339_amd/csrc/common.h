@@ -93,6 +93,8 @@ struct Buffers {
   int32_t *cand_blk;                            // [kQueryBlocks] candidates found by each query block
   int32_t *qlist, *qcount;                      // [Ts], [1]: slave triangles whose prism meets occupied cells
   float4 *qrec;                                 // [Ts][3]: their frames (box lo | T, box hi | env, normal)
+  int32_t *slist, *scount;                      // [n_tiles], [1]: work tiles whose swept boxes meet occupied cells
+  int32_t *tflag;                               // [n_tiles]: tile listed (zero between calls)
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
   void *tri_nrm;                                // [Ts][3] R

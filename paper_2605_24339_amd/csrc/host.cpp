@@ -203,6 +203,9 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.qlist = p.take<int32_t>(s.Ts);
   t.qcount = p.take<int32_t>(1);
   t.qrec = p.take<float4>(3 * s.Ts);
+  t.slist = p.take<int32_t>(s.n_tiles);
+  t.scount = p.take<int32_t>(1);
+  t.tflag = p.take<int32_t>(s.n_tiles);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
   t.tri_nrm = p.take<char>(rsz * 3 * s.Ts);
   t.tri_sum = p.take<char>(rsz * 9 * s.Ts);
@@ -474,6 +477,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
       fill_i32(c, c->b.scell_cnt, 0, caps->grid_cells + 1) != hipSuccess ||
       fill_i32(c, c->b.mp_cnt, 0, s.Tm + 1) != hipSuccess ||
       fill_i32(c, c->b.scan_tmp, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
+      fill_i32(c, c->b.tflag, 0, s.n_tiles) != hipSuccess ||
       fill_i32(c, c->b.scan_tmp2, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
