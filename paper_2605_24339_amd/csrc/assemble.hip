@@ -71,6 +71,7 @@ struct NarrowArgs {
   Pair<R> *pair;
   int64_t cap_pairs;
   int32_t *mp_cnt;  // pairs per master triangle (counted where the pairs are written)
+  int32_t *atile, *atile_cnt;  // tiles with selected samples (read by the linearised step bound)
   double *tile_E;
   DevStatus *st;
   bool features;                                   // clipped samples: edge and point samples too
@@ -88,31 +89,40 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   constexpr int kNW = narrow_waves<R>();
   __shared__ CandL<R> sc[kNW][kWave];
   __shared__ SampL<R> ss[kNW][kWave];
-  __shared__ unsigned int alloc_r[kNW], alloc_p[kNW];
+  __shared__ unsigned int alloc_r[kNW], alloc_p[kNW], alloc_t[kNW];
   __shared__ unsigned long long alloc_rb, alloc_pb;
+  __shared__ int alloc_tb;
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  // the block's allocation: every wave calls it once (two block barriers)
+  // the block's allocation: every wave calls it once (two block barriers);
+  // a wave with records also takes a slot of the active-tile list
+  int tslot = -1;
   auto allocate = [&](int nrec, int npair, unsigned long long &rb, unsigned long long &pb) {
     if (lane == 0) {
       alloc_r[w] = (unsigned)nrec;
       alloc_p[w] = (unsigned)npair;
+      alloc_t[w] = nrec > 0 ? 1u : 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long tr = 0, tp = 0;
+      unsigned tt = 0;
       for (int i = 0; i < kNW; ++i) {
-        const unsigned r0 = alloc_r[i], p0 = alloc_p[i];
+        const unsigned r0 = alloc_r[i], p0 = alloc_p[i], t0 = alloc_t[i];
         alloc_r[i] = (unsigned)tr;
         alloc_p[i] = (unsigned)tp;
+        alloc_t[i] = tt;
         tr += r0;
         tp += p0;
+        tt += t0;
       }
       alloc_rb = tr ? atomicAdd(&a.st->n_active, tr) : 0;
       alloc_pb = tp ? atomicAdd(&a.st->n_pairs, tp) : 0;
+      alloc_tb = (tt && a.atile) ? atomicAdd(a.atile_cnt, (int)tt) : 0;
     }
     __syncthreads();
     rb = alloc_rb + alloc_r[w];
     pb = alloc_pb + alloc_p[w];
+    if (nrec > 0) tslot = alloc_tb + (int)alloc_t[w];
   };
   const int tile_id = xcd_block(blockIdx.x, gridDim.x) * kNW + w;
   if (tile_id >= a.n_tiles) {
@@ -349,6 +359,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   allocate(nsel, npair_w, rbase, pbase);
   const bool rec_ok = rbase + nsel <= (unsigned long long)a.cap_active;
   if (nsel && !rec_ok && lane == 0) atomicCAS(&a.st->code, 0, GMCP_E_CAPACITY);
+  if (lane == 0 && tslot >= 0 && a.atile) a.atile[tslot] = tile_id;
   if (sel && rec_ok) {
     Rec<R> r;
     r.k = k;
@@ -1318,15 +1329,35 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     for (int64_t e = a.row_ptr[row] + lane; e < e1; e += kWave) {
       const int32_t c = a.col[e];
       if (c >= a.Vs) break;  // columns ascend: the slave columns come first
+      // column `row` in slave row c: an 8-way search (seven probes loaded
+      // together per round, then the last <= 8 entries at once), so a row of
+      // up to 64 columns takes two rounds of loads
       int64_t lo = a.row_ptr[c], hi = a.row_ptr[c + 1];
-      const int64_t end = hi;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a.col[mid] < row) lo = mid + 1;
-        else hi = mid;
+      while (hi - lo > 8) {
+        const int64_t step = (hi - lo + 7) >> 3;
+        int32_t pv[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) pv[k] = lo + (k + 1) * step < hi ? a.col[lo + (k + 1) * step] : INT32_MAX;
+        int64_t nlo = lo, nhi = hi;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const int64_t idx = lo + (k + 1) * step;
+          if (idx >= hi) break;
+          if (pv[k] <= (int32_t)row) nlo = idx;
+          else if (idx < nhi) nhi = idx;
+        }
+        lo = nlo;
+        hi = nhi;
       }
-      if (lo < end && a.col[lo] == row) {
-        for (int z = 0; z < 9; ++z) a.val[9 * e + z] = a.val[9 * lo + z];
+      int64_t at = -1;
+      int32_t cv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cv[k] = lo + k < hi ? a.col[lo + k] : -1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (cv[k] == (int32_t)row) at = lo + k;
+      if (at >= 0) {
+        for (int z = 0; z < 9; ++z) a.val[9 * e + z] = a.val[9 * at + z];
       } else {
         set_error(a.st, GMCP_E_CAPACITY, (unsigned long long)row);  // unreachable: the patterns are symmetric
       }
@@ -1883,6 +1914,8 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   si.nzero[0] = 2;
   si.zero[1] = b.row_cnt + c->V;  // the scan's tail
   si.nzero[1] = 1;
+  si.zero[2] = b.atile_cnt;  // active-tile list length
+  si.nzero[2] = 1;
   hipError_t e = stage_init(c, si);
   if (e != hipSuccess) return e;
   NarrowArgs<R> na;
@@ -1915,6 +1948,8 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.pair = (Pair<R> *)b.pair;
   na.cap_pairs = c->caps.pairs;
   na.mp_cnt = b.mp_cnt;
+  na.atile = c->mortar ? nullptr : b.atile;  // clipped samples: the step bound walks every tile
+  na.atile_cnt = b.atile_cnt;
   na.tile_E = b.tile_E;
   na.st = b.status;
   na.features = c->features;

@@ -62,14 +62,18 @@ __device__ inline void env_min(uint32_t *bits, int env, float a, int lane, unsig
 }
 
 // Eq. (ccd): alpha_k = 0.9 g_k / (-grad g_k . dx) for grad g_k . dx < 0.
-// One wave per work tile (the narrow phase's Morton tiles): lane (j, r0) takes
-// records r0, r0 + nq, ... of the tile's triangle j (contiguous per triangle),
-// so the triangle's normal and slave displacements are shared loads and the
-// wave belongs to one environment (one atomic per block and environment).
+// One wave per work tile (the narrow phase's Morton tiles) with selected
+// samples - the tiles the narrow phase listed, or every tile (list ==
+// nullptr, clipped samples): lane (j, r0) takes records r0, r0 + nq, ... of
+// the tile's triangle j (contiguous per triangle), so the triangle's normal
+// and slave displacements are shared loads and the wave belongs to one
+// environment (one atomic per tile).
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restrict__ rec, const DevStatus *st,
                                                           int64_t cap_active, const Tile *__restrict__ tiles,
-                                                          int n_tiles, const int32_t *__restrict__ s_order,
+                                                          int n_tiles, const int32_t *__restrict__ list,
+                                                          const int32_t *__restrict__ count,
+                                                          const int32_t *__restrict__ s_order,
                                                           const int32_t *__restrict__ tri_roff,
                                                           const int32_t *__restrict__ tri_rcnt,
                                                           const R *__restrict__ tri_nrm,
@@ -79,13 +83,23 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
                                                           const double *__restrict__ rule, const R *__restrict__ dxs,
                                                           const R *__restrict__ dxm, uint32_t *bits) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int tile_id = xcd_block(blockIdx.x, gridDim.x) * (kThreads / kWave) + threadIdx.x / kWave;
-  const bool ok = tile_id < n_tiles && (int64_t)st->n_active <= cap_active;
-  float a = INFINITY;
-  int e = -1;
-  if (ok) {
+  const int64_t nlist = (int64_t)st->n_active > cap_active ? 0 : (list ? *count : n_tiles);
+  // the wave's running minimum of environment ew (flushed when the
+  // environment changes; the last one goes through the block reduction)
+  int ew = -1;
+  float aw = INFINITY;
+  for (int64_t li = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave; li < nlist;
+       li += (int64_t)gridDim.x * (kThreads / kWave)) {
+    const int tile_id = list ? list[li] : (int)li;
+    float a = INFINITY;
     const Tile tl = tiles[tile_id];
-    e = tl.env;
+    const int e = tl.env;
+    if (e != ew) {
+      for (int o = 32; o > 0; o >>= 1) aw = fminf(aw, __shfl_xor(aw, o, kWave));
+      if (lane == 0 && ew >= 0 && aw < INFINITY) atomicMin(&bits[ew], __float_as_uint(aw));
+      ew = e;
+      aw = INFINITY;
+    }
     const int j = lane / tl.nq, r0 = lane - j * tl.nq;
     if (j < tl.count) {
       const int T = s_order[tl.first + j];
@@ -110,8 +124,9 @@ __global__ __launch_bounds__(kThreads) void k_ccd_linear(const Rec<R> *__restric
         if (gd < R(0)) a = fminf(a, to_float_down<R>(R(0.9) * rc.g / (-gd)));
       }
     }
+    aw = fminf(aw, a);
   }
-  env_min(bits, e, a, lane);
+  env_min(bits, ew, aw, lane);
 }
 
 // squared distance from the origin-relative point p to triangle (a, b, c):
@@ -359,6 +374,12 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const bool grid_ok = cell_start[total_cells] <= cap_items;
   const int64_t nlist = *count;
+  // the wave's running minimum of environment ew (flushed when the
+  // environment changes; the last one goes through the block reduction)
+  // and its pair count
+  int ew = -1;
+  float aw = INFINITY;
+  unsigned long long npairs = 0;
   // the waves walk the listed tiles (k_ccd_pre); each tile's flag is
   // cleared once it is done, ready for the next call
   for (int64_t li = (int64_t)blockIdx.x * (kThreads / kWave) + w; li < nlist;
@@ -370,9 +391,14 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
     }
     wave_sync();  // the previous tile's LDS reads are done
     float amin = INFINITY;
-    unsigned long long npairs = 0;
     const Tile tl = tiles[tile_id];
     const int e = tl.env;
+    if (e != ew) {
+      for (int o = 32; o > 0; o >>= 1) aw = fminf(aw, __shfl_xor(aw, o, kWave));
+      if (lane == 0 && ew >= 0 && aw < INFINITY) atomicMin(&bits[ew], __float_as_uint(aw));
+      ew = e;
+      aw = INFINITY;
+    }
     const int j = lane / tl.nq, q = lane - j * tl.nq;
     const bool live = j < tl.count;
     const int64_t T = live ? s_order[tl.first + j] : 0;
@@ -526,18 +552,13 @@ __global__ __launch_bounds__(kThreads) void k_ccd_accd(
             }
           }
     }
-    // the tile's minimum and pair count (one environment per tile)
-    unsigned long long tot = npairs;
-    for (int o = 32; o > 0; o >>= 1) {
-      tot += __shfl_xor(tot, o, kWave);
-      amin = fminf(amin, __shfl_xor(amin, o, kWave));
-    }
-    if (lane == 0) {
-      if (amin < INFINITY) atomicMin(&bits[e], __float_as_uint(amin));
-      if (tot) atomicAdd(&st->n_swept, tot);
-      tflag[tile_id] = 0;
-    }
+    aw = fminf(aw, amin);
+    if (lane == 0) tflag[tile_id] = 0;
   }
+  // pair count: wave sums, one atomic per block (with the minimum)
+  unsigned long long tot = npairs;
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, kWave);
+  env_min(bits, ew, aw, lane, tot, &st->n_swept);
 }
 
 template <typename R>
@@ -591,10 +612,13 @@ hipError_t launch_ccd_finish(gmcp_ctx *c, const R *dxs, const R *dxm, R *alpha) 
   Buffers &b = c->b;
   hipStream_t s = c->stream;
   prof_mark(c, ST_CCD_LINEAR, 0);
+  // a fixed grid walks the tiles with selected samples (their number is
+  // known on the device only); clipped samples: every tile
+  const unsigned lin_blocks = (unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave), 4096));
   if (c->n_tiles)
-    hipLaunchKernelGGL(k_ccd_linear<R>, dim3((unsigned)((c->n_tiles + kThreads / kWave - 1) / (kThreads / kWave))),
-                       dim3(kThreads), 0, s,
-                       (const Rec<R> *)b.rec, b.status, c->caps.active, b.tiles, (int)c->n_tiles, b.s_order,
+    hipLaunchKernelGGL(k_ccd_linear<R>, dim3(lin_blocks), dim3(kThreads), 0, s, (const Rec<R> *)b.rec, b.status,
+                       c->caps.active, b.tiles, (int)c->n_tiles, c->mortar ? nullptr : b.atile, b.atile_cnt, b.s_order,
                        b.tri_roff, b.tri_rcnt, (const R *)b.tri_nrm, c->ts, c->tm, b.env, b.rule, dxs, dxm,
                        b.alpha_bits);
   prof_mark(c, ST_CCD_LINEAR, 1);

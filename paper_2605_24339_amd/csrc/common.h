@@ -95,6 +95,7 @@ struct Buffers {
   float4 *qrec;                                 // [Ts][3]: their frames (box lo | T, box hi | env, normal)
   int32_t *slist, *scount;                      // [n_tiles], [1]: work tiles whose swept boxes meet occupied cells
   int32_t *tflag;                               // [n_tiles]: tile listed (zero between calls)
+  int32_t *atile, *atile_cnt;                   // [n_tiles], [1]: tiles with selected samples (last assembly)
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
   void *tri_nrm;                                // [Ts][3] R

@@ -206,6 +206,8 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.slist = p.take<int32_t>(s.n_tiles);
   t.scount = p.take<int32_t>(1);
   t.tflag = p.take<int32_t>(s.n_tiles);
+  t.atile = p.take<int32_t>(s.n_tiles);
+  t.atile_cnt = p.take<int32_t>(1);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
   t.tri_nrm = p.take<char>(rsz * 3 * s.Ts);
   t.tri_sum = p.take<char>(rsz * 9 * s.Ts);
