@@ -698,7 +698,7 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   if (nmb)
     hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(nmb)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr, c->tm,
                        c->Tm, mbox, b.m_env, b.env, box, grid, c->n_env, swept ? 1 : 0, cnt);
-  hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1, swept);
+  hipError_t e = scan_exclusive(c, cnt, start, c->total_cells + 1, swept, grid);
   if (e != hipSuccess) return e;
   if (c->Tm)
     hipLaunchKernelGGL(k_grid_insert, dim3(nblk(c->Tm)), dim3(kThreads), 0, s, mbox, b.m_env, b.env, grid, c->Tm,

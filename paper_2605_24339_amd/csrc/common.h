@@ -217,7 +217,10 @@ inline int heavy_row_blocks(const gmcp_ctx *c) {
 // each returns hipSuccess or the launch error
 // side = true uses the second scratch (the swept grid's scans may run on
 // another stream, concurrently with the broad phase and assembly)
-hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side = false);
+// grid: the environments' grids of a cell-count scan (only their used cells
+// and the total get valid starts), nullptr for a plain scan
+hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side = false,
+                          const GridEnv *grid = nullptr);
 hipError_t fill_i32(gmcp_ctx *c, int32_t *p, int32_t v, int64_t n);
 // one launch for a stage's scalar set-up: the status fields of the stage
 // (which: 1 broad phase, 2 assembly, 4 step bound), empty boxes and +inf

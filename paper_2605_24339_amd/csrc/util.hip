@@ -42,11 +42,38 @@ __device__ inline unsigned long long scan_desc(uint32_t epoch, uint32_t state, i
 // that takes the last ticket moves it to the next epoch with no tickets, so
 // the state is ready for the next call without a clearing pass, and the
 // descriptors of earlier calls no longer match.
+//
+// Grid scans (grid != nullptr): the cells of environment e are
+// [cell0_e, cell0_e + budget_e) and only the first nx ny nz of them are
+// used this call; the others hold zero counts and nobody reads their
+// starts.  A tile that meets no used range (nor the element after one, nor
+// the last element) publishes a zero sum and stops: its successors look
+// back past it.
+__device__ inline bool scan_tile_used(int64_t t0, int64_t t1, int64_t n, const GridEnv *grid, const EnvInfo *env,
+                                      int n_env) {
+  if (t1 >= n) return true;  // the total
+  int lo = 0, hi = n_env - 1;  // the last environment starting at or before t0
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (env[mid].cell0 <= t0) lo = mid;
+    else hi = mid - 1;
+  }
+  for (int e = lo; e < n_env && env[e].cell0 < t1; ++e) {
+    const GridEnv &g = grid[e];
+    const int64_t used = g.valid ? (int64_t)g.nx * g.ny * g.nz : 0;
+    if (env[e].cell0 + used >= t0) return true;  // [cell0, cell0 + used] meets [t0, t1)
+  }
+  return false;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const int32_t *__restrict__ in,
                                                                 int32_t *__restrict__ out, int64_t n,
                                                                 int64_t ntiles, unsigned long long *ticket,
-                                                                unsigned long long *desc, DevStatus *st) {
+                                                                unsigned long long *desc, DevStatus *st,
+                                                                const GridEnv *__restrict__ grid,
+                                                                const EnvInfo *__restrict__ env, int n_env) {
   __shared__ uint32_t s_tile, s_epoch;
+  __shared__ int s_used;
   __shared__ int wsum[kScanPer / 4][kScanThreads / kWave];
   __shared__ int lb_first[kScanThreads / kWave], lb_wait[kScanThreads / kWave], lb_sum[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
@@ -56,6 +83,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const int32_t *_
     if ((int64_t)t == ntiles - 1) atomicAdd(ticket, (1ull << 32) - (unsigned long long)ntiles);
     s_tile = t;
     s_epoch = (uint32_t)(tk >> 32) & 0x3fffffffu;
+    s_used = (int64_t)t >= ntiles || !grid ||
+             scan_tile_used((int64_t)t * kScanTile, ((int64_t)t + 1) * kScanTile, n, grid, env, n_env);
   }
   __syncthreads();
   const int64_t tile = (int64_t)s_tile;  // 0 .. 2^32 - 1
@@ -64,6 +93,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const int32_t *_
     return;
   }
   const uint32_t epoch = s_epoch;
+  if (!s_used) {  // unused cells: a zero sum (tile 0: its prefix), nothing loaded or written
+    if (tid == 0)
+      __hip_atomic_store(&desc[tile], scan_desc(epoch, tile == 0 ? 2u : 1u, 0), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   // coalesced loads: group k of the tile is elements [k * 4 * kScanThreads,
   // (k + 1) * 4 * kScanThreads), four consecutive ones per thread
   constexpr int kGroups = kScanPer / 4;
@@ -195,7 +230,7 @@ __global__ void k_stage_init(DevStatus *st, StageInit a, int n_env) {
 
 }  // namespace
 
-hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side) {
+hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t n, bool side, const GridEnv *grid) {
   // one state per stream that scans (the side stream scans the swept grid):
   // the ticket word, then one descriptor per tile
   int32_t *const scratch = side ? c->b.scan_tmp2 : c->b.scan_tmp;
@@ -206,7 +241,7 @@ hipError_t scan_exclusive(gmcp_ctx *c, const int32_t *in, int32_t *out, int64_t 
     return hipErrorInvalidValue;
   unsigned long long *ticket = reinterpret_cast<unsigned long long *>(scratch);
   hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)ntiles), dim3(kScanThreads), 0, c->stream, in, out, n, ntiles,
-                     ticket, ticket + 1, c->b.status);
+                     ticket, ticket + 1, c->b.status, grid, c->b.env, c->n_env);
   return hipGetLastError();
 }
 
