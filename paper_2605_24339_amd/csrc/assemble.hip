@@ -1316,12 +1316,30 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   // XCDs holding them finish last)
   const int lblk = blockIdx.x;
   // each list entry carries the row's adjacency range and contribution
-  // count (k_row_pre), so a row starts with one load
-  for (int64_t li = (int64_t)lblk * nw + w; li < nlist; li += (int64_t)gridDim.x * nw)
-    [&](const int4 rr) {
+  // count (k_row_pre), so a row starts with one load.  The loads are
+  // pipelined over the wave's rows: the entry two rows ahead and the first
+  // adjacency entries (one per lane) of the next row are in flight while the
+  // wave works on the current one.
+  const int64_t lstride = (int64_t)gridDim.x * nw;
+  int64_t li = (int64_t)lblk * nw + w;
+  auto first_ent = [&](const int4 r) -> int {  // adjacency entry sb + lane of row r
+    if (pass == 3 || r.y + lane >= r.z) return 0;
+    return r.x < a.Vs ? a.s_vt[r.y + lane] : a.m_vt[r.y + lane];
+  };
+  int4 rr_c = li < nlist ? rlist[li] : make_int4(0, 0, 0, 0);
+  int4 rr_n = li + lstride < nlist ? rlist[li + lstride] : make_int4(0, 0, 0, 0);
+  int ent_c = li < nlist ? first_ent(rr_c) : 0;
+  for (; li < nlist; li += lstride) {
+    const int ent_n = li + lstride < nlist ? first_ent(rr_n) : 0;
+    const int4 rr_nn = li + 2 * lstride < nlist ? rlist[li + 2 * lstride] : make_int4(0, 0, 0, 0);
+    [&](const int4 rr, const int ent0) {
   wave_sync();  // the previous row's LDS reads are done
   const int64_t row = rr.x;
   const bool slave = row < a.Vs;
+  // adjacency entry src of this row (the first one per lane was prefetched)
+  auto vt_at = [&](int src) -> int {
+    return src - rr.y == lane ? ent0 : (slave ? a.s_vt[src] : a.m_vt[src]);
+  };
 
   if (pass == 3) {
     if (slave) return;
@@ -1374,7 +1392,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       // gradient row: lane partials over the incident triangles, fixed-order butterfly
       R gr[3] = {0, 0, 0};
       for (int src = sb + lane; src < se; src += kWave) {
-        const int ent = a.m_vt[src], t = ent >> 2, corner = ent & 3;
+        const int ent = vt_at(src), t = ent >> 2, corner = ent & 3;
         if (a.mp_off[t] == a.mp_off[t + 1]) continue;
         const R *G = a.mtri + 45 * (int64_t)t + 36 + 3 * corner;
         for (int d = 0; d < 3; ++d) gr[d] += G[d];
@@ -1401,7 +1419,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       const int src = s0 + lane;
       int t = 0, corner = 0, np = 0, pb = 0, tv[3] = {0, 0, 0};
       if (lane < kRowSrc && src < se) {
-        const int ent = a.m_vt[src];
+        const int ent = vt_at(src);
         t = ent >> 2;
         corner = ent & 3;
         pb = a.mp_off[t];
@@ -1524,7 +1542,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     // partials, fixed-order butterfly)
     R gr[3] = {0, 0, 0};
     for (int src = sb + lane; src < se; src += kWave) {
-      const int ent = a.s_vt[src], t = ent >> 2, corner = ent & 3;
+      const int ent = vt_at(src), t = ent >> 2, corner = ent & 3;
       if (a.tri_npair[t] == 0) continue;
       const R cf = -a.tri_sum[9 * (int64_t)t + 6 + corner];
       const R *nn = a.tri_nrm + 3 * (int64_t)t;
@@ -1560,7 +1578,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     const int src = s0 + lane;
     int t = 0, corner = 0, np = 0, pb = 0;
     if (lane < kRowSrc && src < se) {
-      const int ent = a.s_vt[src];
+      const int ent = vt_at(src);
       t = ent >> 2;
       corner = ent & 3;
       np = a.tri_npair[t];
@@ -1672,7 +1690,11 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     ov[3] = v[1]; ov[4] = v[3]; ov[5] = v[4];
     ov[6] = v[2]; ov[7] = v[4]; ov[8] = v[5];
   }
-    }(rlist[li]);
+    }(rr_c, ent_c);
+    rr_c = rr_n;
+    ent_c = ent_n;
+    rr_n = rr_nn;
+  }
 }
 
 
