@@ -445,8 +445,9 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     """HBM traffic of every kernel of a workload's step from two counter runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
     same counter reads for a plain device copy of known size.  Launches per
-    step are the kernel's dispatches over those of ref_kernel (once per
-    step).  Stored in profiles/traffic.json under the current source hash."""
+    step are the dispatches of one step (between the last two launches of
+    ref_kernel, once per step).  Stored in profiles/traffic.json under the
+    current source hash."""
     import csv
     copy_bytes = 4 * 64 * 1024 * 1024
     cf = _counter_means(copy_fetch_csv, "FETCH_SIZE")
@@ -457,22 +458,28 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     f = _counter_means(fetch_csv, "FETCH_SIZE")
     w = _counter_means(write_csv, "WRITE_SIZE")
 
-    def dispatches(path):
+    def step_launches(path):
+        """Launches of each kernel in one step: the dispatches from the
+        second-to-last launch of ref_kernel (once per step) to the last."""
         import re
-        n = {}
+        seq = []
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") != "FETCH_SIZE":
                     continue
                 name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
                 name = re.sub(r"\(.*", "", re.sub(r"^void ", "", name)).split("::")[-1]
-                n[name] = n.get(name, 0) + 1
+                seq.append((int(r["Dispatch_Id"]), name))
+        seq.sort()
+        ref = [i for i, (_, n) in enumerate(seq) if n == ref_kernel]
+        n = {}
+        for _, k in seq[ref[-2]:ref[-1]]:
+            n[k] = n.get(k, 0) + 1
         return n
 
-    nd = dispatches(fetch_csv)
-    per_step = {k: nd[k] / nd[ref_kernel] for k in nd}
+    per_step = step_launches(fetch_csv)
     kernels = {k: f[k] * 1024.0 * f_scale + w.get(k, 0.0) * 1024.0 * w_scale for k in f}
-    step = sum(kernels[k] * round(per_step[k], 2) for k in kernels if k.startswith("k_"))
+    step = sum(kernels[k] * per_step.get(k, 0) for k in kernels)
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     known = {}
     if os.path.exists(tf):
@@ -480,7 +487,7 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
             known = json.load(fh)
     known[workload] = {"src_hash": src_hash(), "kernels": {k: round(v) for k, v in kernels.items()
                                                            if k.startswith("k_")},
-                       "launches_per_step": {k: round(v, 2) for k, v in per_step.items() if k.startswith("k_")},
+                       "launches_per_step": per_step,
                        "step_bytes": round(step), "copy_kernel": ck, "fetch_scale": f_scale, "write_scale": w_scale}
     with open(tf, "w") as fh:
         json.dump(known, fh, indent=1)
