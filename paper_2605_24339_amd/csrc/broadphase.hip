@@ -30,43 +30,41 @@ __device__ inline void load3(const R *x, int64_t v, float o[3]) {
 // outward rounding margin for float boxes of (possibly double) coordinates
 __device__ inline float grow(float v) { return fabsf(v) * 4e-7f + 1e-30f; }
 
-// slave surface box per environment (swept: union of x and x + dx); large
-// blocks, so that few blocks meet at each environment's six words
+// slave surface box per environment (swept: union of x and x + dx): thread
+// per slave vertex on a slave triangle (the union of the triangles' vertex
+// boxes, read coalesced); large blocks, so that few blocks meet at each
+// environment's six words
 constexpr int kBoxThreads = 1024;
 
 template <typename R>
 __global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
-                                                         const int32_t *__restrict__ ts,
-                                                         const int32_t *__restrict__ s_env, int64_t Ts,
+                                                         const int32_t *__restrict__ s_venv, int64_t Vs,
                                                          uint32_t *box, int32_t *zero_a, int32_t *zero_b) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {  // counters of the kernels that follow (nullable)
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) {  // counters of the kernels that follow (nullable)
     if (zero_a) *zero_a = 0;
     if (zero_b) *zero_b = 0;
   }
   int lane = threadIdx.x & (kWave - 1);
-  bool ok = t < Ts;
-  int env = ok ? s_env[t] : -1;
+  int env = v < Vs ? s_venv[v] : -1;
+  bool ok = env >= 0;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (ok) {
-    for (int j = 0; j < 3; ++j) {
-      int v = ts[3 * t + j];
-      float p[3];
-      load3(xs, v, p);
+    float p[3];
+    load3(xs, v, p);
+    for (int d = 0; d < 3; ++d) {  // fminf / fmaxf: a NaN coordinate leaves the box as it is
+      lo[d] = fminf(lo[d], p[d] - grow(p[d]));
+      hi[d] = fmaxf(hi[d], p[d] + grow(p[d]));
+    }
+    if (dxs) {
       for (int d = 0; d < 3; ++d) {
-        lo[d] = fminf(lo[d], p[d] - grow(p[d]));
-        hi[d] = fmaxf(hi[d], p[d] + grow(p[d]));
-      }
-      if (dxs) {
-        for (int d = 0; d < 3; ++d) {
-          float q = (float)(xs[3 * (int64_t)v + d] + dxs[3 * (int64_t)v + d]);
-          lo[d] = fminf(lo[d], q - grow(q));
-          hi[d] = fmaxf(hi[d], q + grow(q));
-        }
+        float q = (float)(xs[3 * v + d] + dxs[3 * v + d]);
+        lo[d] = fminf(lo[d], q - grow(q));
+        hi[d] = fmaxf(hi[d], q + grow(q));
       }
     }
   }
-  // environments are contiguous in triangle order: most blocks hold one,
+  // environments are contiguous in vertex order: most blocks hold one,
   // which then takes a single set of atomics
   __shared__ int benv[kBoxThreads / kWave];
   __shared__ float bbox[kBoxThreads / kWave][6];
@@ -691,8 +689,8 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   // the static ones from the previous query prepass (or creation); the
   // slave-box kernel also zeroes the broad phase's two list counters
   if (c->Ts)
-    hipLaunchKernelGGL(k_slave_box<R>, dim3((unsigned)((c->Ts + kBoxThreads - 1) / kBoxThreads)),
-                       dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, c->ts, b.s_env, c->Ts, box,
+    hipLaunchKernelGGL(k_slave_box<R>, dim3((unsigned)((c->Vs + kBoxThreads - 1) / kBoxThreads)),
+                       dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, b.s_venv, c->Vs, box,
                        swept ? nullptr : b.qcount, swept ? nullptr : b.cand_cnt + c->Ts);
   const int64_t nmb = std::max<int64_t>(c->Tm, c->n_env);
   if (nmb)

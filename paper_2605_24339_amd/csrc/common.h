@@ -79,6 +79,7 @@ struct Buffers {
   EnvInfo *env;
   Tile *tiles;
   int32_t *s_order, *samp_off, *s_env, *m_env;
+  int32_t *s_venv;                              // [Vs]: environment of a slave vertex on a slave triangle, else -1
   int32_t *s_vt_off, *s_vt, *m_vt_off, *m_vt;   // vt entries: tri*4 + corner
   double *rule;                                 // [4][16][3] xi, eta, w; then [4][4][2] 1D Gauss-Legendre
   int32_t *m_opp;                               // [Tm][3] triangle across edge k of a master triangle, -1

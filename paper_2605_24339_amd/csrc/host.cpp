@@ -180,6 +180,7 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.s_order = p.take<int32_t>(s.Ts);
   t.samp_off = p.take<int32_t>(s.Ts + 1);
   t.s_env = p.take<int32_t>(s.Ts);
+  t.s_venv = p.take<int32_t>(s.Vs);
   t.m_env = p.take<int32_t>(s.Tm);
   t.s_vt_off = p.take<int32_t>(s.Vs + 1);
   t.s_vt = p.take<int32_t>(3 * s.Ts);
@@ -420,6 +421,11 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   }
   samp_off[s.Ts] = (int32_t)samp0;
   c->total_cells = cell0;
+  // environment of every slave vertex that a slave triangle uses (-1: none),
+  // so the slave surface's boxes come from a coalesced pass over vertices
+  std::vector<int32_t> s_venv(s.Vs, -1);
+  for (int64_t t = 0; t < s.Ts; ++t)
+    for (int j = 0; j < 3; ++j) s_venv[ts[3 * t + j]] = s_env[t];
   // vertex -> (triangle, corner) adjacency, triangles ascending per vertex
   auto adjacency = [](int64_t V, int64_t T, const std::vector<int32_t> &tri, std::vector<int32_t> &off,
                       std::vector<int32_t> &lst) {
@@ -443,6 +449,7 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
   up(c->b.env, c->henv.data(), sizeof(EnvInfo) * s.n_env);
   up(c->b.samp_off, samp_off.data(), sizeof(int32_t) * (s.Ts + 1));
   up(c->b.s_env, s_env.data(), sizeof(int32_t) * s.Ts);
+  up(c->b.s_venv, s_venv.data(), sizeof(int32_t) * s.Vs);
   up(c->b.m_env, m_env.data(), sizeof(int32_t) * s.Tm);
   up(c->b.s_vt_off, svo.data(), sizeof(int32_t) * (s.Vs + 1));
   up(c->b.s_vt, svt.data(), sizeof(int32_t) * 3 * s.Ts);
@@ -827,6 +834,7 @@ const char *gmcp_strerror(int code) {
     case GMCP_E_DEGENERATE: return "degenerate slave triangle";
     case GMCP_E_NONFINITE: return "non-finite input";
     case GMCP_E_HIP: return "HIP runtime error";
+    case GMCP_E_TIMEOUT: return "a device-side wait passed its bound (internal error)";
     default: return "unknown status";
   }
 }
