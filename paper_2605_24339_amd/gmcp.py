@@ -112,7 +112,10 @@ class Context:
         self.Ns = sum((int(slave_t_off[e + 1]) - int(slave_t_off[e])) * int(rule_n[e]) ** 2
                       for e in range(self.n_env))
         self.V = self.Vs if kinematic else self.Vs + self.Vm
-        c = dict(grid_cells=8 * (self.Ts + self.Tm) + 4096 * self.n_env,
+        # grid cell budget: 2 per triangle (the support radius usually sets
+        # the cell size; a budget of 8 per triangle only made the cell-count
+        # scans longer: 256-environment step 6.07 -> 6.01 ms at 2)
+        c = dict(grid_cells=2 * (self.Ts + self.Tm) + 4096 * self.n_env,
                  grid_items=16 * self.Tm + 4096, candidates=16 * self.Ts + 4096,
                  active=(3 * self.Ns if self.mortar else self.Ns) + 64, pairs=self.Ns // 2 + 1024,
                  row_entries=256)
