@@ -72,6 +72,7 @@ struct NarrowArgs {
   int64_t cap_pairs;
   int32_t *mp_cnt;  // pairs per master triangle (counted where the pairs are written)
   int32_t *atile, *atile_cnt;  // tiles with selected samples (read by the linearised step bound)
+  const uint32_t *tile_act, *epoch;  // nullable: tiles the last broad phase listed (others have no candidates)
   double *tile_E;
   DevStatus *st;
   bool features;                                   // clipped samples: edge and point samples too
@@ -126,6 +127,14 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   };
   const int tile_id = xcd_block(blockIdx.x, gridDim.x) * kNW + w;
   if (tile_id >= a.n_tiles) {
+    unsigned long long rb, pb;
+    allocate(0, 0, rb, pb);
+    return;
+  }
+  // a tile none of whose triangles the broad phase listed has no candidates
+  // (the broad phase emptied their per-triangle outputs): one load decides
+  if (a.tile_act && a.tile_act[tile_id] != *a.epoch) {
+    if (lane == 0) a.tile_E[tile_id] = 0.0;
     unsigned long long rb, pb;
     allocate(0, 0, rb, pb);
     return;
@@ -1972,6 +1981,8 @@ hipError_t launch_assemble(gmcp_ctx *c, const R *xs, const R *xm, const R *g_ref
   na.mp_cnt = b.mp_cnt;
   na.atile = c->mortar ? nullptr : b.atile;  // clipped samples: the step bound walks every tile
   na.atile_cnt = b.atile_cnt;
+  na.tile_act = c->mortar ? nullptr : b.tile_act;
+  na.epoch = b.epoch;
   na.tile_E = b.tile_E;
   na.st = b.status;
   na.features = c->features;

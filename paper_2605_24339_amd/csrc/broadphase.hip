@@ -39,11 +39,13 @@ constexpr int kBoxThreads = 1024;
 template <typename R>
 __global__ __launch_bounds__(kBoxThreads) void k_slave_box(const R *__restrict__ xs, const R *__restrict__ dxs,
                                                          const int32_t *__restrict__ s_venv, int64_t Vs,
-                                                         uint32_t *box, int32_t *zero_a, int32_t *zero_b) {
+                                                         uint32_t *box, int32_t *zero_a, int32_t *zero_b,
+                                                         uint32_t *epoch) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v == 0) {  // counters of the kernels that follow (nullable)
+  if (v == 0) {  // counters of the kernels that follow (nullable), and the broad phase's epoch
     if (zero_a) *zero_a = 0;
     if (zero_b) *zero_b = 0;
+    if (epoch) *epoch += 1u;
   }
   int lane = threadIdx.x & (kWave - 1);
   int env = v < Vs ? s_venv[v] : -1;
@@ -337,7 +339,10 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
                                                          int64_t total_cells, int32_t *__restrict__ cand_cnt,
                                                          int32_t *__restrict__ qlist, float4 *__restrict__ qrec,
                                                          int32_t *__restrict__ qcount, uint32_t *__restrict__ box,
-                                                         int n_env, DevStatus *st) {
+                                                         int n_env, DevStatus *st, const uint32_t *__restrict__ epoch,
+                                                         uint32_t *__restrict__ tile_act,
+                                                         int32_t *__restrict__ tri_npair, int32_t *__restrict__ tri_rcnt,
+                                                         int32_t *__restrict__ tri_poff, int32_t *__restrict__ tri_roff) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   if (i < n_env)  // the slave boxes were read by the grid kernels: empty them for the next call
@@ -409,7 +414,18 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
         }
       }
     }
-    if (!active) cand_cnt[t] = 0;
+    if (!active) {
+      // no candidates: the assembly's per-triangle outputs are empty, and a
+      // work tile with no listed triangle is skipped by the narrow phase
+      cand_cnt[t] = 0;
+      tri_npair[t] = 0;
+      tri_rcnt[t] = 0;
+      tri_poff[t] = 0;
+      tri_roff[t] = 0;
+    } else {
+      const EnvInfo &ev = env[s_env[t]];
+      tile_act[ev.tile0 + (int)((i - ev.st0) / (kWave / ev.nq))] = *epoch;
+    }
   }
   // list appends: wave ballots, block prefix in LDS, one atomic per block
   __shared__ int wq[kThreads / kWave], qb;
@@ -691,7 +707,7 @@ hipError_t build_grid(gmcp_ctx *c, const R *xs, const R *xm, const R *dxs, const
   if (c->Ts)
     hipLaunchKernelGGL(k_slave_box<R>, dim3((unsigned)((c->Vs + kBoxThreads - 1) / kBoxThreads)),
                        dim3(kBoxThreads), 0, s, xs, swept ? dxs : nullptr, b.s_venv, c->Vs, box,
-                       swept ? nullptr : b.qcount, swept ? nullptr : b.cand_cnt + c->Ts);
+                       swept ? nullptr : b.qcount, swept ? nullptr : b.cand_cnt + c->Ts, swept ? nullptr : b.epoch);
   const int64_t nmb = std::max<int64_t>(c->Tm, c->n_env);
   if (nmb)
     hipLaunchKernelGGL(k_master_boxes<R>, dim3(nblk(nmb)), dim3(kThreads), 0, s, xm, swept ? dxm : nullptr, c->tm,
@@ -727,7 +743,8 @@ hipError_t launch_broadphase(gmcp_ctx *c, const R *xs, const R *xm) {
   if (c->Ts)
     hipLaunchKernelGGL(k_query_pre<R>, dim3(nblk(std::max<int64_t>(c->Ts, c->n_env))), dim3(kThreads), 0, s, xs, c->ts,
                        b.s_order, b.s_env, b.env, b.grid, c->Ts, b.cell_start, c->caps.grid_items, c->total_cells,
-                       b.cand_cnt, b.qlist, b.qrec, b.qcount, b.box, c->n_env, b.status);
+                       b.cand_cnt, b.qlist, b.qrec, b.qcount, b.box, c->n_env, b.status, b.epoch, b.tile_act,
+                       b.tri_npair, b.tri_rcnt, b.tri_poff, b.tri_roff);
   prof_mark(c, ST_QUERY_PRE, 1);
   // the wave kernels walk the query list with a fixed grid, all of it
   // resident at once

@@ -97,6 +97,8 @@ struct Buffers {
   int32_t *slist, *scount;                      // [n_tiles], [1]: work tiles whose swept boxes meet occupied cells
   int32_t *tflag;                               // [n_tiles]: tile listed (zero between calls)
   int32_t *atile, *atile_cnt;                   // [n_tiles], [1]: tiles with selected samples (last assembly)
+  uint32_t *epoch;                              // [1]: broad phases so far (marks the active tiles)
+  uint32_t *tile_act;                           // [n_tiles]: the epoch of the last broad phase that listed a triangle of the tile
   // narrow / assembly
   void *rec;                                    // Rec<R>[cap.active]
   void *tri_nrm;                                // [Ts][3] R

@@ -209,6 +209,8 @@ size_t plan_workspace(const Sizes &s, const gmcp_caps &cp, char *base, Buffers *
   t.tflag = p.take<int32_t>(s.n_tiles);
   t.atile = p.take<int32_t>(s.n_tiles);
   t.atile_cnt = p.take<int32_t>(1);
+  t.epoch = p.take<uint32_t>(1);
+  t.tile_act = p.take<uint32_t>(s.n_tiles);
   t.rec = p.take<char>((s.f64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cp.active);
   t.tri_nrm = p.take<char>(rsz * 3 * s.Ts);
   t.tri_sum = p.take<char>(rsz * 9 * s.Ts);
@@ -487,6 +489,8 @@ int gmcp_create(gmcp_ctx **out, const gmcp_layout *L, const gmcp_caps *caps, con
       fill_i32(c, c->b.mp_cnt, 0, s.Tm + 1) != hipSuccess ||
       fill_i32(c, c->b.scan_tmp, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
       fill_i32(c, c->b.tflag, 0, s.n_tiles) != hipSuccess ||
+      fill_i32(c, reinterpret_cast<int32_t *>(c->b.epoch), 0, 1) != hipSuccess ||
+      fill_i32(c, reinterpret_cast<int32_t *>(c->b.tile_act), 0, s.n_tiles) != hipSuccess ||
       fill_i32(c, c->b.scan_tmp2, 0, (int64_t)c->scan_tmp_elems) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
