@@ -403,6 +403,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
     Pair<R> p;
     p.T = T;
     p.M = bM;
+    for (int m = 0; m < 3; ++m) p.mv[m] = a.tm[3 * (int64_t)bM + m];
     for (int z = 0; z < 6; ++z) p.mm[z] = 0;
     for (int z = 0; z < 9; ++z) p.sm[z] = 0;
     for (int z = 0; z < 3; ++z) p.gm[z] = 0;
@@ -988,6 +989,7 @@ __device__ __forceinline__ void mortar_body(const NarrowArgs<R> &a) {
         Pair<R> pr;
         pr.T = T;
         pr.M = M;
+        for (int m = 0; m < 3; ++m) pr.mv[m] = a.tm[3 * (int64_t)M + m];
         for (int z = 0; z < 6; ++z) pr.mm[z] = pacc[z][lane];
         for (int z = 0; z < 9; ++z) pr.sm[z] = pacc[6 + z][lane];
         for (int z = 0; z < 3; ++z) pr.gm[z] = pacc[15 + z][lane];
@@ -1541,7 +1543,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       const int pb = a.tri_poff[t], np = a.tri_npair[t];
       for (int p = pb; p < pb + np; ++p) {
         const Pair<R> &P = a.pair[p];
-        for (int m = 0; m < 3; ++m) visit((int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]), P.sm[3 * corner + m], t);
+        for (int m = 0; m < 3; ++m) visit((int32_t)(a.Vs + P.mv[m]), P.sm[3 * corner + m], t);
       }
     }
   };
@@ -1635,7 +1637,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       } else {  // pair j - 1 of the triangle: its master vertices
         const Pair<R> &P = a.pair[spb[lo] + j - 1];
         for (int m = 0; m < 3; ++m) {
-          col[m] = (int32_t)(a.Vs + a.tm[3 * (int64_t)P.M + m]);
+          col[m] = (int32_t)(a.Vs + P.mv[m]);
           cf[m] = P.sm[3 * c + m];
         }
         put3(col, cf, seo[lo] + 3 + 3 * (j - 1), lo);

@@ -68,6 +68,7 @@ struct Rec {               // active sample record
 template <typename R>
 struct Pair {              // one (slave triangle, master triangle) contact
   int32_t T, M;
+  int32_t mv[3];           // M's vertex ids (saves the row kernels a dependent gather)
   R mm[6];   // sum c2 bm_i bm_j           (sym, order 00 01 02 11 12 22)
   R sm[9];   // sum -c2 bs_a bm_j          (a-major)
   R gm[3];   // sum c1 bm_j
