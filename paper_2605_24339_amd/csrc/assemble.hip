@@ -35,6 +35,11 @@ template <typename R> struct SampL {
   R s1, s2;  // the rule point (slave barycentrics 1 - s1 - s2, s1, s2)
 };
 
+template <typename R> union NarrowSlot {
+  CandL<R> c;
+  SampL<R> s;
+};
+
 __device__ inline int sym3(int a, int b) {  // 00 01 02 11 12 22
   if (a > b) { int t = a; a = b; b = t; }
   return a == 0 ? b : (a == 1 ? 2 + b : 5);
@@ -88,8 +93,9 @@ template <typename R> constexpr int narrow_waves() { return sizeof(R) == 4 ? 8 :
 template <typename R>
 __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   constexpr int kNW = narrow_waves<R>();
-  __shared__ CandL<R> sc[kNW][kWave];
-  __shared__ SampL<R> ss[kNW][kWave];
+  // a wave's staged candidates and, once its candidate loop is done, its
+  // sample records share one LDS slot per lane (more resident blocks)
+  __shared__ NarrowSlot<R> nl[kNW][kWave];
   __shared__ unsigned int alloc_r[kNW], alloc_p[kNW], alloc_t[kNW];
   __shared__ unsigned long long alloc_rb, alloc_pb;
   __shared__ int alloc_tb;
@@ -241,11 +247,11 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
         cl.inv_den = R(1) / den;
       }
     }
-    sc[w][lane] = cl;
+    nl[w][lane].c = cl;
     wave_sync();
     int nc = min(nq, ccnt - base);
     for (int c = 0; c < nc; ++c) {
-      const CandL<R> &e = sc[w][j * nq + c];
+      const CandL<R> &e = nl[w][j * nq + c].c;
       if (e.M < 0) continue;
       R dv[3] = {e.d0[0] - ps[0], e.d0[1] - ps[1], e.d0[2] - ps[2]};  // m0 - x_s,k
       R t = (e.N[0] * dv[0] + e.N[1] * dv[1] + e.N[2] * dv[2]) * e.inv_den;
@@ -309,7 +315,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   me.b2 = bb2;
   me.s1 = xi;
   me.s2 = eta;
-  ss[w][lane] = me;
+  nl[w][lane].s = me;
   wave_sync();
 
   // ---- per slave triangle sums (A6): ss[6] = sum c2 bs_a bs_b, gs[3] = sum c1 bs_a
@@ -330,7 +336,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
         ib = -1;
       }
       for (int i = 0; i < nq; ++i) {
-        const SampL<R> &o = ss[w][j * nq + i];
+        const SampL<R> &o = nl[w][j * nq + i].s;
         if (o.M < 0) continue;
         R bs[3] = {R(1) - o.s1 - o.s2, o.s1, o.s2};
         acc += ib >= 0 ? o.c2 * bs[ia] * bs[ib] : o.c1 * bs[ia];
@@ -347,7 +353,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   if (sel) {
     leader = true;
     for (int i = 0; i < q; ++i)
-      if (ss[w][j * nq + i].M == bM) {
+      if (nl[w][j * nq + i].s.M == bM) {
         leader = false;
         break;
       }
@@ -355,7 +361,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
   const uint64_t leadmask = __ballot(leader);
   if (leader) {
     for (int i = 0; i < nq; ++i) {
-      const SampL<R> &o = ss[w][j * nq + i];
+      const SampL<R> &o = nl[w][j * nq + i].s;
       if (((leadmask >> (j * nq + i)) & 1) && o.M < bM) ++rank;
     }
   }
@@ -408,7 +414,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs<R> &a) {
     for (int z = 0; z < 9; ++z) p.sm[z] = 0;
     for (int z = 0; z < 3; ++z) p.gm[z] = 0;
     for (int i = 0; i < nq; ++i) {
-      const SampL<R> &o = ss[w][j * nq + i];
+      const SampL<R> &o = nl[w][j * nq + i].s;
       if (o.M != bM) continue;
       R bs[3] = {R(1) - o.s1 - o.s2, o.s1, o.s2};
       R bm[3] = {o.b0, o.b1, o.b2};
