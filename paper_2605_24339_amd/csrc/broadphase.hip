@@ -283,6 +283,8 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
 
 constexpr int kQueryWaves = kThreads / kWave;
 constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS set)
+constexpr int kQuerySmall = 128;      // the first set a triangle tries
+constexpr int kQuerySmallProbe = 32;  // probes before it moves to the full set
 constexpr int kMaxSlabs = 64;
 
 // vertex box and unit normal of slave triangle t (float, grown outward)
@@ -535,70 +537,78 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
   }
   const int work = __shfl(incl, kWave - 1, kWave);
   const int64_t base = env[e].cell0;
-  // the listed triangles' prisms meet occupied cells (k_query_pre): the set
-  // takes its full size, which saves a counting pass over the cells
-  constexpr int tsz = kQuerySet;
-  for (int k = lane; k < tsz; k += kWave) set[w][k] = -1;
-  wave_sync();
-  bool full = false;
-  // the (slab, cell) items are taken 64 at a time; their master-triangle
-  // incidences are flattened over the lanes (exclusive prefix of the cell
-  // sizes in LDS, binary search per incidence), so a crowded cell does not
-  // serialise on one lane
-  for (int w0 = 0; w0 < work; w0 += kWave) {
-    const int wi = w0 + lane;
-    int s = 0;
-    for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
-    s = min(s, kWave - 1);
-    const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
-    const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
-    const int sstart = __shfl(incl - ncs, s, kWave);
-    int cs = 0, cn = 0;
-    if (wi < work) {
-      const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
-      const int li = wi - sstart;
-      const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
-      const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
-      cs = cell_start[cell];
-      cn = cell_start[cell + 1] - cs;
-    }
-    int ci = cn;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int v = __shfl_up(ci, d, kWave);
-      if (lane >= d) ci += v;
-    }
-    const int tot = __shfl(ci, kWave - 1, kWave);
+  // the candidate set starts small (most triangles have a few candidates:
+  // a short set is cheap to clear and compact); a triangle whose insertions
+  // probe too far walks its cells again with the full set
+  int tsz = kQuerySmall;
+  bool full;
+  for (;;) {
+    for (int k = lane; k < tsz; k += kWave) set[w][k] = -1;
     wave_sync();
-    ipfx[w][lane] = ci - cn;
-    istart[w][lane] = cs;
-    islab[w][lane] = s;
-    wave_sync();
-    for (int f = lane; f < tot; f += kWave) {
-      int lo_k = 0, hi_k = kWave - 1;  // the last item whose prefix is <= f
-      while (lo_k < hi_k) {
-        const int mid = (lo_k + hi_k + 1) >> 1;
-        if (ipfx[w][mid] <= f) lo_k = mid;
-        else hi_k = mid - 1;
+    full = false;
+    const int max_probe = tsz == kQuerySet ? kQuerySet : kQuerySmallProbe;
+    // the (slab, cell) items are taken 64 at a time; their master-triangle
+    // incidences are flattened over the lanes (exclusive prefix of the cell
+    // sizes in LDS, binary search per incidence), so a crowded cell does not
+    // serialise on one lane
+    for (int w0 = 0; w0 < work; w0 += kWave) {
+      const int wi = w0 + lane;
+      int s = 0;
+      for (int z = 0; z < S; ++z) s += __shfl(incl, z, kWave) <= wi;  // slab holding item wi
+      s = min(s, kWave - 1);
+      const int sc0x = __shfl(c0[0], s, kWave), sc0y = __shfl(c0[1], s, kWave), sc0z = __shfl(c0[2], s, kWave);
+      const int sc1x = __shfl(c1[0], s, kWave), sc1y = __shfl(c1[1], s, kWave);
+      const int sstart = __shfl(incl - ncs, s, kWave);
+      int cs = 0, cn = 0;
+      if (wi < work) {
+        const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
+        const int li = wi - sstart;
+        const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+        const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
+        cs = cell_start[cell];
+        cn = cell_start[cell + 1] - cs;
       }
-      const int j = istart[w][lo_k] + (f - ipfx[w][lo_k]);
-      const int sl = islab[w][lo_k];
-      float lo[3], hi[3];
-      slab_box(tlo, thi, n, -eps + sl * dt, -eps + (sl + 1) * dt, margin, lo, hi);
-      const int M = items[j];
-      const float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1];
-      if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
-      const float4 nm = mbox[3 * (int64_t)M + 2];
-      // facing test with slack: the narrow phase takes the exact decision
-      if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
-      uint32_t h = ((uint32_t)M * 2654435761u) & (uint32_t)(tsz - 1);
-      int probe = 0;
-      for (; probe < tsz; ++probe) {
-        const int prev = atomicCAS(&set[w][h], -1, M);
-        if (prev == -1 || prev == M) break;
-        h = (h + 1) & (uint32_t)(tsz - 1);
+      int ci = cn;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int v = __shfl_up(ci, d, kWave);
+        if (lane >= d) ci += v;
       }
-      if (probe == tsz) full = true;
+      const int tot = __shfl(ci, kWave - 1, kWave);
+      wave_sync();
+      ipfx[w][lane] = ci - cn;
+      istart[w][lane] = cs;
+      islab[w][lane] = s;
+      wave_sync();
+      for (int f = lane; f < tot; f += kWave) {
+        int lo_k = 0, hi_k = kWave - 1;  // the last item whose prefix is <= f
+        while (lo_k < hi_k) {
+          const int mid = (lo_k + hi_k + 1) >> 1;
+          if (ipfx[w][mid] <= f) lo_k = mid;
+          else hi_k = mid - 1;
+        }
+        const int j = istart[w][lo_k] + (f - ipfx[w][lo_k]);
+        const int sl = islab[w][lo_k];
+        float lo[3], hi[3];
+        slab_box(tlo, thi, n, -eps + sl * dt, -eps + (sl + 1) * dt, margin, lo, hi);
+        const int M = items[j];
+        const float4 a = mbox[3 * (int64_t)M], b = mbox[3 * (int64_t)M + 1];
+        if (a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2]) continue;
+        const float4 nm = mbox[3 * (int64_t)M + 2];
+        // facing test with slack: the narrow phase takes the exact decision
+        if (n[0] * nm.x + n[1] * nm.y + n[2] * nm.z >= 1e-5f) continue;
+        uint32_t h = ((uint32_t)M * 2654435761u) & (uint32_t)(tsz - 1);
+        int probe = 0;
+        for (; probe < max_probe; ++probe) {
+          const int prev = atomicCAS(&set[w][h], -1, M);
+          if (prev == -1 || prev == M) break;
+          h = (h + 1) & (uint32_t)(tsz - 1);
+        }
+        if (probe == max_probe) full = true;
+      }
     }
+    if (!__any(full) || tsz == kQuerySet) break;
+    tsz = kQuerySet;
+    wave_sync();  // the small set's accesses are done before the full one is cleared
   }
   if (__any(full)) {
     if (lane == 0) {
