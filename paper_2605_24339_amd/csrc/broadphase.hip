@@ -283,8 +283,8 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
 
 constexpr int kQueryWaves = kThreads / kWave;
 constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS set)
-constexpr int kQuerySmall = 128;      // the first set a triangle tries
-constexpr int kQuerySmallProbe = 32;  // probes before it moves to the full set
+constexpr int kQuerySmall = 64;       // the first set a triangle tries
+constexpr int kQuerySmallProbe = 16;  // probes before it moves to the full set
 constexpr int kMaxSlabs = 64;
 
 // vertex box and unit normal of slave triangle t (float, grown outward)
