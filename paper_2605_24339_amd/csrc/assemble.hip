@@ -1221,10 +1221,18 @@ __global__ __launch_bounds__(kThreads) void k_row_pre(RowArgs<R> a, int4 *__rest
       const int64_t vid = slave ? row : row - a.Vs;
       sb = slave ? a.s_vt_off[vid] : a.m_vt_off[vid];
       se = slave ? a.s_vt_off[vid + 1] : a.m_vt_off[vid + 1];
-      for (int src = sb; src < se; ++src) {
-        const int t = (slave ? a.s_vt[src] : a.m_vt[src]) >> 2;
-        const int np = slave ? a.tri_npair[t] : a.mp_off[t + 1] - a.mp_off[t];
-        if (np > 0) n_ent += 3 + ((slave && a.kinematic) ? 0 : 3 * np);
+      // four incident triangles at a time, their loads in flight together
+      const int32_t *vt = slave ? a.s_vt : a.m_vt;
+      for (int s0 = sb; s0 < se; s0 += 4) {
+        int t[4], np[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] = s0 + k < se ? vt[s0 + k] >> 2 : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          np[k] = t[k] < 0 ? 0 : (slave ? a.tri_npair[t[k]] : a.mp_off[t[k] + 1] - a.mp_off[t[k]]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (np[k] > 0) n_ent += 3 + ((slave && a.kinematic) ? 0 : 3 * np[k]);
       }
     }
     if (n_ent == 0) {

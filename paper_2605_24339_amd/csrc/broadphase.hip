@@ -254,6 +254,13 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
                                                            int64_t total_cells, DevStatus *st) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Tm) return;
+  // the overflow is reported by thread 0 whatever its own triangle does
+  const int64_t total = cell_start[total_cells];
+  const bool fits = total <= cap_items;
+  if (!fits && t == 0) {
+    atomicMax(&st->need_items, (unsigned long long)total);
+    atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+  }
   int e = m_env[t];
   GridEnv g = grid[e];
   if (!g.valid) return;
@@ -265,20 +272,26 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
     c0[d] = cell_coord(g, lo[d], d);
     c1[d] = cell_coord(g, hi[d], d);
   }
-  int64_t base = env[e].cell0;
-  const int64_t total = cell_start[total_cells];
-  const bool fits = total <= cap_items;
-  if (!fits && t == 0) {
-    atomicMax(&st->need_items, (unsigned long long)total);
-    atomicCAS(&st->code, 0, GMCP_E_CAPACITY);
+  const int64_t base = env[e].cell0;
+  // the box's cells four at a time: their atomics in flight together
+  const int nx = c1[0] - c0[0] + 1, nxy = nx * (c1[1] - c0[1] + 1);
+  const int ncell = nxy * (c1[2] - c0[2] + 1);
+  for (int i0 = 0; i0 < ncell; i0 += 4) {
+    int64_t cell[4];
+    int slot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k < ncell ? i0 + k : i0;
+      const int x = c0[0] + i % nx, y = c0[1] + (i % nxy) / nx, z = c0[2] + i / nxy;
+      cell[k] = base + ((int64_t)z * g.ny + y) * g.nx + x;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      slot[k] = i0 + k < ncell ? cell_start[cell[k]] + atomicSub(&cell_cnt[cell[k]], 1) - 1 : -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (fits && slot[k] >= 0) items[slot[k]] = (int32_t)t;
   }
-  for (int z = c0[2]; z <= c1[2]; ++z)
-    for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) {
-        int64_t cell = base + ((int64_t)z * g.ny + y) * g.nx + x;
-        int slot = cell_start[cell] + atomicSub(&cell_cnt[cell], 1) - 1;
-        if (fits) items[slot] = (int32_t)t;
-      }
 }
 
 constexpr int kQueryWaves = kThreads / kWave;
