@@ -534,7 +534,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path; run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -3,7 +3,7 @@
 A per-vertex MLP maps (position, velocity, previous correction) to the
 correction d = x* - (x_t + dt v_t) of the coming step; the Newton solve then
 starts from x_t + dt v_t + d (after the same contact step-bound filter as
-the plain start) and its converged solution is the judge.  Forward,
+the plain start) and its converged solution measures the start's error.  Forward,
 backward, loss and Adam run in the library's kernels (matrix cores, bf16
 operands, float32 accumulation); this module holds parameters, feature
 scaling and the training loop.
