@@ -300,32 +300,6 @@ constexpr int kQuerySmall = 64;       // the first set a triangle tries
 constexpr int kQuerySmallProbe = 16;  // probes before it moves to the full set
 constexpr int kMaxSlabs = 64;
 
-// vertex box and unit normal of slave triangle t (float, grown outward)
-template <typename R>
-__device__ inline bool tri_frame(const R *xs, const int32_t *ts, int64_t t, float tlo[3], float thi[3], float n[3]) {
-  R p[3][3];
-  for (int j = 0; j < 3; ++j) {
-    int64_t v = ts[3 * t + j];
-    for (int d = 0; d < 3; ++d) p[j][d] = xs[3 * v + d];
-  }
-  R e1[3], e2[3];
-  for (int d = 0; d < 3; ++d) {
-    e1[d] = p[1][d] - p[0][d];
-    e2[d] = p[2][d] - p[0][d];
-  }
-  R N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-  R len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-  if (!(len > R(0))) return false;
-  for (int d = 0; d < 3; ++d) {
-    n[d] = (float)(N[d] / len);
-    float a = fminf(fminf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
-    float b = fmaxf(fmaxf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
-    tlo[d] = a - grow(a);
-    thi[d] = b + grow(b);
-  }
-  return true;
-}
-
 // box of the prism slab {p + t n : p in T, t0 <= t <= t1}
 __device__ inline void slab_box(const float tlo[3], const float thi[3], const float n[3], float t0, float t1,
                                 float margin, float lo[3], float hi[3]) {
@@ -370,11 +344,15 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
   float4 fr[3];  // the listed triangle's frame for the query kernel
   if (i < Ts) {
     t = s_order[i];
-    R e1[3], e2[3], s0[3];
+    R p[3][3], e1[3], e2[3];
+    for (int j = 0; j < 3; ++j) {
+      const int64_t v = ts[3 * t + j];
+      for (int d = 0; d < 3; ++d) p[j][d] = xs[3 * v + d];
+    }
+    const R *s0 = p[0];
     for (int d = 0; d < 3; ++d) {
-      s0[d] = xs[3 * (int64_t)ts[3 * t] + d];
-      e1[d] = xs[3 * (int64_t)ts[3 * t + 1] + d] - s0[d];
-      e2[d] = xs[3 * (int64_t)ts[3 * t + 2] + d] - s0[d];
+      e1[d] = p[1][d] - s0[d];
+      e2[d] = p[2][d] - s0[d];
     }
     const R c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
     const R len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
@@ -388,8 +366,17 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
       const int e = s_env[t];
       const GridEnv g = grid[e];
       const float eps = (float)env[e].dhat;
+      // the frame the query starts from: unit normal and vertex box (float,
+      // grown outward)
       float tlo[3], thi[3], n[3];
-      if (g.valid && tri_frame(xs, ts, t, tlo, thi, n)) {
+      for (int d = 0; d < 3; ++d) {
+        n[d] = (float)(c[d] / len);
+        const float lo_d = fminf(fminf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
+        const float hi_d = fmaxf(fmaxf((float)p[0][d], (float)p[1][d]), (float)p[2][d]);
+        tlo[d] = lo_d - grow(lo_d);
+        thi[d] = hi_d + grow(hi_d);
+      }
+      if (g.valid) {
         fr[0] = make_float4(tlo[0], tlo[1], tlo[2], __int_as_float((int)t));
         fr[1] = make_float4(thi[0], thi[1], thi[2], __int_as_float(e));
         fr[2] = make_float4(n[0], n[1], n[2], 0.0f);
