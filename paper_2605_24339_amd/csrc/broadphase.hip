@@ -273,17 +273,24 @@ __global__ __launch_bounds__(kThreads) void k_grid_insert(const float4 *__restri
     c1[d] = cell_coord(g, hi[d], d);
   }
   const int64_t base = env[e].cell0;
-  // the box's cells four at a time: their atomics in flight together
-  const int nx = c1[0] - c0[0] + 1, nxy = nx * (c1[1] - c0[1] + 1);
+  // the box's cells four at a time: their atomics in flight together (the
+  // cell coordinates stepped x-fastest, no divisions)
+  const int nxy = (c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1);
   const int ncell = nxy * (c1[2] - c0[2] + 1);
+  int x = c0[0], y = c0[1], z = c0[2];
   for (int i0 = 0; i0 < ncell; i0 += 4) {
     int64_t cell[4];
     int slot[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k < ncell ? i0 + k : i0;
-      const int x = c0[0] + i % nx, y = c0[1] + (i % nxy) / nx, z = c0[2] + i / nxy;
       cell[k] = base + ((int64_t)z * g.ny + y) * g.nx + x;
+      if (++x > c1[0]) {
+        x = c0[0];
+        if (++y > c1[1]) {
+          y = c0[1];
+          ++z;
+        }
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -299,6 +306,15 @@ constexpr int kQuerySet = 512;   // distinct candidates per slave triangle (LDS 
 constexpr int kQuerySmall = 64;       // the first set a triangle tries
 constexpr int kQuerySmallProbe = 16;  // probes before it moves to the full set
 constexpr int kMaxSlabs = 64;
+
+// a / b for 0 <= a and 1 <= b (both below 2^24): a float quotient, then
+// corrected to the exact integer one (a fraction of an integer division's cost)
+__device__ inline int div_small(int a, int b) {
+  int q = (int)__fdividef((float)a, (float)b);
+  while (q > 0 && q * b > a) --q;
+  while ((q + 1) * b <= a) ++q;
+  return q;
+}
 
 // box of the prism slab {p + t n : p in T, t0 <= t <= t1}
 __device__ inline void slab_box(const float tlo[3], const float thi[3], const float n[3], float t0, float t1,
@@ -397,14 +413,19 @@ __global__ __launch_bounds__(kThreads) void k_query_pre(const R *__restrict__ xs
             // the (y, z) rows of the box, 8 at a time so that their loads are
             // in flight together; a row's x-run of cells is contiguous
             const int ny = c1[1] - c0[1] + 1, nrow = ny * (c1[2] - c0[2] + 1);
+            int ry = 0, rz = 0;  // row r0 + k as (y, z) offsets, stepped (no divisions)
             for (int r0 = 0; r0 < nrow && !active; r0 += 8) {
               int32_t hi_s[8], lo_s[8];
 #pragma unroll
               for (int k = 0; k < 8; ++k) {
                 const int r = r0 + k;
                 hi_s[k] = lo_s[k] = 0;
+                const int64_t row = base + ((int64_t)(c0[2] + rz) * g.ny + c0[1] + ry) * g.nx;
+                if (++ry == ny) {
+                  ry = 0;
+                  ++rz;
+                }
                 if (r < nrow) {
-                  const int64_t row = base + ((int64_t)(c0[2] + r / ny) * g.ny + c0[1] + r % ny) * g.nx;
                   hi_s[k] = cell_start[row + c1[0] + 1];
                   lo_s[k] = cell_start[row + c0[0]];
                 }
@@ -563,7 +584,8 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
       if (wi < work) {
         const int nxr = sc1x - sc0x + 1, nyr = sc1y - sc0y + 1;
         const int li = wi - sstart;
-        const int x = sc0x + li % nxr, y = sc0y + (li / nxr) % nyr, zc = sc0z + li / (nxr * nyr);
+        const int q1 = div_small(li, nxr), q2 = div_small(q1, nyr);
+        const int x = sc0x + (li - q1 * nxr), y = sc0y + (q1 - q2 * nyr), zc = sc0z + q2;
         const int64_t cell = base + ((int64_t)zc * g.ny + y) * g.nx + x;
         cs = cell_start[cell];
         cn = cell_start[cell + 1] - cs;

@@ -309,14 +309,19 @@ __global__ __launch_bounds__(kThreads) void k_ccd_pre(const R *__restrict__ xs, 
           // the (y, z) rows of the box, 8 at a time (their loads in flight
           // together); a row's x-run of cells is contiguous
           const int ny = c1[1] - c0[1] + 1, nrow = ny * (c1[2] - c0[2] + 1);
+          int ry = 0, rz = 0;  // row r0 + k as (y, z) offsets, stepped (no divisions)
           for (int r0 = 0; r0 < nrow && !active; r0 += 8) {
             int32_t hi_s[8], lo_s[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               const int r = r0 + k;
               hi_s[k] = lo_s[k] = 0;
+              const int64_t row = base + ((int64_t)(c0[2] + rz) * g.ny + c0[1] + ry) * g.nx;
+              if (++ry == ny) {
+                ry = 0;
+                ++rz;
+              }
               if (r < nrow) {
-                const int64_t row = base + ((int64_t)(c0[2] + r / ny) * g.ny + c0[1] + r % ny) * g.nx;
                 hi_s[k] = cell_start[row + c1[0] + 1];
                 lo_s[k] = cell_start[row + c0[0]];
               }
