@@ -41,7 +41,7 @@ constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + IN * HID, OFF_W2 = OFF_B1 + HID,
                   OFF_B4 = OFF_W4 + HID * OUT, N_PARAMS = OFF_B4 + OUT;
 constexpr int ACT = 6 * HID;  // saved activations per row
 
-enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2 };
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_SILU_BWD = 3 };
 
 __device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
 __device__ inline float silu_grad(float z) {
@@ -53,12 +53,15 @@ __device__ inline float silu_grad(float z) {
 // A(m,k) = transA ? A[k*lda + m] : A[m*lda + k]; B(k,n) likewise.
 // Block tile 64 x 64 (four waves of 32 x 32), K step 32 (two MFMAs).
 // Split-K (EPI_STORE): block z handles k in [z*kc, (z+1)*kc) and writes
-// its partial product at C + z * split_stride.
+// its partial product at C + z * split_stride.  EPI_SILU_BWD multiplies the
+// product by silu'(Z) (Z [M][ldz], the layer's pre-activations): the
+// backward pass's dZ = (dH W^T) * silu'(Z) in the GEMM's epilogue.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const float *__restrict__ A, int lda, int transA,
                                                const float *__restrict__ B, int ldb, int transB, int M, int N, int K,
                                                int kc, const float *__restrict__ bias, float *__restrict__ C,
-                                               int ldc, float *__restrict__ C2, int64_t split_stride) {
+                                               int ldc, float *__restrict__ C2, int64_t split_stride,
+                                               const float *__restrict__ Z, int ldz) {
   __shared__ __bf16 As[64][32 + 8];
   __shared__ __bf16 Bs[32][64 + 8];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -101,6 +104,8 @@ __global__ __launch_bounds__(256) void k_gemm(const float *__restrict__ A, int l
       C[blockIdx.z * split_stride + (int64_t)m * ldc + n] = v;
     } else if (EPI == EPI_BIAS) {
       C[(int64_t)m * ldc + n] = v + bias[n];
+    } else if (EPI == EPI_SILU_BWD) {
+      C[(int64_t)m * ldc + n] = v * silu_grad(Z[(int64_t)m * ldz + n]);
     } else {
       float z = v + bias[n];
       C[(int64_t)m * ldc + n] = z;
@@ -127,16 +132,6 @@ __global__ void k_colsum_partial(const float *__restrict__ X, int64_t B, int ld,
   float s = 0.0f;
   for (int64_t r = r0; r < r1; ++r) s += X[r * ld + c];
   part[(int64_t)blockIdx.x * ncol + c] = s;
-}
-
-// dZ = dH * silu'(Z)   (all [B][ld], first 128 columns)
-__global__ void k_silu_bwd(const float *__restrict__ dH, int ldh, const float *__restrict__ Z, int ldz,
-                           float *__restrict__ dZ, int ldd, int64_t B) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B * HID) return;
-  int64_t r = i / HID;
-  int c = (int)(i % HID);
-  dZ[r * ldd + c] = dH[r * ldh + c] * silu_grad(Z[r * ldz + c]);
 }
 
 // dY = 2 (Y - T) / (B n_out) on the first n_out columns, 0 on the padding;
@@ -347,12 +342,13 @@ inline unsigned nb(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 
 template <int EPI>
 hipError_t gemm(hipStream_t s, const float *A, int lda, int tA, const float *B, int ldb, int tB, int M, int N, int K,
-                const float *bias, float *C, int ldc, float *C2, int splits = 1, int64_t split_stride = 0) {
+                const float *bias, float *C, int ldc, float *C2, int splits = 1, int64_t split_stride = 0,
+                const float *Z = nullptr, int ldz = 0) {
   int kc = (K + splits - 1) / splits;
   kc = (kc + 31) / 32 * 32;
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
   hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, s, A, lda, tA, B, ldb, tB, M, N, K, kc, bias, C, ldc, C2,
-                     split_stride);
+                     split_stride, Z, ldz);
   return hipGetLastError();
 }
 
@@ -457,31 +453,26 @@ int gmcp_mlp_backward(const float *params, const float *x, const float *act, con
     hipLaunchKernelGGL(k_reduce_split, dim3(1), dim3(HID), 0, s, cpart, (int)cblocks, (int64_t)ncol, db);
     e = hipGetLastError();
   };
-  // layer 4: Y = H3 W4 + b4
+  // layer 4: Y = H3 W4 + b4; each dZ of the layers below comes out of the
+  // GEMM with silu'(Z) applied in its epilogue (dA and dB alternate)
   wgrad(H3, ld, HID, dy, OUT, OUT, grad + OFF_W4);
   bgrad(dy, OUT, OUT, grad + OFF_B4);
-  if (e == hipSuccess) e = gemm<EPI_STORE>(s, dy, OUT, 0, P + OFF_W4, OUT, 1, (int)B, HID, OUT, nullptr, dA, HID, nullptr);
+  if (e == hipSuccess)
+    e = gemm<EPI_SILU_BWD>(s, dy, OUT, 0, P + OFF_W4, OUT, 1, (int)B, HID, OUT, nullptr, dB, HID, nullptr, 1, 0, Z3,
+                           ld);
   // layer 3
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_silu_bwd, dim3(nb(B * HID)), dim3(256), 0, s, dA, HID, Z3, ld, dB, HID, B);
-    e = hipGetLastError();
-  }
   wgrad(H2, ld, HID, dB, HID, HID, grad + OFF_W3);
   bgrad(dB, HID, HID, grad + OFF_B3);
-  if (e == hipSuccess) e = gemm<EPI_STORE>(s, dB, HID, 0, P + OFF_W3, HID, 1, (int)B, HID, HID, nullptr, dA, HID, nullptr);
+  if (e == hipSuccess)
+    e = gemm<EPI_SILU_BWD>(s, dB, HID, 0, P + OFF_W3, HID, 1, (int)B, HID, HID, nullptr, dA, HID, nullptr, 1, 0, Z2,
+                           ld);
   // layer 2
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_silu_bwd, dim3(nb(B * HID)), dim3(256), 0, s, dA, HID, Z2, ld, dB, HID, B);
-    e = hipGetLastError();
-  }
-  wgrad(H1, ld, HID, dB, HID, HID, grad + OFF_W2);
-  bgrad(dB, HID, HID, grad + OFF_B2);
-  if (e == hipSuccess) e = gemm<EPI_STORE>(s, dB, HID, 0, P + OFF_W2, HID, 1, (int)B, HID, HID, nullptr, dA, HID, nullptr);
+  wgrad(H1, ld, HID, dA, HID, HID, grad + OFF_W2);
+  bgrad(dA, HID, HID, grad + OFF_B2);
+  if (e == hipSuccess)
+    e = gemm<EPI_SILU_BWD>(s, dA, HID, 0, P + OFF_W2, HID, 1, (int)B, HID, HID, nullptr, dB, HID, nullptr, 1, 0, Z1,
+                           ld);
   // layer 1
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_silu_bwd, dim3(nb(B * HID)), dim3(256), 0, s, dA, HID, Z1, ld, dB, HID, B);
-    e = hipGetLastError();
-  }
   wgrad(x, IN, IN, dB, HID, HID, grad + OFF_W1);
   bgrad(dB, HID, HID, grad + OFF_B1);
   return e == hipSuccess ? GMCP_OK : GMCP_E_HIP;
