@@ -1299,13 +1299,13 @@ constexpr int kRowEnt = 512;     // contribution stash of heavy rows (light rows
 constexpr int kRowSrc = 32;
 
 // LDS bytes of one wave of k_rows: hash set (slots, compacted in place),
-// the incident-triangle table, and in PASS 1 the contribution stash - in
+// the incident-triangle table, the item marks of one round, and in PASS 1 the contribution stash - in
 // groups of three (a triangle's own vertices, or one pair's master
 // vertices: three distinct columns, the table index, three coefficients) -
 // and the incident triangles' normals; a multiple of 16 bytes
 template <typename R>
 constexpr size_t row_lds_wave(int slots, int pass, bool heavy, int light_bound) {
-  return ((size_t)slots * 4 + (size_t)8 * kRowSrc * 4 +
+  return ((size_t)slots * 4 + (size_t)8 * kRowSrc * 4 + (size_t)kWave * 4 +
           (pass == 1 ? (size_t)((heavy ? kRowEnt : light_bound) / 3 + 1) * (16 + 3 * sizeof(R)) +
                            (size_t)kRowSrc * 3 * sizeof(R)
                      : 0) +
@@ -1328,11 +1328,30 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
   int32_t *sco = stt + kRowSrc;
   int32_t *spb = sco + kRowSrc;
   int32_t *stv = spb + kRowSrc;  // master rows: the triangle's three vertex ids
+  int32_t *smk = stv + 3 * kRowSrc;  // per round of 64 items: the table entry whose items start at a lane
   const int gcap = ecap / 3 + 1;
-  int4 *egrp = reinterpret_cast<int4 *>(stv + 3 * kRowSrc);  // PASS 1 stash: three columns + table index,
+  int4 *egrp = reinterpret_cast<int4 *>(smk + kWave);  // PASS 1 stash: three columns + table index,
   R *ecoef = reinterpret_cast<R *>(egrp + gcap);          // three coefficients per group
   R *snrm = ecoef + 3 * gcap;                             // normals of the table's triangles
   if ((pass == 1 || pass == 3) && (int64_t)a.row_ptr[a.V] > a.cap_nnzb) return;
+
+  // the table entry owning item f0 + lane (the last entry whose item prefix
+  // is <= it): each entry with items marks the lane of its first item, a
+  // ballot of the marks gives the highest mark at or below each lane, and a
+  // lane before the round's first mark continues the previous round's last
+  // entry (carry) - two round trips instead of a five-step binary search
+  auto owner = [&](int f0, int first, int nit, int &carry) -> int {
+    wave_sync();  // the previous round's mark reads are done
+    smk[lane] = -1;
+    if (lane < kRowSrc && nit > 0 && first >= f0 && first < f0 + kWave) smk[first - f0] = lane;
+    wave_sync();
+    const int mk = smk[lane];
+    const uint64_t le = __ballot(mk >= 0) & ((2ull << lane) - 1);
+    int lo = __shfl(mk, le ? 63 - __builtin_clzll(le) : 0, kWave);
+    if (!le) lo = carry;
+    carry = __builtin_amdgcn_readlane(lo, kWave - 1);
+    return lo;
+  };
   // the waves walk the list of rows with contributions (k_row_pre)
   const int64_t nlist = *rcount;
   const int nw = blockDim.x / kWave;
@@ -1467,14 +1486,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
         spb[lane] = pb;
         for (int m = 0; m < 3; ++m) stv[3 * lane + m] = tv[m];
       }
-      wave_sync();
-      for (int f = lane; f < items; f += kWave) {
-        int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sip[mid] <= f) lo = mid;
-          else hi = mid - 1;
-        }
+      int carry = 0;
+      for (int f0 = 0; f0 < items; f0 += kWave) {
+        const int lo = owner(f0, iin - nit, nit, carry), f = f0 + lane;
+        if (f >= items) continue;
         const int j = f - sip[lo];
         if (j == 0) {
           for (int m = 0; m < 3; ++m) row_slot(key, tsz, (int32_t)(a.Vs + stv[3 * lo + m]), &full);
@@ -1630,14 +1645,10 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
       if (stash && np > 0)
         for (int d = 0; d < 3; ++d) snrm[3 * lane + d] = a.tri_nrm[3 * (int64_t)t + d];
     }
-    wave_sync();
-    for (int f = lane; f < items; f += kWave) {
-      int lo = 0, hi = kRowSrc - 1;  // the last table entry whose item prefix is <= f
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sip[mid] <= f) lo = mid;
-        else hi = mid - 1;
-      }
+    int carry = 0;
+    for (int f0 = 0; f0 < items; f0 += kWave) {
+      const int lo = owner(f0, iin - nit, nit, carry), f = f0 + lane;
+      if (f >= items) continue;
       const int j = f - sip[lo], tt = stt[lo], c = sco[lo];
       int32_t col[3];
       R cf[3];

@@ -501,7 +501,7 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
                                                      int32_t *__restrict__ cand_blk, DevStatus *st) {
   __shared__ int32_t set[kQueryWaves][kQuerySet];
   __shared__ int32_t dense[kQueryWaves][kQuerySet];
-  __shared__ int32_t ipfx[kQueryWaves][kWave], istart[kQueryWaves][kWave], islab[kQueryWaves][kWave];
+  __shared__ int2 imark[kQueryWaves][kWave];  // per round of 64 incidences: where each item's incidences start
   __shared__ int blk_req;  // candidates requested by this block's triangles (LDS atomics)
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   // (blocks take list entries in dispatch order: an XCD-by-XCD mapping of
@@ -596,20 +596,33 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
         if (lane >= d) ci += v;
       }
       const int tot = __shfl(ci, kWave - 1, kWave);
-      wave_sync();
-      ipfx[w][lane] = ci - cn;
-      istart[w][lane] = cs;
-      islab[w][lane] = s;
-      wave_sync();
-      for (int f = lane; f < tot; f += kWave) {
-        int lo_k = 0, hi_k = kWave - 1;  // the last item whose prefix is <= f
-        while (lo_k < hi_k) {
-          const int mid = (lo_k + hi_k + 1) >> 1;
-          if (ipfx[w][mid] <= f) lo_k = mid;
-          else hi_k = mid - 1;
+      const int pfx = ci - cn;  // the lane's first incidence
+      // incidences 64 per round, one per lane; the owner of incidence f is
+      // the item whose range [pfx, pfx + cn) holds it: every item with
+      // incidences marks the lane of its first one in LDS (its cell offset
+      // less its prefix, and its slab), a ballot of the marks gives the
+      // highest mark at or below each lane, and a lane before the round's
+      // first mark continues the previous round's last item - two round
+      // trips instead of a six-step binary search over the prefixes
+      int carry_off = 0, carry_sl = 0;
+      for (int f0 = 0; f0 < tot; f0 += kWave) {
+        wave_sync();  // the previous round's mark reads are done
+        imark[w][lane] = make_int2(0, -1);
+        if (cn > 0 && pfx >= f0 && pfx < f0 + kWave) imark[w][pfx - f0] = make_int2(cs - pfx, s);
+        wave_sync();
+        const int2 mk = imark[w][lane];
+        const uint64_t le = __ballot(mk.y >= 0) & ((2ull << lane) - 1);  // marks at lanes 0..lane
+        const int pos = le ? 63 - __builtin_clzll(le) : 0;
+        int off = __shfl(mk.x, pos, kWave), sl = __shfl(mk.y, pos, kWave);
+        if (!le) {
+          off = carry_off;
+          sl = carry_sl;
         }
-        const int j = istart[w][lo_k] + (f - ipfx[w][lo_k]);
-        const int sl = islab[w][lo_k];
+        carry_off = __builtin_amdgcn_readlane(off, kWave - 1);  // uniform: scalar registers
+        carry_sl = __builtin_amdgcn_readlane(sl, kWave - 1);
+        const int f = f0 + lane;
+        if (f >= tot) continue;
+        const int j = off + f;
         float lo[3], hi[3];
         slab_box(tlo, thi, n, -eps + sl * dt, -eps + (sl + 1) * dt, margin, lo, hi);
         const int M = items[j];
