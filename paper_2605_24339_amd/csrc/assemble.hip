@@ -1472,11 +1472,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
           for (int m = 0; m < 3; ++m) tv[m] = a.tm[3 * (int64_t)t + m];
       }
       const int nit = np > 0 ? 1 + np : 0;
-      int iin = nit;
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int vi = __shfl_up(iin, d, kWave);
-        if (lane >= d) iin += vi;
-      }
+      const int iin = wave_incl_add(nit);
       const int items = __shfl(iin, kWave - 1, kWave);
       wave_sync();  // the previous chunk's table reads are done
       if (lane < kRowSrc) {
@@ -1626,14 +1622,7 @@ __global__ __launch_bounds__(kWave *kRowWaves) void k_rows(RowArgs<R> a, int slo
     }
     const int nit = np > 0 ? 1 + (a.kinematic ? 0 : np) : 0;
     const int nen = np > 0 ? 3 + (a.kinematic ? 0 : 3 * np) : 0;
-    int iin = nit, ein = nen;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int vi = __shfl_up(iin, d, kWave), ve = __shfl_up(ein, d, kWave);
-      if (lane >= d) {
-        iin += vi;
-        ein += ve;
-      }
-    }
+    const int iin = wave_incl_add(nit), ein = wave_incl_add(nen);
     const int items = __shfl(iin, kWave - 1, kWave), ents = __shfl(ein, kWave - 1, kWave);
     wave_sync();  // the previous chunk's table reads are done
     if (lane < kRowSrc) {

@@ -551,11 +551,7 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
       ncs = (c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
     }
   }
-  int incl = ncs;
-  for (int d = 1; d < kWave; d <<= 1) {
-    int v = __shfl_up(incl, d, kWave);
-    if (lane >= d) incl += v;
-  }
+  const int incl = wave_incl_add(ncs);
   const int work = __shfl(incl, kWave - 1, kWave);
   const int64_t base = env[e].cell0;
   // the candidate set starts small (most triangles have a few candidates:
@@ -590,11 +586,7 @@ __device__ __forceinline__ void query_body(const R *__restrict__ xs, const int32
         cs = cell_start[cell];
         cn = cell_start[cell + 1] - cs;
       }
-      int ci = cn;
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int v = __shfl_up(ci, d, kWave);
-        if (lane >= d) ci += v;
-      }
+      const int ci = wave_incl_add(cn);
       const int tot = __shfl(ci, kWave - 1, kWave);
       const int pfx = ci - cn;  // the lane's first incidence
       // incidences 64 per round, one per lane; the owner of incidence f is

@@ -301,4 +301,21 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP lane moves
+// (VALU operations, no LDS round trips): shifts by 1, 2, 4 and 8 lanes
+// within each row of 16 scan the rows; then the last lane of row 0 is added
+// to row 1 and that of row 2 to row 3 (row broadcast 15, rows 1 and 3
+// enabled), then the last lane of row 1 to rows 2 and 3 (row broadcast 31,
+// rows 2 and 3 enabled).  A lane whose source is outside its row, or whose
+// row is not enabled, adds 0.  Every lane of the wave must be active.
+__device__ inline int wave_incl_add(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 }  // namespace gmcp
