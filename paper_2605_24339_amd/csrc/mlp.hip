@@ -114,24 +114,44 @@ __global__ __launch_bounds__(256) void k_gemm(const float *__restrict__ A, int l
   }
 }
 
-// out[i] = sum_s part[s][i] (fixed order)
-__global__ void k_reduce_split(const float *__restrict__ part, int S, int64_t n, float *__restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// out[i] = sum_s part[s][i], 64 outputs per block of 1024 threads: thread
+// group g (of 16) adds the partials s = g, g + 16, ... in that order, then
+// the 16 group sums are added in group order (a fixed order, so runs agree
+// bitwise; sixteen short chains of loads instead of one long one)
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(kWave *kRedGroups) void k_reduce_split(const float *__restrict__ part, int S, int64_t n,
+                                                                     float *__restrict__ out) {
+  __shared__ float red[kRedGroups][kWave];
+  const int e = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
+  const int64_t i = (int64_t)blockIdx.x * kWave + e;
   float s = 0.0f;
-  for (int z = 0; z < S; ++z) s += part[z * n + i];
-  out[i] = s;
+  if (i < n)
+    for (int z = g; z < S; z += kRedGroups) s += part[(int64_t)z * n + i];
+  red[g][e] = s;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float t = 0.0f;
+    for (int k = 0; k < kRedGroups; ++k) t += red[k][e];
+    out[i] = t;
+  }
 }
 
-// column sums of X [B][ld] (first ncol columns) into out [ncol], two levels
-__global__ void k_colsum_partial(const float *__restrict__ X, int64_t B, int ld, int ncol, int rows_per,
-                                 float *__restrict__ part) {
-  int c = threadIdx.x;
-  if (c >= ncol) return;
-  int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = min(B, r0 + rows_per);
+// column sums of X [B][ld] (the first ncol <= 128 columns) over chunks of
+// rows_per rows, one chunk per block of 256 threads: thread (h, c) adds
+// column c over the chunk's rows h, h + 2, ... in order, and the two halves
+// are added in LDS (fixed order); part [chunks][ncol]
+constexpr int kColRows = 64;  // rows per chunk
+__global__ __launch_bounds__(2 * HID) void k_colsum_partial(const float *__restrict__ X, int64_t B, int ld, int ncol,
+                                                             int rows_per, float *__restrict__ part) {
+  __shared__ float half[HID];
+  const int c = threadIdx.x & (HID - 1), h = threadIdx.x / HID;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = min(B, r0 + rows_per);
   float s = 0.0f;
-  for (int64_t r = r0; r < r1; ++r) s += X[r * ld + c];
-  part[(int64_t)blockIdx.x * ncol + c] = s;
+  if (c < ncol)
+    for (int64_t r = r0 + h; r < r1; r += 2) s += X[r * ld + c];
+  if (h == 1) half[c] = s;
+  __syncthreads();
+  if (h == 0 && c < ncol) part[(int64_t)blockIdx.x * ncol + c] = s + half[c];
 }
 
 // dY = 2 (Y - T) / (B n_out) on the first n_out columns, 0 on the padding;
@@ -391,7 +411,7 @@ size_t gmcp_mlp_work_bytes(int64_t B) {
   int S = splits_for(B);
   // two [B][128] gradient buffers, split partials for the largest weight,
   // column-sum partials, loss partials
-  return sizeof(float) * ((size_t)2 * B * HID + (size_t)S * HID * HID + (size_t)((B + 255) / 256 + 1) * HID +
+  return sizeof(float) * ((size_t)2 * B * HID + (size_t)S * HID * HID + (size_t)((B + kColRows - 1) / kColRows + 1) * HID +
                           (size_t)(B * OUT + 255) / 256 + 64);
 }
 
@@ -430,7 +450,7 @@ int gmcp_mlp_backward(const float *params, const float *x, const float *act, con
   float *dB = dA + (size_t)B * HID;          // [B][128]
   float *part = dB + (size_t)B * HID;        // [S][128][128]
   float *cpart = part + (size_t)S * HID * HID;
-  const int rows_per = 256;
+  const int rows_per = kColRows;
   const unsigned cblocks = (unsigned)((B + rows_per - 1) / rows_per);
   const float *Z1 = act, *H1 = act + HID, *Z2 = act + 2 * HID, *H2 = act + 3 * HID, *Z3 = act + 4 * HID,
               *H3 = act + 5 * HID;
@@ -442,15 +462,16 @@ int gmcp_mlp_backward(const float *params, const float *x, const float *act, con
       e = gemm<EPI_STORE>(s, Hin, ldh, 1, dZ, ldz, 0, fin, fout, (int)B, nullptr, part, fout, nullptr, S,
                           (int64_t)fin * fout);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_reduce_split, dim3(nb((int64_t)fin * fout)), dim3(256), 0, s, part, S,
-                         (int64_t)fin * fout, dW);
+      hipLaunchKernelGGL(k_reduce_split, dim3(nb((int64_t)fin * fout, kWave)), dim3(kWave * kRedGroups), 0, s, part,
+                         S, (int64_t)fin * fout, dW);
       e = hipGetLastError();
     }
   };
   auto bgrad = [&](const float *dZ, int ldz, int ncol, float *db) {
     if (e != hipSuccess) return;
-    hipLaunchKernelGGL(k_colsum_partial, dim3(cblocks), dim3(HID), 0, s, dZ, B, ldz, ncol, rows_per, cpart);
-    hipLaunchKernelGGL(k_reduce_split, dim3(1), dim3(HID), 0, s, cpart, (int)cblocks, (int64_t)ncol, db);
+    hipLaunchKernelGGL(k_colsum_partial, dim3(cblocks), dim3(2 * HID), 0, s, dZ, B, ldz, ncol, rows_per, cpart);
+    hipLaunchKernelGGL(k_reduce_split, dim3(nb(ncol, kWave)), dim3(kWave * kRedGroups), 0, s, cpart, (int)cblocks,
+                       (int64_t)ncol, db);
     e = hipGetLastError();
   };
   // layer 4: Y = H3 W4 + b4; each dZ of the layers below comes out of the
