@@ -6,6 +6,11 @@
 * the quadratic form 1/2 u^T K u equals the element-by-element energy;
 * rigid translations and infinitesimal rotations are in the null space of K;
 * K u equals central differences of the energy;
+* the energy of a simple shear, a uniform dilation and a uniaxial strain
+  equals the volume times G gamma^2 / 2, 9 K e^2 / 2 and M e^2 / 2 with
+  the engineering moduli of an isotropic solid (shear G = E / (2 (1 + nu)),
+  bulk K = E / (3 (1 - 2 nu)), P-wave M = E (1 - nu) / ((1 + nu) (1 - 2 nu))),
+  which pins the Lame parameters the energy is written with;
 * the lumped mass adds up to rho times the volume;
 * with the indenter out of reach, the implicit step solves the linear
   system M (x - x_tilde)/dt^2 + K (x - X) = 0 on the free vertices.
@@ -40,6 +45,23 @@ def test_patch_test_affine_field():
     interior = np.all((X > lo + 1e-12) & (X < hi - 1e-12), axis=1)
     assert interior.sum() > 0
     assert np.abs(f[interior]).max() < 1e-12 * np.abs(f).max()
+
+
+def test_energy_matches_engineering_moduli():
+    X, tets, top, bottom = _block()
+    vol = (3e-3) * (3e-3) * (2e-3)
+    for E, nu in ((3e5, 0.45), (2e11, 0.3), (1e6, 0.0)):
+        G = E / (2.0 * (1.0 + nu))
+        K = E / (3.0 * (1.0 - 2.0 * nu))
+        Mp = E * (1.0 - nu) / ((1.0 + nu) * (1.0 - 2.0 * nu))
+        g, e = 2e-3, 1e-3
+        shear = X.copy()
+        shear[:, 0] += g * X[:, 1]                       # u_x = gamma y
+        dil = X * (1.0 + e)                              # u = e X
+        uni = X.copy()
+        uni[:, 2] *= 1.0 + e                             # u_z = e z
+        for x, want in ((shear, G * g * g / 2), (dil, 9.0 * K * e * e / 2), (uni, Mp * e * e / 2)):
+            assert abs(fem.elastic_energy(X, tets, E, nu, x) / (vol * want) - 1) < 1e-12
 
 
 def test_rigid_modes_in_null_space():
