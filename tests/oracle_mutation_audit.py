@@ -170,6 +170,66 @@ MUTATIONS = [
     ('py stroud weight', 'oracle/rule.py',
      'wu = wj / 4.0',
      'wu = wj / 2.0', 0),
+    ('ploss dp drops gamma', 'oracle/gmcp_oracle.c',
+     'dp = -kappa * gam * ora_barrier_d2(g, eps);',
+     'dp = -kappa * ora_barrier_d2(g, eps);', 0),
+    ('ploss slave sign', 'oracle/gmcp_oracle.c',
+     '+= r * dp * (-bs[a]) * n[d];',
+     '+= r * dp * (bs[a]) * n[d];', 0),
+    ('ploss ddelta', 'oracle/gmcp_oracle.c',
+     'dLddelta[k] = act ? r * dp : 0.0;',
+     'dLddelta[k] = act ? r : 0.0;', 0),
+    ('hvp master index', 'oracle/gmcp_oracle.c',
+     'dot += bm[j] * v_dot(n, vx + 3 * ((int64_t)Vs + tm[3 * M[k] + j]));',
+     'dot += bm[j] * v_dot(n, vx + 3 * ((int64_t)Vs + tm[3 * M[k] + (j + 1) % 3]));', 0),
+    ('hvp vd dropped', 'oracle/gmcp_oracle.c',
+     '    if (vd) dot += vd[k];\n',
+     '', 0),
+    ('hvp slave sign', 'oracle/gmcp_oracle.c',
+     'out_x[3 * (int64_t)ts[3 * T + a] + d] += s * (-bs[a]) * n[d];',
+     'out_x[3 * (int64_t)ts[3 * T + a] + d] += s * (bs[a]) * n[d];', 0),
+    ('swept count pad', 'oracle/gmcp_oracle.c',
+     'lo[d] = l - (pad_rel * fabs(l) + pad_abs);',
+     'lo[d] = l;', 0),
+    ('swept count end', 'oracle/gmcp_oracle.c',
+     'double e = p + (b0 * dA[d] + xi * dB[d] + eta * dC[d]);',
+     'double e = p + (b0 * dA[d] + xi * dB[d] + xi * dC[d]);', 0),
+    ('ccd swept dp', 'oracle/gmcp_oracle.c',
+     'dp[d] = b0 * dA[d] + xi * dB[d] + eta * dC[d];',
+     'dp[d] = b0 * dA[d] + xi * dB[d];', 0),
+    ('sample geom point', 'oracle/gmcp_oracle.c',
+     'p[d] = s0[d] + rule[3 * q] * e1[d] + rule[3 * q + 1] * e2[d];',
+     'p[d] = s0[d] + rule[3 * q + 1] * e1[d] + rule[3 * q] * e2[d];', 0),
+    ('slave normal orientation', 'oracle/gmcp_oracle.c',
+     'v_cross(e1, e2, cr);',
+     'v_cross(e2, e1, cr);', 0),
+    ('py edge weight length', 'oracle/mortar.py',
+     'L * (t1 - t0) * wj',
+     '(t1 - t0) * wj', 0),
+    ('py edge gap', 'oracle/mortar.py',
+     'float((1.0 - eta) * ha + eta * hb)',
+     'float(eta * ha + (1.0 - eta) * hb)', 0),
+    ('py point strictly inside', 'oracle/mortar.py',
+     'if y[0] > 0.0 and y[1] > 0.0 and 1.0 - y[0] - y[1] > 0.0:',
+     'if y[0] > 0.0 and y[1] > 0.0:', 0),
+    ('py mortar linear 0.9', 'oracle/mortar.py',
+     'a = min(a, 0.9 * s.g / (-gd))',
+     'a = min(a, s.g / (-gd))', 0),
+    ('py mortar linear master', 'oracle/mortar.py',
+     'gd += s.n @ (s.bm @ dxm[s.mv])',
+     'gd -= s.n @ (s.bm @ dxm[s.mv])', 0),
+    ('py weights factor', 'oracle/__init__.py',
+     'return (2.0 * area[:, None] * P.rule[None, :, 2]).ravel()',
+     'return (area[:, None] * P.rule[None, :, 2]).ravel()', 0),
+    ('py mass quarter', 'oracle/fem.py',
+     'rho * vol / 4.0',
+     'rho * vol / 3.0', 0),
+    ('py inertia dt2', 'oracle/fem.py',
+     'g = (self.m[:, None] * dv / dt2).ravel() + Ku',
+     'g = (self.m[:, None] * dv / self.dt).ravel() + Ku', 0),
+    ('py stress mu', 'oracle/fem.py',
+     '+ 2.0 * mu * eps',
+     '+ mu * eps', 0),
 ]
 
 
