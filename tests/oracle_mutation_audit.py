@@ -1,5 +1,5 @@
 """Mutation audit of the oracle's pins (test infrastructure; run by hand on
-the CPU, not collected by pytest: about 30 minutes).
+the CPU, not collected by pytest: about 45 minutes).
 
     python tests/oracle_mutation_audit.py [name-substring ...]
 

@@ -174,3 +174,37 @@ def test_swept_count_brute_force_tiny():
     assert oracle.ccd_step(P, nr.M, dxs, dxm).n_swept == brute
     assert oracle.swept_count(P, dxs, dxm, pad_rel=1e-3, pad_abs=1e-5) >= brute
     assert oracle.swept_count(P, dxs, dxm, pad_abs=1.0) == len(pts) * tm.shape[0]
+
+
+@pytest.mark.parametrize("seed", [3, 5, 8])
+def test_swept_count_brute_force_deforming(seed):
+    """Exact swept-pair counts on denser scenes whose vertices move
+    independently (each sample path depends on all three of its triangle's
+    vertex motions), with and without an absolute box margin: a margin d on
+    both boxes makes them overlap when every axis gap is at most 2 d."""
+    rng = np.random.default_rng(seed)
+    from gen import meshes
+    xs, ts = meshes.pad(6, 2e-3)
+    xm = rng.uniform(-1.2e-3, 1.2e-3, size=(30, 3))
+    xm[:, 2] = rng.uniform(5e-5, 4e-4, size=30)
+    tm = rng.integers(0, 30, size=(40, 3))
+    tm = tm[(tm[:, 0] != tm[:, 1]) & (tm[:, 1] != tm[:, 2]) & (tm[:, 0] != tm[:, 2])]
+    dxs = rng.uniform(-3e-4, 3e-4, size=xs.shape)
+    dxm = rng.uniform(-3e-4, 3e-4, size=xm.shape)
+    P = oracle.Problem(xs, ts, xm, tm, rule_n=3)
+    boxes = []
+    for T in range(ts.shape[0]):
+        for q in range(P.nq):
+            xi, eta = P.rule[q, 0], P.rule[q, 1]
+            b = np.array([1 - xi - eta, xi, eta])
+            p0 = b @ xs[ts[T]]
+            p1 = p0 + b @ dxs[ts[T]]
+            boxes.append((np.minimum(p0, p1), np.maximum(p0, p1)))
+    tri = [(np.concatenate([xm[t], xm[t] + dxm[t]]).min(axis=0), np.concatenate([xm[t], xm[t] + dxm[t]]).max(axis=0))
+           for t in tm]
+    for pad in (0.0, 2e-5):
+        brute = sum(bool(np.all(plo - pad <= hi + pad) and np.all(lo - pad <= phi + pad))
+                    for lo, hi in tri for plo, phi in boxes)
+        assert brute > 50
+        assert oracle.swept_count(P, dxs, dxm, pad_abs=pad) == brute
+        assert oracle.swept_count(P, dxs, dxm, pad_abs=pad, use_grid=False) == brute

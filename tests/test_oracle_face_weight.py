@@ -21,7 +21,11 @@ formula:
   the nearer one, at exactly its gap (the closest opposing hit);
 * Eq. (adaptive_eps): a selected sample contributes if and only if its gap
   is below min(0.9 g_ref, dhat), checked just inside and just outside the
-  boundary, in the selection and in the assembly.
+  boundary, in the selection and in the assembly;
+* with partial face weights, central differences in the per-sample gap
+  offsets pin the pressure loss's gradient and the offset part of the joint
+  Hessian-vector product (the derivative of the assembly's dE/ddelta and
+  gradient along one offset).
 """
 import numpy as np
 import pytest
@@ -210,3 +214,46 @@ def test_adaptive_support_radius_boundary():
     k = int(np.nonzero(capped)[0][0])
     A0 = oracle.assemble(P, nr.M)
     assert A.Ek[k] == A0.Ek[k]
+
+
+def _partial(P, nr, count=12):
+    act = np.nonzero(nr.M >= 0)[0]
+    mb = nr.bm[act].min(axis=1)
+    part = act[(mb > 0.0) & (mb < DELTA_T)]
+    return part[np.linspace(0, len(part) - 1, count).astype(int)]
+
+
+def test_pressure_loss_offset_gradient_with_partial_face_weight(curved):
+    P, nr, A = curved
+    rng = np.random.default_rng(6)
+    pt = A.press + rng.normal(size=P.Ns) * np.abs(A.press).max() * 0.1
+    delta = rng.uniform(-1e-6, 1e-6, size=P.Ns) * (nr.M >= 0)
+    _, _, dLdd = oracle.pressure_loss(P, nr.M, pt, delta)
+    h = 1e-11
+    scale = np.abs(dLdd).max()
+    for k in _partial(P, nr):
+        dp, dm = delta.copy(), delta.copy()
+        dp[k] += h
+        dm[k] -= h
+        fd = (oracle.pressure_loss(P, nr.M, pt, dp)[0] - oracle.pressure_loss(P, nr.M, pt, dm)[0]) / (2 * h)
+        assert abs(fd - dLdd[k]) <= 1e-5 * scale, (k, fd, dLdd[k])
+
+
+def test_joint_hvp_offset_part(curved):
+    # H [0; e_k] = (d/ddelta_k) [dE/dx; dE/ddelta]: the change of the
+    # gradient and of c1 = dE/ddelta under a small offset of sample k's gap
+    P, nr, A = curved
+    h = 1e-10
+    vx = np.zeros((P.Vs + P.Vm, 3))
+    for k in _partial(P, nr, 6):
+        vd = np.zeros(P.Ns)
+        vd[k] = 1.0
+        ox, od = oracle.hvp(P, nr.M, A.c2, vx, vd)
+        dp, dm = np.zeros(P.Ns), np.zeros(P.Ns)
+        dp[k], dm[k] = h, -h
+        Ap, Am = oracle.assemble(P, nr.M, delta_gap=dp, hessian=False), oracle.assemble(P, nr.M, delta_gap=dm, hessian=False)
+        fd_d = (Ap.c1 - Am.c1) / (2 * h)
+        fd_x = (Ap.grad - Am.grad) / (2 * h)
+        assert abs(od[k] - fd_d[k]) <= 1e-5 * abs(fd_d[k]) and od[k] > 0.0, (k, od[k], fd_d[k])
+        assert np.all(od[np.arange(P.Ns) != k] == 0.0)
+        assert np.allclose(ox, fd_x, rtol=0, atol=1e-5 * np.abs(fd_x).max()), k

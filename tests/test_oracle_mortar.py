@@ -2,8 +2,9 @@
 samples, Sec. 4.2): the clipping against hand-computed polygons, exact
 overlap areas and exact integrals of linear gaps for flat punches (which
 whole-triangle samples only approximate), the projection property of every
-sample, and the gradient against finite differences of the frozen-sample
-energy."""
+sample, the gradient against finite differences of the frozen-sample
+energy, and Eq. (ccd) over clipped samples against its closed form for
+flat surfaces closing along the normal."""
 import math
 
 import numpy as np
@@ -222,3 +223,23 @@ def test_reference_gaps_per_slave_triangle_closed_form():
     # without reference gaps every triangle has the full radius
     O0 = mortar.assemble(P, mortar.samples(P))
     assert abs(O0.energy / (P.kappa * area.sum() * oracle.barrier(g0, P.dhat)) - 1) <= 1e-10
+
+
+def test_mortar_linear_step_closed_form():
+    """Flat punch at the uniform gap g0, every clipped sample active: a
+    closing speed v along the normal (the master moving down, the slave up,
+    or both) gives Eq. (ccd)'s bound 0.9 g0 / v for every sample; moving
+    apart gives no bound."""
+    P, w = _punch_problem(1.4e-2)
+    act = mortar.assemble(P, mortar.samples(P)).active
+    assert len(act) > 0
+    g0 = 3e-4
+    zs, zm = np.zeros_like(P.xs), np.zeros_like(P.xm)
+    down = zm.copy()
+    down[:, 2] = -1e-4
+    up = zs.copy()
+    up[:, 2] = 5e-5
+    assert abs(mortar.linear_step(P, act, zs, down) / (0.9 * g0 / 1e-4) - 1) < 1e-12
+    assert abs(mortar.linear_step(P, act, up, zm) / (0.9 * g0 / 5e-5) - 1) < 1e-12
+    assert abs(mortar.linear_step(P, act, up, down) / (0.9 * g0 / 1.5e-4) - 1) < 1e-12
+    assert mortar.linear_step(P, act, -up, -down) == np.inf
