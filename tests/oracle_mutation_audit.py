@@ -1,5 +1,5 @@
 """Mutation audit of the oracle's pins (test infrastructure; run by hand on
-the CPU, not collected by pytest: about 45 minutes).
+the CPU, not collected by pytest: about 50 minutes).
 
     python tests/oracle_mutation_audit.py [name-substring ...]
 
@@ -15,7 +15,9 @@ Expected survivors, each a change that keeps what the pins can fix:
 "no psd clamp" (B'' > 0 on (0, eps), so the clamp never acts on a face
 sample), "accd mean" and "accd later step" (other shifts and step
 fractions of additive CCD still give a conservative time of impact, the
-property pinned against exact times)."""
+property pinned against exact times), and "py armijo sign" (it only
+changes which step lengths the oracle's Newton line search accepts when a
+full step raises the energy, which the pinned scenes never take)."""
 import os
 import shutil
 import subprocess
@@ -230,6 +232,39 @@ MUTATIONS = [
     ('py stress mu', 'oracle/fem.py',
      '+ 2.0 * mu * eps',
      '+ mu * eps', 0),
+    ('grid cell range', 'oracle/gmcp_oracle.c',
+     'c1[d] = clampi((int64_t)floor((hi[d] - g->lo[d]) / g->h), 0, g->nc[d] - 1);',
+     'c1[d] = clampi((int64_t)floor((hi[d] - g->lo[d]) / g->h) - 1, 0, g->nc[d] - 1);', 0),
+    ('grid box test', 'oracle/gmcp_oracle.c',
+     'if (a[0] > hi[0] || b[0] < lo[0] || a[1] > hi[1] || b[1] < lo[1] || a[2] > hi[2] || b[2] < lo[2])\n            continue;\n          if (cnt < cap)',
+     'if (a[0] > hi[0] || b[0] < lo[0] || a[1] > hi[1] || b[1] < lo[1])\n            continue;\n          if (cnt < cap)', 0),
+    ('py newton bound ignored', 'oracle/fem.py',
+     'alpha = min(1.0, step_bound(P, nr, A, d))',
+     'alpha = 1.0', 0),
+    ('py armijo sign', 'oracle/fem.py',
+     'if En <= E0 + armijo * alpha * slope or',
+     'if En <= E0 - armijo * alpha * slope or', 0),
+    ('py mlp skip activation', 'oracle/mlp.py',
+     'Z2 = H1 @ w["W2"] + w["b2"]',
+     'Z2 = Z1 @ w["W2"] + w["b2"]', 0),
+    ('py adam m', 'oracle/mlp.py',
+     'm = b1 * m + (1 - b1) * g',
+     'm = b1 * m + g', 0),
+    ('py weights rest areas', 'oracle/__init__.py',
+     'area = rest_area(P.xs_rest, P.ts)\n    return (2.0',
+     'area = rest_area(P.xs, P.ts)\n    return (2.0', 0),
+    ('py assemble rest areas', 'oracle/__init__.py',
+     '    area = rest_area(P.xs_rest, P.ts)\n    Ek, c1, c2, pr',
+     '    area = rest_area(P.xs, P.ts)\n    Ek, c1, c2, pr', 0),
+    ('py mortar rest areas', 'oracle/mortar.py',
+     'area = oracle.rest_area(P.xs_rest, P.ts)',
+     'area = oracle.rest_area(P.xs, P.ts)', 0),
+    ('py dual edge clip', 'oracle/dualmesh.py',
+     't = np.clip(((p - s0) * e).sum(1) / (e * e).sum(1), 0.0, 1.0)',
+     't = ((p - s0) * e).sum(1) / (e * e).sum(1)', 0),
+    ('py edge gauss weights', 'oracle/mortar.py',
+     'xg, wg = (xg + 1.0) / 2.0, wg / 2.0',
+     'xg, wg = (xg + 1.0) / 2.0, wg', 0),
 ]
 
 

@@ -89,6 +89,28 @@ def test_weights_sum_to_tactile_area():
     assert abs(oracle.weights(P2).sum() / tot - 1) < 1e-13
 
 
+def test_weights_come_from_the_rest_mesh():
+    """A pad stretched in its plane by 1.3 (still flat, still under the
+    punch at the same gap) keeps its rest weights: they sum to the rest
+    area, the whole-triangle energy is kappa B(g0) times the rest area, and
+    so are the clipped mortar samples' weights and energy."""
+    from oracle import mortar
+    g0 = 3e-4
+    w, P0 = _punch(g0)
+    xs = P0.xs.copy()
+    xs[:, 0] *= 1.3
+    P = oracle.Problem(xs, P0.ts, P0.xm, P0.tm, P0.rule_n, P0.kappa, P0.dhat, P0.delta_T, xs_rest=P0.xs)
+    rest = 1e-4
+    assert abs(oracle.weights(P).sum() / rest - 1) < 1e-12
+    nr = oracle.narrow(P)
+    assert np.all(nr.M >= 0)
+    A = oracle.assemble(P, nr.M, hessian=False)
+    assert abs(A.energy / (P.kappa * oracle.barrier(g0, P.dhat) * rest) - 1) < 1e-12
+    MA = mortar.assemble(P, mortar.samples(P))
+    assert abs(sum(s.w for s in MA.active) / rest - 1) < 1e-12
+    assert abs(MA.energy / (P.kappa * oracle.barrier(g0, P.dhat) * rest) - 1) < 1e-12
+
+
 def test_zero_beyond_dhat_bitwise():
     w, P = _punch(1.5e-3)
     nr = oracle.narrow(P)
