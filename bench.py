@@ -39,11 +39,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMCP samples/s (E+grad+Hess) & CCD pairs/s, % HBM peak; Newton iters learned vs plain"
 HBM_PEAK_GBS = 8000.0
-# kernels that one profiled stage brackets exactly (candidates for the roofline)
+# kernels that one profiled stage brackets exactly (candidates for the
+# roofline); the additive CCD stage also holds its tile prepass, so it is
+# not one of them
 KERNEL_STAGES = {"query": "k_query_f32", "cand_move": "k_cand_move", "narrow": "k_narrow_f32",
                  "rows_count": "k_rows<float, 0, false>", "rows_fill": "k_rows<float, 1, false>",
                  "rows_count_heavy": "k_rows<float, 0, true>", "rows_fill_heavy": "k_rows<float, 1, true>",
-                 "ccd_linear": "k_ccd_linear<float>", "ccd_accd": "k_ccd_accd<float>"}
+                 "ccd_linear": "k_ccd_linear<float>"}
 
 
 # sources of the step's kernels and launches (the traffic counters of a
