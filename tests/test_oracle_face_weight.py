@@ -192,7 +192,7 @@ def test_nearest_of_two_stacked_sheets():
 
 def test_adaptive_support_radius_boundary():
     g0 = 3e-4
-    w, P = None, workloads.to_problem(workloads.flat_punch(gap=g0))
+    P = workloads.to_problem(workloads.flat_punch(gap=g0))
     nr = oracle.narrow(P)
     assert np.all(nr.M >= 0) and np.allclose(nr.g, g0, rtol=1e-12)
     rng = np.random.default_rng(4)
